@@ -1,0 +1,175 @@
+"""Whole-grid second implementation of the step, no subdomains (test
+infrastructure only).
+
+Written directly from the scheme (Sec. 2.2.1 eq. VF_scheme, the
+Lax-Friedrichs flux of Sec. 2.2.1, the Euler system of Sec. 5, the spray
+system of Sec. 6.1) with numpy array shifts instead of the subdomain tasks.
+It evaluates the same operations in the same order as the C oracle, so for
+advection and Euler the two must agree bit for bit at any partition; this is
+what pins the task decomposition (overlap copies, interior/border split) to
+the unpartitioned scheme. A torch version of the same formula gives the exact
+discrete adjoint through torch.autograd for small grids.
+"""
+from __future__ import annotations
+
+import math
+
+import numpy as np
+
+ADV, EULER, SPRAY = 0, 1, 2
+PERIODIC, TRANSMISSIVE = 0, 1
+TINY = 1e-300
+
+
+def _neighbours(W, axis, bc):
+    """(left, right) neighbour arrays along a spatial axis (2 = x, 1 = y)."""
+    if bc == PERIODIC:
+        return np.roll(W, 1, axis=axis), np.roll(W, -1, axis=axis)
+    n = W.shape[axis]
+    idx_l = np.clip(np.arange(n) - 1, 0, n - 1)
+    idx_r = np.clip(np.arange(n) + 1, 0, n - 1)
+    return np.take(W, idx_l, axis=axis), np.take(W, idx_r, axis=axis)
+
+
+def phys_flux(model, W, d, gamma=1.4, a=(0.0, 0.0)):
+    if model == ADV:
+        return a[d] * W, np.full(W.shape[1:], abs(a[d]))
+    if model == EULER:
+        r, ru, rv, e = W
+        u = ru / r
+        v = rv / r
+        ke = 0.5 * (ru * u + rv * v)
+        p = (gamma - 1.0) * (e - ke)
+        c = np.sqrt(gamma * p / r)
+        un = u if d == 0 else v
+        f1 = ru * un
+        f2 = rv * un
+        if d == 0:
+            f1 = f1 + p
+        else:
+            f2 = f2 + p
+        F = np.stack([r * un, f1, f2, (e + p) * un])
+        return F, np.abs(un) + c
+    m2 = W[2]
+    un = np.where(m2 > TINY, W[4 + d] / np.where(m2 > TINY, m2, 1.0), 0.0)
+    return W * un, np.abs(un)
+
+
+def num_flux(model, WL, WR, d, gamma=1.4, a=(0.0, 0.0)):
+    if model == ADV:
+        ap = a[d] if a[d] > 0.0 else 0.0
+        am = a[d] if a[d] < 0.0 else 0.0
+        return ap * WL + am * WR
+    if model == EULER:
+        FL, sl = phys_flux(model, WL, d, gamma)
+        FR, sr = phys_flux(model, WR, d, gamma)
+        sigma = np.where(sl >= sr, sl, sr)
+        return 0.5 * (FL + FR) - 0.5 * sigma * (WR - WL)
+    m2l, m2r = WL[2], WR[2]
+    ul = np.where(m2l > TINY, WL[4 + d] / np.where(m2l > TINY, m2l, 1.0), 0.0)
+    ur = np.where(m2r > TINY, WR[4 + d] / np.where(m2r > TINY, m2r, 1.0), 0.0)
+    up = np.where(ul > 0.0, ul, 0.0)
+    um = np.where(ur < 0.0, ur, 0.0)
+    return WL * up + WR * um
+
+
+def spray_source(W, ug, K, theta, s_eps):
+    m0, m1, m2 = W[0], W[1], W[2]
+    ok = (m0 > TINY) & (m1 > TINY) & (m2 > TINY)
+    safe = lambda x: np.where(ok, x, 1.0)
+    m0s, m1s, m2s = safe(m0), safe(m1), safe(m2)
+    ux = W[4] / m2s
+    uy = W[5] / m2s
+    L1 = np.log(m1s / m0s)
+    L2 = np.log(m2s / m0s)
+    s2 = 4.0 * (L2 - 2.0 * L1)
+    s2 = np.where(s2 < 1e-8, 1e-8, s2)
+    mu = 2.0 * L1 - s2 / 4.0
+    mmh = m0s * np.exp(-mu / 2.0 + s2 / 8.0)
+    z = math.log(s_eps) - mu
+    n0 = m0s / (s_eps * np.sqrt(2.0 * math.pi * s2)) * np.exp(-(z * z) / (2.0 * s2))
+    S = np.stack([-K * n0, -(K / 2.0) * mmh, -K * m0s, -(1.5 * K) * m1s,
+                  -K * m0s * ux + m0s * (ug[0] - ux) / theta,
+                  -K * m0s * uy + m0s * (ug[1] - uy) / theta])
+    return np.where(ok[None], S, 0.0)
+
+
+def step(model, W, dt, *, bc=PERIODIC, lx=1.0, ly=1.0, gamma=1.4,
+         a=(0.0, 0.0), ug=None, K=1.0, theta=0.1, s_eps=0.01):
+    """One step W^n -> W^{n+1} with the given dt on the whole grid."""
+    W = np.asarray(W, dtype=np.float64)
+    nx, ny = W.shape[2], W.shape[1]
+    mux = dt / (lx / nx)
+    muy = dt / (ly / ny)
+    Wl, Wr = _neighbours(W, 2, bc)
+    Ws, Wn = _neighbours(W, 1, bc)
+    FE = num_flux(model, W, Wr, 0, gamma, a)
+    FW = num_flux(model, Wl, W, 0, gamma, a)
+    GN = num_flux(model, W, Wn, 1, gamma, a)
+    GS = num_flux(model, Ws, W, 1, gamma, a)
+    t = mux * (FE - FW) + muy * (GN - GS)
+    Wstar = W + (-t)
+    if model == SPRAY:
+        Wstar = Wstar + dt * spray_source(Wstar, ug, K, theta, s_eps)
+    return Wstar
+
+
+def speeds(model, W, gamma=1.4, a=(0.0, 0.0)):
+    _, sx = phys_flux(model, W, 0, gamma, a)
+    _, sy = phys_flux(model, W, 1, gamma, a)
+    return float(np.max(sx)), float(np.max(sy))
+
+
+def cfl_dt(model, W, cfl, *, lx=1.0, ly=1.0, gamma=1.4, a=(0.0, 0.0)):
+    nx, ny = W.shape[2], W.shape[1]
+    sx, sy = speeds(model, W, gamma, a)
+    return cfl / (sx / (lx / nx) + sy / (ly / ny))
+
+
+# --------------------------------------------------------------------------
+# torch version (fp64, CPU) for the exact discrete adjoint via autograd
+# --------------------------------------------------------------------------
+
+def torch_step(model, W, dt, *, bc=PERIODIC, lx=1.0, ly=1.0, gamma=1.4,
+               a=(0.0, 0.0)):
+    """Differentiable whole-grid transport step (advection or Euler)."""
+    import torch
+
+    def nb(X, axis):
+        if bc == PERIODIC:
+            return torch.roll(X, 1, dims=axis), torch.roll(X, -1, dims=axis)
+        n = X.shape[axis]
+        il = torch.clamp(torch.arange(n) - 1, 0, n - 1)
+        ir = torch.clamp(torch.arange(n) + 1, 0, n - 1)
+        return torch.index_select(X, axis, il), torch.index_select(X, axis, ir)
+
+    def pflux(X, d):
+        if model == ADV:
+            return a[d] * X, None
+        r, ru, rv, e = X[0], X[1], X[2], X[3]
+        u = ru / r
+        v = rv / r
+        p = (gamma - 1.0) * (e - 0.5 * (ru * u + rv * v))
+        c = torch.sqrt(gamma * p / r)
+        un = u if d == 0 else v
+        f1 = ru * un + (p if d == 0 else 0.0)
+        f2 = rv * un + (p if d == 1 else 0.0)
+        return torch.stack([r * un, f1, f2, (e + p) * un]), torch.abs(un) + c
+
+    def nflux(XL, XR, d):
+        if model == ADV:
+            ap = a[d] if a[d] > 0.0 else 0.0
+            am = a[d] if a[d] < 0.0 else 0.0
+            return ap * XL + am * XR
+        FL, sl = pflux(XL, d)
+        FR, sr = pflux(XR, d)
+        sigma = torch.where(sl >= sr, sl, sr)
+        return 0.5 * (FL + FR) - 0.5 * sigma * (XR - XL)
+
+    nx, ny = W.shape[2], W.shape[1]
+    mux = dt / (lx / nx)
+    muy = dt / (ly / ny)
+    Wl, Wr = nb(W, 2)
+    Ws, Wn = nb(W, 1)
+    t = mux * (nflux(W, Wr, 0) - nflux(Wl, W, 0)) + muy * (nflux(W, Wn, 1) - nflux(Ws, W, 1))
+    return W - t

@@ -1,0 +1,517 @@
+"""Pins of the CPU oracle against what the paper and the mathematics fix.
+
+None of these tests touches the GPU. Each one ties the oracle to something
+other than itself: a closed form, a library routine (FFT, autograd, numerical
+quadrature, eigenvalues), a conservation law, an invariant, brute force on a
+tiny grid, or the convergence order the paper prints.
+"""
+import json
+import math
+import os
+
+import numpy as np
+import pytest
+
+from oracle import bruteforce as bf
+from paper_1701_05431_amd import inputs
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def _rel_linf(a, b):
+    a = np.asarray(a)
+    b = np.asarray(b)
+    out = []
+    for v in range(a.shape[0]):
+        den = max(float(np.max(np.abs(b[v]))), 1e-300)
+        out.append(float(np.max(np.abs(a[v] - b[v]))) / den)
+    return max(out)
+
+
+# --------------------------------------------------------------------------
+# advection: closed forms
+# --------------------------------------------------------------------------
+
+def test_advection_dt_reading(orc):
+    """64x64, a = (1, 0.5), C = 0.9: dt = C/(Sx/dx + Sy/dy) = 0.9/96."""
+    P = orc.from_preset(inputs.ADVECTION_64)
+    u0 = inputs.advection_state(64, 64, 0)
+    sx, sy, dt = orc.cfl(P, u0)
+    assert (sx, sy) == (1.0, 0.5)
+    assert dt == 0.9 / 96.0
+    assert abs(dt - 0.009375) < 1e-18
+
+
+@pytest.mark.parametrize("seed", [0, 1, 2])
+def test_advection_fft_closed_form(orc, seed):
+    """Upwind on a periodic grid is a circulant operator with symbol
+    g = 1 - nux (1 - e^{-i tx}) - nuy (1 - e^{-i ty}); 100 steps of the
+    64x64 workload equal IFFT(g^100 FFT(u0))."""
+    pre = inputs.ADVECTION_64
+    P = orc.from_preset(pre)
+    u0 = inputs.advection_state(64, 64, seed)
+    un, dts = orc.run(P, u0, pre.nsteps)
+    assert np.all(dts == dts[0])
+    nux = pre.ax * dts[0] * 64
+    nuy = pre.ay * dts[0] * 64
+    kx = np.fft.fftfreq(64)[None, :]
+    ky = np.fft.fftfreq(64)[:, None]
+    g = 1 - nux * (1 - np.exp(-2j * np.pi * kx)) - nuy * (1 - np.exp(-2j * np.pi * ky))
+    ref = np.real(np.fft.ifft2(g ** pre.nsteps * np.fft.fft2(u0[0])))
+    assert np.max(np.abs(un[0] - ref)) < 1e-13 * np.max(np.abs(u0))
+
+
+@pytest.mark.parametrize("a", [(1.0, 0.0), (-1.0, 0.0), (0.0, 1.0), (0.0, -1.0)])
+def test_advection_exact_translation_at_courant_one(orc, a):
+    """At Courant number 1 along an axis the upwind step is an exact shift."""
+    n = 32
+    P = orc.params(orc.ADV, n, n, ax=a[0], ay=a[1], cfl=1.0, npx=2, npy=4)
+    u = inputs.advection_state(n, n, 5)
+    u0 = u.copy()
+    shift_axis = 2 if a[0] != 0 else 1
+    shift = 1 if (a[0] > 0 or a[1] > 0) else -1
+    amax = np.max(np.abs(u0))
+    for _ in range(n):
+        un, dts = orc.run(P, u, 1)
+        assert dts[0] == 1.0 / n
+        assert np.max(np.abs(un - np.roll(u, shift, axis=shift_axis))) <= 2.3e-16 * amax
+        u = un
+    assert np.max(np.abs(u - u0)) <= n * 2.3e-16 * amax
+
+
+def test_advection_maximum_principle(orc):
+    pre = inputs.ADVECTION_64
+    P = orc.from_preset(pre)
+    u0 = inputs.advection_state(64, 64, 1)
+    u = u0.copy()
+    for _ in range(10):
+        u, _ = orc.run(P, u, 20)
+        assert u.min() >= u0.min() - 1e-15 and u.max() <= u0.max() + 1e-15
+
+
+def test_paper_one_dimensional_cfl_breaks_maximum_principle(orc):
+    """Documents the CFL reading: the 1-D form dt = C min(dx,dy)/max|a| at
+    C = 0.9 gives nux + nuy = 1.35 > 1 for a = (1, 0.5), and the unsplit upwind
+    step then leaves the initial range; the 2-D form does not."""
+    pre = inputs.ADVECTION_64
+    P = orc.from_preset(pre)
+    u0 = inputs.advection_state(64, 64, 1)
+    dt_1d = 0.9 * (1.0 / 64) / 1.0
+    u = orc.run_dts(P, u0, [dt_1d] * 100)
+    assert u.max() > u0.max() + 1e-3 or u.min() < u0.min() - 1e-3
+
+
+def test_advection_matrix_power_8x8(orc):
+    """Brute force on 8x8: the step operator assembled column by column from
+    unit inputs, raised to the 7th power, equals 7 oracle steps; the adjoint
+    step equals the transposed operator."""
+    n = 8
+    P = orc.params(orc.ADV, n, n, ax=0.7, ay=-0.4, cfl=0.8, npx=2, npy=2)
+    dt = 0.8 / (0.7 * n + 0.4 * n)
+    A = np.zeros((n * n, n * n))
+    for k in range(n * n):
+        e = np.zeros((1, n, n))
+        e.reshape(-1)[k] = 1.0
+        A[:, k] = orc.run_dts(P, e, [dt]).reshape(-1)
+    # each column is one upwind stencil: 1 - nux - nuy, nux (west/east), nuy
+    nux, nuy = 0.7 * dt * n, 0.4 * dt * n
+    assert np.allclose(np.sort(A[:, 0][A[:, 0] != 0]), np.sort([1 - nux - nuy, nux, nuy]), atol=1e-15)
+    u0 = inputs.advection_state(n, n, 3)
+    ref = np.linalg.matrix_power(A, 7) @ u0.reshape(-1)
+    got = orc.run_dts(P, u0, [dt] * 7)
+    assert np.max(np.abs(got.reshape(-1) - ref)) < 1e-14
+    lam = np.random.default_rng(0).standard_normal((1, n, n))
+    adj = orc.adjoint_step(P, u0, dt, lam)
+    assert np.max(np.abs(adj.reshape(-1) - A.T @ lam.reshape(-1))) < 1e-14
+
+
+# --------------------------------------------------------------------------
+# brute force: subdomain tasks == whole-grid formula, bit for bit
+# --------------------------------------------------------------------------
+
+PARTS = [(1, 1), (2, 2), (1, 4), (4, 1), (2, 8), (8, 8)]
+
+
+@pytest.mark.parametrize("bc", [0, 1])
+@pytest.mark.parametrize("model", [0, 1])
+def test_partitions_equal_whole_grid_bitwise(orc, model, bc):
+    n = 8
+    if model == 0:
+        W = inputs.advection_state(n, n, 4)
+        kw = dict(ax=0.8, ay=-0.3)
+    else:
+        W = inputs.riemann_state(n, n, 4)
+        kw = {}
+    base = None
+    for npx, npy in PARTS:
+        P = orc.params(model, n, n, bc=bc, npx=npx, npy=npy, cfl=0.45, **kw)
+        got, dts = orc.run(P, W, 6)
+        ref = W.copy()
+        for dt in dts:
+            ref = bf.step(model, ref, dt, bc=bc, a=(kw.get("ax", 0.0), kw.get("ay", 0.0)))
+        assert np.array_equal(got, ref)
+        if base is None:
+            base = got
+        assert np.array_equal(got, base)
+
+
+def test_spray_partitions_bitwise_and_whole_grid(orc):
+    n = 64
+    W, ug = inputs.spray_state(n, n, 2)
+    base = None
+    for npx, npy in [(1, 1), (2, 4), (64, 16)]:
+        P = orc.params(orc.SPRAY, n, n, npx=npx, npy=npy, cfl=0.9)
+        got, dts = orc.run(P, W, 4, ug=ug)
+        if base is None:
+            base = got
+        assert np.array_equal(got, base)
+    ref = W.copy()
+    for dt in dts:
+        ref = bf.step(bf.SPRAY, ref, dt, ug=ug)
+    # numpy's exp/log may differ from libm by an ulp
+    assert _rel_linf(base, ref) < 1e-14
+
+
+# --------------------------------------------------------------------------
+# conservation, invariants, symmetry
+# --------------------------------------------------------------------------
+
+def _fsum_planes(W):
+    return np.array([math.fsum(W[v].reshape(-1)) for v in range(W.shape[0])])
+
+
+def test_euler_periodic_conservation(orc):
+    n = 32
+    P = orc.params(orc.EULER, n, n, npx=4, npy=2, cfl=0.45)
+    W0 = inputs.riemann_state(n, n, 7)
+    s0 = _fsum_planes(W0)
+    W, _ = orc.run(P, W0, 200)
+    s1 = _fsum_planes(W)
+    assert np.all(np.abs(s1 - s0) <= 1e-13 * np.abs(s0) + 1e-13 * n * n * np.max(np.abs(W0), axis=(1, 2)))
+
+
+def test_spray_transport_conservation(orc):
+    n = 32
+    P = orc.params(orc.SPRAY, n, n, npx=2, npy=2, cfl=0.9, K=0.0, theta=math.inf)
+    W0, ug = inputs.spray_state(n, n, 3)
+    s0 = _fsum_planes(W0)
+    W, _ = orc.run(P, W0, 100, ug=ug)
+    s1 = _fsum_planes(W)
+    assert np.all(np.abs(s1 - s0) <= 1e-12 * np.abs(s0) + 1e-15)
+
+
+@pytest.mark.parametrize("bc", [0, 1])
+def test_uniform_state_is_fixed_point(orc, bc):
+    n = 8
+    w = inputs.conservative_from_primitive(0.7, 0.3, -0.2, 0.6)
+    W = np.broadcast_to(w[:, None, None], (4, n, n)).copy()
+    P = orc.params(orc.EULER, n, n, bc=bc, npx=2, npy=4)
+    got, _ = orc.run(P, W, 5)
+    assert np.array_equal(got, W)
+
+
+def test_transposition_symmetry_bitwise(orc):
+    n = 16
+    W = inputs.riemann_state(n, n, 11)
+    Wt = np.stack([W[0].T, W[2].T, W[1].T, W[3].T]).copy()
+    for bc in (0, 1):
+        P = orc.params(orc.EULER, n, n, bc=bc, npx=2, npy=4)
+        Pt = orc.params(orc.EULER, n, n, bc=bc, npx=4, npy=2)
+        a, da = orc.run(P, W, 4)
+        b, db = orc.run(Pt, Wt, 4)
+        assert np.array_equal(da, db)
+        assert np.array_equal(np.stack([b[0].T, b[2].T, b[1].T, b[3].T]), a)
+
+
+def test_x_only_data_keeps_rows_identical(orc):
+    n = 16
+    row = inputs.riemann_state(n, 2, 5)[:, :1, :]
+    W = np.broadcast_to(row, (4, n, n)).copy()
+    for bc in (0, 1):
+        P = orc.params(orc.EULER, n, n, bc=bc, npx=4, npy=4)
+        got, _ = orc.run(P, W, 10)
+        assert np.array_equal(got, np.broadcast_to(got[:, :1, :], got.shape))
+
+
+def test_localized_cosine_keeps_velocity_and_pressure(orc):
+    """Constant u, v, p with variable rho: every flux component is affine in
+    rho with the same coefficients, so u, v, p stay uniform."""
+    n = 32
+    prim = inputs.localized_cosine_primitives(n, n)
+    W = inputs.conservative_from_primitive(*prim)
+    P = orc.params(orc.EULER, n, n, npx=2, npy=2)
+    got, _ = orc.run(P, W, 30)
+    r = got[0]
+    u = got[1] / r
+    v = got[2] / r
+    p = 0.4 * (got[3] - 0.5 * r * (u * u + v * v))
+    assert np.max(np.abs(u - 1)) < 1e-13 and np.max(np.abs(v - 1)) < 1e-13
+    assert np.max(np.abs(p - 1 / 1.4)) < 1e-13
+    assert np.max(np.abs(r - prim[0])) > 1e-3
+
+
+def test_transmissive_boundary_balance(orc):
+    """With zero-gradient ghosts the boundary face flux is F(W_b) exactly, so
+    the change of the cell sums is the net boundary flux."""
+    n = 24
+    W = inputs.riemann_state(n, n, 13)
+    P = orc.params(orc.EULER, n, n, bc=orc.TRANSMISSIVE, npx=3, npy=2)
+    W1, dts = orc.run(P, W, 1)
+    mux = muy = dts[0] * n
+    bal = np.zeros(4)
+    for j in range(n):
+        bal -= mux * (orc.phys_flux(P, W[:, j, n - 1], 0)[0] - orc.phys_flux(P, W[:, j, 0], 0)[0])
+    for i in range(n):
+        bal -= muy * (orc.phys_flux(P, W[:, n - 1, i], 1)[0] - orc.phys_flux(P, W[:, 0, i], 1)[0])
+    d = _fsum_planes(W1) - _fsum_planes(W)
+    assert np.all(np.abs(d - bal) < 1e-12 * (1 + np.abs(_fsum_planes(W))))
+
+
+# --------------------------------------------------------------------------
+# Euler flux against textbook closed forms
+# --------------------------------------------------------------------------
+
+@pytest.mark.parametrize("mach", [1.5, 3.0])
+@pytest.mark.parametrize("d", [0, 1])
+def test_euler_flux_rankine_hugoniot(orc, mach, d):
+    """Normal-shock relations give states with equal physical flux."""
+    g = 1.4
+    rho1, p1 = 1.0, 1.0
+    c1 = math.sqrt(g * p1 / rho1)
+    u1 = mach * c1
+    rho2 = rho1 * (g + 1) * mach ** 2 / ((g - 1) * mach ** 2 + 2)
+    p2 = p1 * (1 + 2 * g / (g + 1) * (mach ** 2 - 1))
+    u2 = u1 * rho1 / rho2
+    vt = 0.3  # tangential velocity, continuous across the shock
+    def state(rho, un, p):
+        u, v = (un, vt) if d == 0 else (vt, un)
+        return inputs.conservative_from_primitive(rho, u, v, p)
+    P = orc.params(orc.EULER, 4, 4)
+    f1, _ = orc.phys_flux(P, state(rho1, u1, p1), d)
+    f2, _ = orc.phys_flux(P, state(rho2, u2, p2), d)
+    assert np.max(np.abs(f1 - f2)) < 1e-13 * np.max(np.abs(f1))
+
+
+@pytest.mark.parametrize("d", [0, 1])
+def test_euler_flux_jacobian_eigenvalues(orc, d):
+    """The eigenvalues of dF.n/dW are u.n - c, u.n, u.n, u.n + c with
+    c^2 = gamma p / rho (Sec. 5); the reported speed is |u.n| + c."""
+    P = orc.params(orc.EULER, 4, 4)
+    rho, u, v, p = 0.8, 0.35, -0.6, 0.45
+    w = inputs.conservative_from_primitive(rho, u, v, p)
+    J = np.zeros((4, 4))
+    for l in range(4):
+        h = 1e-6 * max(1.0, abs(w[l]))
+        e = np.zeros(4)
+        e[l] = h
+        J[:, l] = (orc.phys_flux(P, w + e, d)[0] - orc.phys_flux(P, w - e, d)[0]) / (2 * h)
+    ev = np.sort(np.linalg.eigvals(J).real)
+    c = math.sqrt(1.4 * p / rho)
+    un = u if d == 0 else v
+    assert np.allclose(ev, np.sort([un - c, un, un, un + c]), atol=1e-8)
+    assert abs(orc.phys_flux(P, w, d)[1] - (abs(un) + c)) < 1e-15
+
+
+def test_lax_friedrichs_consistency(orc):
+    P = orc.params(orc.EULER, 4, 4)
+    w = inputs.conservative_from_primitive(0.5, -0.2, 0.1, 0.9)
+    for d in (0, 1):
+        assert np.array_equal(orc.num_flux(P, w, w, d), orc.phys_flux(P, w, d)[0])
+
+
+# --------------------------------------------------------------------------
+# the paper's printed convergence order
+# --------------------------------------------------------------------------
+
+def _error_at(orc, case, n, T=0.2, C=0.4):
+    fn = {"cosine": inputs.localized_cosine_primitives,
+          "vortex": inputs.isentropic_vortex_primitives}[case]
+    W0 = inputs.conservative_from_primitive(*fn(n, n, 0.0))
+    P = orc.params(orc.EULER, n, n, npx=2, npy=2, cfl=C)
+    _, _, dt = orc.cfl(P, W0)
+    steps = int(math.ceil(T / dt))
+    W = orc.run_dts(P, W0, [T / steps] * steps)
+    rho_ex = fn(n, n, T)[0]
+    e = W[0] - rho_ex
+    return np.mean(np.abs(e)), math.sqrt(np.mean(e * e))
+
+
+@pytest.mark.parametrize("case", ["cosine", "vortex"])
+def test_first_order_convergence(orc, case):
+    """Mesh convergence on the two analytic Euler cases: the paper reports
+    L1 and L2 slopes of about 0.95."""
+    paper = json.load(open(os.path.join(GOLDEN, "paper_numbers.json")))
+    slope_paper = paper["convergence_slope"]["value"]
+    errs = [_error_at(orc, case, n) for n in (64, 128, 256)]
+    for k in range(2):
+        s = math.log2(errs[-2][k] / errs[-1][k])
+        assert abs(s - slope_paper) < 0.15, (case, k, s, errs)
+
+
+# --------------------------------------------------------------------------
+# spray source and closure
+# --------------------------------------------------------------------------
+
+def test_spray_uniform_velocity_transport_is_upwind(orc):
+    """With K = 0, no drag and a uniform velocity the kinetic flux is upwind
+    advection of every component: compare with the FFT closed form."""
+    n = 32
+    ux, uy = 0.6, 0.25
+    m0 = 1.0 + 0.5 * inputs.gaussian_bumps(n, n, 1)
+    m1 = 0.5 + 0.2 * inputs.gaussian_bumps(n, n, 2)
+    m2 = 0.3 + 0.1 * inputs.gaussian_bumps(n, n, 3)
+    m3 = 0.2 + 0.1 * inputs.gaussian_bumps(n, n, 4)
+    W0 = np.stack([m0, m1, m2, m3, m2 * ux, m2 * uy])
+    ug = np.zeros((2, n, n))
+    P = orc.params(orc.SPRAY, n, n, cfl=0.9, K=0.0, theta=math.inf, npx=2, npy=2)
+    W, dts = orc.run(P, W0, 40, ug=ug)
+    nux, nuy = ux * dts[0] * n, uy * dts[0] * n
+    kx = np.fft.fftfreq(n)[None, :]
+    ky = np.fft.fftfreq(n)[:, None]
+    g = 1 - nux * (1 - np.exp(-2j * np.pi * kx)) - nuy * (1 - np.exp(-2j * np.pi * ky))
+    for v in range(4):
+        ref = np.real(np.fft.ifft2(g ** 40 * np.fft.fft2(W0[v])))
+        assert np.max(np.abs(W[v] - ref)) < 1e-13
+    assert np.max(np.abs(W[4] / W[2] - ux)) < 1e-13
+
+
+def test_spray_closure_matches_quadrature(orc):
+    """For exact lognormal moments the fitted m_{-1/2} equals the integral of
+    S^{-1/2} n(S) and n0 equals the density at S_eps."""
+    from scipy import integrate
+    P = orc.params(orc.SPRAY, 4, 4, s_eps=0.01)
+    N0, mu, s = 1.3, math.log(0.1) + 0.2, 0.35
+    dens = lambda S: N0 / (S * s * math.sqrt(2 * math.pi)) * math.exp(-(math.log(S) - mu) ** 2 / (2 * s * s))
+    def mom(k):
+        f = lambda S: S ** (k / 2) * dens(S)
+        mid = math.exp(mu)
+        a = integrate.quad(f, 0, mid, limit=400, epsabs=0, epsrel=1e-13)[0]
+        b = integrate.quad(f, mid, np.inf, limit=400, epsabs=0, epsrel=1e-13)[0]
+        return a + b
+    m = [mom(k) for k in range(4)]
+    w = np.array(m + [0.0, 0.0])
+    mmh, n0 = orc.spray_closure(P, w)
+    assert abs(mmh - mom(-1)) < 1e-10 * mom(-1)
+    assert abs(n0 - dens(0.01)) < 1e-9 * max(dens(0.01), 1e-300) + 1e-300
+
+
+def test_spray_uniform_state_one_step_closed_form(orc):
+    """A uniform state has zero transport, so one step is W + dt S(W) with S
+    from the known lognormal parameters (Sec. 6.1 eq. Essadki)."""
+    n = 8
+    K, theta, seps = 1.0, 0.1, 0.01
+    N0, mu, s = 0.9, math.log(0.1) - 0.1, 0.3
+    m = [N0 * math.exp(k * mu / 2 + k * k * s * s / 8) for k in range(4)]
+    ux, uy, ugx, ugy = 0.2, -0.1, 0.5, 0.3
+    w = np.array(m + [m[2] * ux, m[2] * uy])
+    W = np.broadcast_to(w[:, None, None], (6, n, n)).copy()
+    ug = np.stack([np.full((n, n), ugx), np.full((n, n), ugy)])
+    P = orc.params(orc.SPRAY, n, n, K=K, theta=theta, s_eps=seps, cfl=0.9)
+    W1, dts = orc.run(P, W, 1, ug=ug)
+    dt = dts[0]
+    mmh = N0 * math.exp(-mu / 2 + s * s / 8)
+    n0 = N0 / (seps * s * math.sqrt(2 * math.pi)) * math.exp(-(math.log(seps) - mu) ** 2 / (2 * s * s))
+    S = np.array([-K * n0, -K / 2 * mmh, -K * m[0], -1.5 * K * m[1],
+                  -K * m[0] * ux + m[0] * (ugx - ux) / theta,
+                  -K * m[0] * uy + m[0] * (ugy - uy) / theta])
+    ref = w + dt * S
+    for v in range(6):
+        assert np.max(np.abs(W1[v] - ref[v])) < 1e-12 * max(abs(ref[v]), 1e-3)
+
+
+def test_spray_drag_only(orc):
+    n = 4
+    w = np.array([0.8, 0.5, 0.3, 0.2, 0.3 * 0.4, -0.3 * 0.2])
+    W = np.broadcast_to(w[:, None, None], (6, n, n)).copy()
+    ug = np.stack([np.full((n, n), -0.1), np.full((n, n), 0.7)])
+    P = orc.params(orc.SPRAY, n, n, K=0.0, theta=0.05)
+    W1, dts = orc.run(P, W, 1, ug=ug)
+    dt = dts[0]
+    q = w[4:] + dt * w[0] * (np.array([-0.1, 0.7]) - w[4:] / w[2]) / 0.05
+    assert np.allclose(W1[4:, 0, 0], q, rtol=1e-14, atol=1e-16)
+    assert np.array_equal(W1[:4], W[:4])
+
+
+# --------------------------------------------------------------------------
+# fixed-dt check and error paths
+# --------------------------------------------------------------------------
+
+def test_fixed_dt_check(orc):
+    n = 16
+    W = inputs.riemann_state(n, n, 1)
+    P = orc.params(orc.EULER, n, n, bc=orc.TRANSMISSIVE, npx=2, npy=2)
+    sx, sy, _ = orc.cfl(P, W)
+    dt_lim = (1.0 / n) / max(sx, sy)
+    rc, got = orc.step_fixed(P, W, dt_lim * 1.01)
+    assert rc == orc.ECFL and np.array_equal(got, W)
+    rc, got = orc.step_fixed(P, W, dt_lim * 0.99)
+    assert rc == orc.OK
+    assert np.array_equal(got, orc.run_dts(P, W, [dt_lim * 0.99]))
+
+
+@pytest.mark.parametrize("what", ["nan", "rho", "p"])
+def test_nonfinite_and_nonphysical_states(orc, what):
+    n = 8
+    W = inputs.riemann_state(n, n, 1)
+    if what == "nan":
+        W[2, 3, 4] = np.nan
+    elif what == "rho":
+        W[0, 3, 4] = -0.1
+    else:
+        W[3, 3, 4] = 0.0  # zero energy with nonzero velocity: p < 0
+    P = orc.params(orc.EULER, n, n)
+    rc, _, _ = orc.run(P, W, 1, return_status=True)
+    assert rc == orc.ENONFINITE
+
+
+def test_validation(orc):
+    assert orc.validate(orc.params(orc.EULER, 10, 10, npx=3)) == orc.EINVAL
+    assert orc.validate(orc.params(7, 10, 10)) == orc.EINVAL
+    assert orc.validate(orc.params(orc.EULER, 0, 10)) == orc.EINVAL
+    assert orc.validate(orc.params(orc.EULER, 12, 10, npx=3, npy=5)) == orc.OK
+
+
+# --------------------------------------------------------------------------
+# adjoint
+# --------------------------------------------------------------------------
+
+@pytest.mark.parametrize("bc", [0, 1])
+def test_euler_adjoint_matches_autograd(orc, bc):
+    """The oracle's hand-written adjoint equals torch.autograd applied to the
+    whole-grid step (fp64), over three steps with frozen dts."""
+    import torch
+    nx, ny = 12, 10
+    W0 = inputs.riemann_state(nx, ny, 21)
+    W0 = W0 + 0.01 * np.stack([inputs.gaussian_bumps(nx, ny, 30 + v) for v in range(4)])
+    P = orc.params(orc.EULER, nx, ny, bc=bc, npx=2, npy=2)
+    _, dts = orc.run(P, W0, 3)
+    lam = np.random.default_rng(1).standard_normal(W0.shape)
+    g = orc.adjoint_run(P, W0, dts, lam)
+    X = torch.tensor(W0, requires_grad=True)
+    Y = X
+    for dt in dts:
+        Y = bf.torch_step(bf.EULER, Y, float(dt), bc=bc)
+    assert np.max(np.abs(Y.detach().numpy() - orc.run_dts(P, W0, dts))) < 1e-14
+    (Y * torch.tensor(lam)).sum().backward()
+    assert _rel_linf(g, X.grad.numpy()) < 1e-12
+
+
+def test_euler_adjoint_central_differences(orc):
+    n = 8
+    W0 = inputs.riemann_state(n, n, 2)
+    P = orc.params(orc.EULER, n, n, bc=orc.TRANSMISSIVE)
+    _, dts = orc.run(P, W0, 10)
+    tgt = inputs.adjoint_target_density(n, n, 2)
+    def loss(W):
+        WN = orc.run_dts(P, W, dts)
+        return 0.5 * np.sum((WN[0] - tgt) ** 2)
+    WN = orc.run_dts(P, W0, dts)
+    lamN = np.zeros_like(W0)
+    lamN[0] = WN[0] - tgt
+    g = orc.adjoint_run(P, W0, dts, lamN)
+    rng = np.random.default_rng(3)
+    for _ in range(8):
+        v = rng.standard_normal(W0.shape)
+        eps = 1e-6
+        fd = (loss(W0 + eps * v) - loss(W0 - eps * v)) / (2 * eps)
+        assert abs(np.sum(g * v) - fd) <= 1e-6 * max(1.0, abs(fd))
