@@ -1,0 +1,301 @@
+"""Benchmark of the fused finite-volume step on one MI355X.
+
+    python bench.py [--steps K] [--warmup W] [--gpus 1]
+
+Prints ONE JSON line. The headline workload is the 4096x4096 Euler grid
+(nVar = 4, Rusanov flux, transmissive boundaries, CFL 0.45, 8x8 subdomains,
+seeded four-quadrant Riemann data): `value` is cell-updates per second over K
+adaptive steps (each step = fluxes + update + CFL reduction of every cell),
+inputs already resident in HBM. The line also carries:
+  roofline     -- the fused step kernel against the 8 TB/s HBM peak, with
+                  64 algorithmic bytes per cell-update (read 4 doubles, write
+                  4 doubles) and the launch duration timed with HIP events on
+                  the launch stream;
+  cpu_baseline -- the CPU oracle on the host cores on a bounded sample;
+  workloads    -- the other workloads: spray 2048^2, 256 batched grids
+                  (persistent launch vs one launch per grid), the adjoint at
+                  1024^2 (backward / forward cost) and advection 64^2.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+METRIC = ("Gcell-updates/s and % HBM roofline (FP64); batched vs per-grid; "
+          "adjoint/forward cost")
+KERNEL_SOURCES = ["fvm_kernels.hip", "fvm_step.hpp", "fvm_models.hpp", "fvm_internal.hpp"]
+COUNTERS = os.path.join(ROOT, "profiles", "euler_4096_step_counters.json")
+
+
+def kernel_hash() -> str:
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, "paper_1701_05431_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def log(msg: str) -> None:
+    print(msg, file=sys.stderr, flush=True)
+
+
+def timed(fn, reps: int = 1):
+    """Runs fn() reps times between two HIP events on the current stream;
+    returns seconds per repetition."""
+    import torch
+    s = torch.cuda.Event(enable_timing=True)
+    e = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    s.record()
+    for _ in range(reps):
+        fn()
+    e.record()
+    torch.cuda.synchronize()
+    return s.elapsed_time(e) / 1e3 / reps
+
+
+def bench_euler(args):
+    import torch
+    from paper_1701_05431_amd import inputs
+    from paper_1701_05431_amd.solver import Solver, params_from
+    pre = inputs.EULER_4096
+    p = params_from(pre)
+    s = Solver(p)
+    if args.rows or args.wpb:
+        s.set_tiling(args.rows, args.wpb)
+    W = inputs.riemann_state(pre.nx, pre.ny, 0)
+    s.set_state(torch.from_numpy(W))
+    log(f"euler {pre.nx}x{pre.ny}: warmup {args.warmup}")
+    s.run(args.warmup)
+    torch.cuda.synchronize()
+    log(f"euler: timing {args.steps} steps")
+    sec = timed(lambda: s.run(args.steps))
+    assert s.sync() == 0
+    cells = pre.nx * pre.ny
+    per_launch = sec / args.steps
+    achieved = 64.0 * cells / per_launch / 1e9
+    return dict(sec=sec, cells=cells, per_launch=per_launch, achieved=achieved,
+                tiling=s.tiling(), solver=s)
+
+
+def bench_spray(steps, warmup):
+    import torch
+    from paper_1701_05431_amd import inputs
+    from paper_1701_05431_amd.solver import Solver, params_from
+    pre = inputs.SPRAY_2048
+    W, ug = inputs.spray_state(pre.nx, pre.ny, 0)
+    s = Solver(params_from(pre), ug=ug)
+    s.set_state(torch.from_numpy(W))
+    s.run(warmup)
+    sec = timed(lambda: s.run(steps))
+    st = s.sync()
+    per = sec / steps
+    cells = pre.nx * pre.ny
+    gbs = 112.0 * cells / per / 1e9
+    return {"workload": pre.name, "steps": steps, "status": st,
+            "gcell_updates_per_s": cells * steps / sec / 1e9, "ms_per_step": per * 1e3,
+            "bytes_per_cell": 112, "hbm_gbs": gbs, "hbm_frac": gbs / HBM_PEAK_GBS}
+
+
+def bench_batch(steps, warmup):
+    import torch
+    from paper_1701_05431_amd import inputs
+    from paper_1701_05431_amd.solver import Batch, params_from
+    sizes = inputs.batch_sizes(inputs.BATCH_COUNT, 0)
+    plist = [params_from(inputs.BATCH_256, nx=n, ny=n) for n in sizes]
+    states = [inputs.riemann_state(n, n, k) for k, n in enumerate(sizes)]
+    cells = sum(n * n for n in sizes)
+    out = {"workload": inputs.BATCH_256.name, "grids": len(sizes), "cells": cells,
+           "steps": steps}
+    for name, per_grid in (("persistent", False), ("per_grid", True)):
+        b = Batch(plist)
+        b.set_states(states)
+        b.run(warmup, per_grid=per_grid)
+        sec = timed(lambda: b.run(steps, per_grid=per_grid))
+        st = b.sync()
+        gbs = 64.0 * cells * steps / sec / 1e9
+        out[name] = {"gcell_updates_per_s": cells * steps / sec / 1e9,
+                     "ms_per_step": sec / steps * 1e3, "hbm_frac": gbs / HBM_PEAK_GBS,
+                     "status": st}
+        del b
+    out["batched_vs_per_grid"] = (out["persistent"]["gcell_updates_per_s"] /
+                                  out["per_grid"]["gcell_updates_per_s"])
+    return out
+
+
+def bench_adjoint(reps):
+    import torch
+    from paper_1701_05431_amd import inputs
+    from paper_1701_05431_amd.solver import Solver, params_from
+    pre = inputs.ADJOINT_1024
+    every = inputs.ADJOINT_CKPT_EVERY
+    W = inputs.riemann_state(pre.nx, pre.ny, 0)
+    tgt = torch.from_numpy(inputs.adjoint_target_density(pre.nx, pre.ny, 0)).cuda()
+    s = Solver(params_from(pre))
+    Wt = torch.from_numpy(W).cuda()
+    holder = {}
+
+    def fwd():
+        s.set_state(Wt)
+        holder["ck"], holder["dts"] = s.run_ckpt(pre.nsteps, every)
+
+    def bwd():
+        cur = s.current()[:, :, :pre.nx]
+        lam = torch.zeros_like(s.current())
+        lam[0, :, :pre.nx] = cur[0] - tgt
+        holder["g"] = s.adjoint(holder["ck"], every, holder["dts"], lam)
+
+    fwd()
+    bwd()
+    tf = min(timed(fwd) for _ in range(reps))
+    fwd()
+    tb = min(timed(bwd) for _ in range(reps))
+    cells = pre.nx * pre.ny
+    return {"workload": pre.name, "steps": pre.nsteps, "ckpt_every": every,
+            "forward_ms": tf * 1e3, "backward_ms": tb * 1e3,
+            "adjoint_over_forward": tb / tf,
+            "forward_gcell_updates_per_s": cells * pre.nsteps / tf / 1e9,
+            "status": s.sync()}
+
+
+def bench_advection(steps):
+    import torch
+    from paper_1701_05431_amd import inputs
+    from paper_1701_05431_amd.solver import Solver, params_from
+    pre = inputs.ADVECTION_64
+    s = Solver(params_from(pre))
+    s.set_state(torch.from_numpy(inputs.advection_state(64, 64, 0)))
+    s.run(pre.nsteps)
+    sec = timed(lambda: s.run(pre.nsteps), reps=5)
+    return {"workload": pre.name, "steps": pre.nsteps, "us_per_step": sec / pre.nsteps * 1e6,
+            "status": s.sync()}
+
+
+def cpu_baseline(target_s: float = 12.0):
+    """The oracle as it is, on the host cores, on a bounded sample of the
+    headline workload: a few steps of the 4096^2 Euler grid."""
+    from oracle import fv as orc
+    from paper_1701_05431_amd import inputs
+    pre = inputs.EULER_4096
+    try:
+        cores = len(os.sched_getaffinity(0))
+    except AttributeError:
+        cores = os.cpu_count() or 1
+    cores = min(cores, 16)
+    orc.set_threads(cores)
+    P = orc.from_preset(pre)
+    W = inputs.riemann_state(pre.nx, pre.ny, 0)
+    t0 = time.perf_counter()
+    W, _ = orc.run(P, W, 1)
+    t1 = time.perf_counter() - t0
+    k = max(1, min(20, int(target_s / max(t1, 1e-3))))
+    t0 = time.perf_counter()
+    orc.run(P, W, k)
+    t = time.perf_counter() - t0
+    return {"value": pre.nx * pre.ny * k / t / 1e9, "unit": "Gcell-updates/s",
+            "cores": orc.get_threads(), "kind": "oracle",
+            "sample": f"{pre.name}: {k} adaptive steps after 1 warm-up step, {t:.1f} s"}
+
+
+def traffic_from_counters(per_launch_bytes: float):
+    """HBM bytes per launch from the committed rocprofv3 counter summary,
+    only if it was taken on the current kernel source."""
+    if not os.path.exists(COUNTERS):
+        return None
+    with open(COUNTERS) as fh:
+        c = json.load(fh)
+    if c.get("kernel_hash") != kernel_hash():
+        return None
+    return c.get("bytes_per_launch")
+
+
+def copy_probe(nbytes: int, reps: int):
+    import torch
+    src = torch.ones(nbytes // 8, dtype=torch.float64, device="cuda")
+    dst = torch.empty_like(src)
+    for _ in range(reps):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_probe_bytes": nbytes, "reps": reps}), flush=True)
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--rows", type=int, default=0)
+    ap.add_argument("--wpb", type=int, default=0)
+    ap.add_argument("--only-euler", action="store_true")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-probe", type=int, default=0, help="bytes of a plain D2D copy")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py measures one GPU only: the finite-volume path here runs on a single "
+              "MI355X; run it with --gpus 1", file=sys.stderr)
+        sys.exit(2)
+    import torch
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    torch.cuda.set_device(0)
+    if args.copy_probe:
+        copy_probe(args.copy_probe, 10)
+        return
+
+    e = bench_euler(args)
+    value = e["cells"] * args.steps / e["sec"] / 1e9
+    traffic = traffic_from_counters(64.0 * e["cells"])
+    roof = {"bound": "hbm", "achieved": e["achieved"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": e["achieved"] / HBM_PEAK_GBS, "traffic": traffic,
+            "kernel": "fvm::step_kernel<Euler, transmissive>",
+            "algorithmic_bytes_per_launch": 64 * e["cells"],
+            "avg_launch_ms": e["per_launch"] * 1e3}
+    del e["solver"]
+    work = {}
+    if not args.only_euler:
+        log("spray")
+        work["spray"] = bench_spray(200, 10)
+        log("batch")
+        work["batch"] = bench_batch(100, 4)
+        log("adjoint")
+        work["adjoint"] = bench_adjoint(3)
+        log("advection")
+        work["advection"] = bench_advection(100)
+    cpu = None
+    if not args.no_cpu_baseline:
+        log("cpu baseline (oracle)")
+        cpu = cpu_baseline()
+    out = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "Gcell-updates/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": e["sec"] / args.steps * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": "euler_4096x4096", "nx": 4096, "ny": 4096, "nvar": 4,
+                   "flux": "rusanov", "bc": "transmissive", "cfl": 0.45, "subdomains": "8x8",
+                   "init": "four-quadrant Riemann, seed 0",
+                   "tiling": {"rows_per_strip": e["tiling"][0], "waves_per_block": e["tiling"][1]}},
+        "roofline": roof,
+        "cpu_baseline": cpu,
+        "workloads": work,
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

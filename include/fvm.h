@@ -1,0 +1,253 @@
+/*
+ * fvm.h -- C ABI of the MI355X (gfx950) first-order finite-volume library.
+ *
+ * The library advances a two-dimensional system of conservation laws
+ *     dW/dt + div F(W) = S(W)                       (Sec. 2.1)
+ * on an Nx x Ny Cartesian grid with the explicit first-order scheme
+ *     W* = W^n - dt/dx (F~_{i+1/2} - F~_{i-1/2}) - dt/dy (G~_{j+1/2} - G~_{j-1/2})
+ *                                                   (Sec. 2.2.1, eq. VF_scheme)
+ * followed by the split source step W^{n+1} = W* + dt S(W*)
+ *                                                   (Sec. 2.2.2, eq. SourceTerm)
+ * and a time-step reduction over the characteristic speeds
+ *                                                   (Sec. 2.2.1, eq. CFL_cond).
+ *
+ * Models: linear advection (upwind flux), the Euler equations of a perfect
+ * gas with the Lax-Friedrichs (Rusanov) flux (Sec. 5, eq. Euler), and the
+ * six-moment evaporating-spray system with a kinetic upwind flux and an
+ * evaporation + drag source (Sec. 6.1, eq. Essadki).
+ *
+ * Conventions common to every call
+ * --------------------------------
+ *  - States are FP64 structure-of-arrays in device memory: variable v of cell
+ *    (i, j) is at w[(v * ny + j) * ld + i], 0 <= i < nx, 0 <= j < ny, with a
+ *    row pitch ld >= nx (elements). Cell centres are ((i+1/2)dx, (j+1/2)dy),
+ *    dx = lx/nx, dy = ly/ny. nVar is 1 (advection), 4 (Euler: rho, rho u,
+ *    rho v, rho E) or 6 (spray: m_0, m_{1/2}, m_{2/2}, m_{3/2}, q_x, q_y).
+ *  - The caller owns all device memory (state buffers, the spray gas
+ *    velocity, scratch, checkpoints, adjoint buffers). The library never
+ *    allocates or frees device memory. Host-side plans (fvm_grid, fvm_batch)
+ *    are allocated by the library and released by the matching destroy call.
+ *  - Every call that launches work enqueues it asynchronously on the stream
+ *    given at bind time (a hipStream_t passed as void*; NULL = the null
+ *    stream) and returns without waiting. Errors detected on the device (a
+ *    non-finite or non-physical state, a failed CFL check) are recorded in a
+ *    sticky status word in the scratch buffer and returned by the next
+ *    synchronising call (fvm_sync, fvm_cfl_dt_host, fvm_get_status).
+ *  - Every function returns an int status; no exception or abort crosses the
+ *    ABI. Invalid arguments are rejected before anything is enqueued.
+ *  - Calls on one grid must not overlap from several host threads.
+ */
+#ifndef FVM_H
+#define FVM_H
+
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- status codes ------------------------------------------------------ */
+#define FVM_OK 0
+#define FVM_EINVAL (-1)       /* bad shape, pitch, pointer, dt or parameter  */
+#define FVM_EDEVICE (-2)      /* a HIP runtime call failed                   */
+#define FVM_ECFL (-3)         /* fixed-dt step failed the CFL check          */
+#define FVM_ENONFINITE (-4)   /* NaN/inf speed, rho <= 0, p < 0, m_k < 0     */
+#define FVM_EUNSUPPORTED (-5) /* operation not available for this model      */
+
+/* ---- models and boundary conditions ------------------------------------ */
+#define FVM_ADV 0    /* u_t + a.grad u = 0, flux a+ u_L + a- u_R             */
+#define FVM_EULER 1  /* Sec. 5 eq. (Euler), Lax-Friedrichs flux (Sec. 2.2.1) */
+#define FVM_SPRAY 2  /* Sec. 6.1 eq. (Essadki), kinetic upwind flux          */
+
+#define FVM_PERIODIC 0     /* the domain wraps around (Sec. 5)                */
+#define FVM_TRANSMISSIVE 1 /* ghost cell = boundary cell (zero gradient)      */
+
+typedef struct fvm_params {
+  int model;     /* FVM_ADV, FVM_EULER or FVM_SPRAY                          */
+  int bc;        /* FVM_PERIODIC or FVM_TRANSMISSIVE                         */
+  int nx, ny;    /* cells, >= 1 each                                         */
+  int npart_x;   /* NPartX: balanced subdomains along x, nx % npart_x == 0   */
+  int npart_y;   /* NPartY (Sec. 3.2); the result does not depend on them    */
+  int ld;        /* row pitch in elements, >= nx                             */
+  int reserved;  /* must be 0                                                */
+  double lx, ly; /* domain lengths (> 0); dx = lx/nx, dy = ly/ny             */
+  double gamma;  /* Euler: ratio of specific heats (> 1)                     */
+  double ax, ay; /* advection velocity                                       */
+  double K;      /* spray: evaporation rate (>= 0)                           */
+  double theta;  /* spray: drag relaxation time (> 0; +inf = no drag)        */
+  double s_eps;  /* spray: size at which n(S=0) is evaluated (0 < s_eps < 1) */
+  double cfl;    /* Courant number C of the adaptive step (> 0)              */
+  double dt_max; /* time step when every speed is zero (0 = error)           */
+} fvm_params;
+
+typedef struct fvm_grid fvm_grid;
+typedef struct fvm_batch fvm_batch;
+
+/* Human-readable text of a status code. Never NULL. */
+const char* fvm_strerror(int status);
+
+/* nVar of a model, or 0 for an unknown model. */
+int fvm_nvar(int model);
+
+/* Checks a parameter set: FVM_OK or FVM_EINVAL (including nx % npart_x or
+ * ny % npart_y != 0, the balanced-subdomain rule of Sec. 3.2). */
+int fvm_validate(const fvm_params* p);
+
+/* Bytes of device scratch a grid needs (speed maxima, arrival counter, time
+ * step, status word); a multiple of 256. */
+size_t fvm_scratch_bytes(const fvm_params* p);
+
+/* ---- single grid ------------------------------------------------------- */
+
+/* Creates a host-side plan for one grid. No device work, no allocation of
+ * device memory. *out receives the plan (NULL on error). */
+int fvm_create(const fvm_params* p, fvm_grid** out);
+
+/* Releases the plan and any cached HIP graphs. NULL is accepted. */
+int fvm_destroy(fvm_grid* g);
+
+/* Binds caller-owned device memory and a stream to the plan:
+ *   w_a, w_b : two state buffers of nVar * ny * ld doubles each (ping-pong);
+ *              w_a holds the current state after binding;
+ *   ug       : spray only, the gas velocity (u_gx, u_gy) as 2 planes with the
+ *              same pitch, read-only; NULL for other models;
+ *   scratch  : fvm_scratch_bytes(p) bytes, 256-byte aligned;
+ *   stream   : hipStream_t (void*), NULL = null stream.
+ * Enqueues a kernel that clears the scratch (speeds unknown, status 0). */
+int fvm_bind(fvm_grid* g, double* w_a, double* w_b, const double* ug,
+             void* scratch, void* stream);
+
+/* Changes the stream later calls enqueue on. */
+int fvm_set_stream(fvm_grid* g, void* stream);
+
+/* Device pointer of the buffer that holds the current state. */
+int fvm_current(const fvm_grid* g, double** w);
+
+/* Copies a state (pitch ld) into the current buffer; src is a host pointer
+ * if src_on_device == 0 (the call then waits for the copy), else a device
+ * pointer (asynchronous). Marks the speed maxima as unknown. */
+int fvm_set_state(fvm_grid* g, const double* src, int src_on_device);
+
+/* Copies the current state (pitch ld) to dst; a host destination makes the
+ * call wait. */
+int fvm_get_state(fvm_grid* g, double* dst, int dst_on_device);
+
+/* Speed maxima of the current state (checkTimeStep, Sec. 4.2) and the
+ * adaptive time step dt = C / (Sx/dx + Sy/dy), where Sx (Sy) is the largest
+ * |eigenvalue| along x (y) over all cells. Asynchronous; the dt is kept on the
+ * device for the next adaptive step and also written to *dt_dev if non-NULL
+ * (device pointer). */
+int fvm_cfl_dt(fvm_grid* g, double* dt_dev);
+
+/* As fvm_cfl_dt, then waits and returns dt (and the maxima if non-NULL) on
+ * the host; returns the sticky device status. */
+int fvm_cfl_dt_host(fvm_grid* g, double* dt, double* sx, double* sy);
+
+/* One step with a caller-given dt > 0. The step first checks the paper's
+ * condition dt * max_cells max_p |lambda_p| <= min(dx, dy) (eq. CFL_cond) on
+ * the device; if it fails the state is left unchanged and FVM_ECFL is
+ * recorded in the sticky status. */
+int fvm_step(fvm_grid* g, double dt);
+
+/* nsteps adaptive steps: step n uses dt_n = C / (Sx^n/dx + Sy^n/dy) computed
+ * on the device from the maxima of W^n, which the previous step produced in
+ * its epilogue. If dts_dev is non-NULL (device, >= nsteps doubles) it
+ * receives dt_0 .. dt_{nsteps-1}. Replays a cached HIP graph. */
+int fvm_run(fvm_grid* g, int nsteps, double* dts_dev);
+
+/* nsteps steps with the given time steps (device array, no CFL logic): the
+ * frozen-dt replay used by the adjoint and by finite-difference checks. */
+int fvm_run_dts(fvm_grid* g, int nsteps, const double* dts_dev);
+
+/* As fvm_run, and stores checkpoints: ckpts[s] (host array of device
+ * pointers, ceil(nsteps / ckpt_every) of them, each a full state with pitch
+ * ld) receives W^{s * ckpt_every}. The step that produces a checkpointed
+ * state writes it straight into the checkpoint buffer. */
+int fvm_run_ckpt(fvm_grid* g, int nsteps, int ckpt_every,
+                 double* const* ckpts, double* dts_dev);
+
+/* Waits for the stream and returns the sticky device status. */
+int fvm_sync(fvm_grid* g);
+
+/* Waits, then returns the sticky device status (and clears it if clear != 0). */
+int fvm_get_status(fvm_grid* g, int clear);
+
+/* Gradient of a loss of the final state with respect to the initial state,
+ * through nsteps transport steps with frozen time steps (advection and Euler;
+ * FVM_EUNSUPPORTED for the spray model). The adjoint of one step is
+ *   lam^n = lam^{n+1} + dt/dx [J_L(i+1/2)^T (lam_{i+1} - lam_i)
+ *                             + J_R(i-1/2)^T (lam_i - lam_{i-1})] + (same in y)
+ * with J_L, J_R the Jacobians of the numerical flux with respect to its left
+ * and right states (derived from Sec. 2.2.1; max() follows its left argument
+ * on ties). Inputs (all device memory, pitch ld):
+ *   ckpts[s]   : host array of device pointers, W^{s * ckpt_every}, as
+ *                written by fvm_run_ckpt;
+ *   dts_dev    : the nsteps forward time steps;
+ *   lam        : in: dL/dW^N; out: dL/dW^0;
+ *   lam_tmp    : one state of workspace;
+ *   seg_buf    : (ckpt_every - 1) states of workspace for the recomputed
+ *                forward states of one segment (may be NULL if ckpt_every
+ *                is 1).
+ * Each segment recomputes its forward states from its checkpoint with the
+ * forward kernel, then runs its adjoint steps in reverse. Asynchronous. */
+int fvm_adjoint_run(fvm_grid* g, double* const* ckpts, int ckpt_every,
+                    const double* dts_dev, int nsteps, double* lam,
+                    double* lam_tmp, double* seg_buf);
+
+/* One adjoint step at state w with time step dt: lam_out = (dW^{n+1}/dW^n)^T
+ * lam_in (device pointers, pitch ld). Asynchronous. */
+int fvm_adjoint_step(fvm_grid* g, const double* w, double dt,
+                     const double* lam_in, double* lam_out);
+
+/* Kernel tiling of the fused step: rows marched per wave strip and wave
+ * strips per workgroup. 0 keeps the current value. Returns FVM_EINVAL for
+ * values the kernels do not support. */
+int fvm_set_tiling(fvm_grid* g, int rows_per_strip, int waves_per_block);
+int fvm_get_tiling(const fvm_grid* g, int* rows_per_strip, int* waves_per_block);
+
+/* ---- batches of independent grids -------------------------------------- */
+
+/* Creates a plan for n independent grids solved together, one persistent
+ * launch per time step for all of them (each grid keeps its own adaptive
+ * dt). p[k] are the grids' parameters (all the same model, not spray);
+ * offsets[k] is the element offset of grid k's state inside the packed
+ * buffers, a multiple of 32 elements (256 bytes). */
+int fvm_batch_create(int n, const fvm_params* p, const size_t* offsets,
+                     fvm_batch** out);
+int fvm_batch_destroy(fvm_batch* b);
+
+/* Scratch bytes of a batch (per-grid maxima, counters, dt, status, the work
+ * list of (grid, tile) items). */
+size_t fvm_batch_scratch_bytes(const fvm_batch* b);
+
+/* Binds the packed state buffers (each holding every grid at its offset),
+ * the scratch and a stream; w_a holds the current states. */
+int fvm_batch_bind(fvm_batch* b, double* w_a, double* w_b, void* scratch,
+                   void* stream);
+
+/* Computes every grid's speed maxima and adaptive dt (asynchronous). */
+int fvm_batch_cfl(fvm_batch* b);
+
+/* nsteps adaptive steps of every grid, one persistent launch per step
+ * replayed from a cached HIP graph. dts_dev (nullable) receives
+ * dts_dev[s * n + k] = dt of grid k at step s. */
+int fvm_batch_run(fvm_batch* b, int nsteps, double* dts_dev);
+
+/* The same steps with one launch per grid per step (the reference schedule
+ * the persistent launch is compared against). */
+int fvm_batch_run_per_grid(fvm_batch* b, int nsteps, double* dts_dev);
+
+/* Device pointer of the packed buffer holding the current states. */
+int fvm_batch_current(const fvm_batch* b, double** w);
+
+/* Waits and returns the sticky status of the batch. */
+int fvm_batch_sync(fvm_batch* b);
+
+/* Tile shape of the persistent launch (rows per strip, waves per block). */
+int fvm_batch_set_tiling(fvm_batch* b, int rows_per_strip, int waves_per_block);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* FVM_H */

@@ -1,0 +1,564 @@
+// fvm_api.hip -- the C ABI (include/fvm.h): argument checking, plans, the
+// ping-pong schedule, HIP-graph replay of step sequences, status handling.
+// Host code only; the kernels live in fvm_kernels.hip, fvm_batch.hip and
+// fvm_adjoint.hip.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdint>
+#include <cstring>
+#include <list>
+#include <new>
+#include <vector>
+
+#include "../../include/fvm.h"
+#include "fvm_internal.hpp"
+
+namespace fvm {
+void* step_kernel_ptr(int model, int bc, int wpb);
+hipError_t launch_step(const StepArgs& a, int model, hipStream_t st);
+hipError_t launch_cfl(const CflArgs& a, int model, hipStream_t st);
+hipError_t launch_clear_scratch(GridScratch* s, int n, hipStream_t st);
+hipError_t launch_clear_log_cursor(GridScratch* s, hipStream_t st);
+hipError_t launch_adjoint(const AdjointArgs& a, int model, hipStream_t st);
+}  // namespace fvm
+
+using namespace fvm;
+
+namespace {
+
+constexpr int kDefaultRows = 64;
+constexpr int kDefaultWpb = 4;
+constexpr int kGraphChunk = 32;   // steps per cached graph
+constexpr size_t kGraphCacheMax = 16;
+
+bool valid_params(const fvm_params* p) {
+  if (!p) return false;
+  if (fvm_nvar(p->model) == 0) return false;
+  if (p->bc != FVM_PERIODIC && p->bc != FVM_TRANSMISSIVE) return false;
+  if (p->nx < 1 || p->ny < 1 || p->npart_x < 1 || p->npart_y < 1) return false;
+  if (p->nx % p->npart_x != 0 || p->ny % p->npart_y != 0) return false;
+  if (p->ld < p->nx || p->reserved != 0) return false;
+  if (!(p->lx > 0) || !(p->ly > 0) || !std::isfinite(p->lx) || !std::isfinite(p->ly)) return false;
+  if (!(p->cfl > 0) || !std::isfinite(p->cfl)) return false;
+  if (!(p->dt_max >= 0) || !std::isfinite(p->dt_max)) return false;
+  const double cells = static_cast<double>(p->ld) * p->ny * fvm_nvar(p->model);
+  if (cells > 9.0e15) return false;
+  if (p->model == FVM_EULER && !(p->gamma > 1.0 && std::isfinite(p->gamma))) return false;
+  if (p->model == FVM_ADV && !(std::isfinite(p->ax) && std::isfinite(p->ay))) return false;
+  if (p->model == FVM_SPRAY) {
+    if (!(p->K >= 0) || !std::isfinite(p->K)) return false;
+    if (!(p->theta > 0)) return false;
+    if (!(p->s_eps > 0 && p->s_eps < 1)) return false;
+  }
+  return true;
+}
+
+ModelConsts model_consts(const fvm_params& p) {
+  ModelConsts m{};
+  m.gamma = p.gamma;
+  m.gm1 = p.gamma - 1.0;
+  m.ax = p.ax;
+  m.ay = p.ay;
+  m.K = p.K;
+  m.inv_theta = std::isinf(p.theta) ? 0.0 : 1.0 / p.theta;
+  m.s_eps = p.s_eps;
+  m.log_s_eps = p.s_eps > 0 ? std::log(p.s_eps) : 0.0;
+  return m;
+}
+
+GridGeom geometry(const fvm_params& p) {
+  GridGeom g{};
+  g.nx = p.nx;
+  g.ny = p.ny;
+  g.ld = p.ld;
+  g.bc = p.bc;
+  g.plane = static_cast<size_t>(p.ld) * p.ny;
+  g.dx = p.lx / p.nx;
+  g.dy = p.ly / p.ny;
+  g.cfl = p.cfl;
+  g.dt_max = p.dt_max;
+  g.hmin = g.dx < g.dy ? g.dx : g.dy;
+  return g;
+}
+
+Tiling tiling(const GridGeom& g, int rows, int wpb) {
+  Tiling t{};
+  t.rows = rows;
+  t.wpb = wpb;
+  t.tiles_x = (g.nx + kOutPerWave * wpb - 1) / (kOutPerWave * wpb);
+  t.tiles_y = (g.ny + rows - 1) / rows;
+  t.ntiles = t.tiles_x * t.tiles_y;
+  return t;
+}
+
+bool valid_tiling(int rows, int wpb) {
+  return rows >= 1 && rows <= 4096 && (wpb == 1 || wpb == 2 || wpb == 4 || wpb == 8);
+}
+
+int dev_err(hipError_t e) { return e == hipSuccess ? FVM_OK : FVM_EDEVICE; }
+
+int status_from_bits(unsigned int st) {
+  if (st & kStatusNonFinite) return FVM_ENONFINITE;
+  if (st & kStatusCfl) return FVM_ECFL;
+  if (st & kStatusDt) return FVM_EINVAL;
+  return FVM_OK;
+}
+
+struct GraphKey {
+  int kind;              // 0 adaptive run, 1 dts run
+  int nsteps;
+  const double* start;   // input buffer of the first step
+  const double* other;
+  const double* dts;
+  const double* log;
+  int k0;
+  int rows, wpb;
+  bool operator==(const GraphKey& o) const {
+    return kind == o.kind && nsteps == o.nsteps && start == o.start && other == o.other &&
+           dts == o.dts && log == o.log && k0 == o.k0 && rows == o.rows && wpb == o.wpb;
+  }
+};
+
+struct CachedGraph {
+  GraphKey key;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+};
+
+}  // namespace
+
+struct fvm_grid {
+  fvm_params p{};
+  int nv = 0;
+  GridGeom g{};
+  ModelConsts m{};
+  int rows = kDefaultRows, wpb = kDefaultWpb;
+  double* w_a = nullptr;
+  double* w_b = nullptr;
+  double* cur = nullptr;
+  const double* ug = nullptr;
+  GridScratch* scr = nullptr;
+  hipStream_t stream = nullptr;
+  bool bound = false;
+  bool speeds_valid = false;
+  std::list<CachedGraph> graphs;
+
+  ~fvm_grid() { clear_graphs(); }
+  void clear_graphs() {
+    for (auto& c : graphs) {
+      if (c.exec) (void)hipGraphExecDestroy(c.exec);
+      if (c.graph) (void)hipGraphDestroy(c.graph);
+    }
+    graphs.clear();
+  }
+  double* other(const double* w) const { return w == w_a ? w_b : w_a; }
+
+  StepArgs step_args(const double* win, double* wout, int mode) const {
+    StepArgs a{};
+    a.win = win;
+    a.wout = wout;
+    a.ug = ug;
+    a.scr = scr;
+    a.mode = mode;
+    a.dt_log_stride = 1;
+    a.g = g;
+    a.t = tiling(g, rows, wpb);
+    a.m = m;
+    return a;
+  }
+};
+
+extern "C" {
+
+const char* fvm_strerror(int status) {
+  switch (status) {
+    case FVM_OK: return "ok";
+    case FVM_EINVAL: return "invalid argument";
+    case FVM_EDEVICE: return "HIP runtime error";
+    case FVM_ECFL: return "fixed time step violates the CFL condition";
+    case FVM_ENONFINITE: return "non-finite or non-physical state";
+    case FVM_EUNSUPPORTED: return "operation not supported for this model";
+    default: return "unknown status";
+  }
+}
+
+int fvm_nvar(int model) {
+  switch (model) {
+    case FVM_ADV: return 1;
+    case FVM_EULER: return 4;
+    case FVM_SPRAY: return 6;
+    default: return 0;
+  }
+}
+
+int fvm_validate(const fvm_params* p) { return valid_params(p) ? FVM_OK : FVM_EINVAL; }
+
+size_t fvm_scratch_bytes(const fvm_params* p) {
+  if (!valid_params(p)) return 0;
+  return sizeof(GridScratch);
+}
+
+int fvm_create(const fvm_params* p, fvm_grid** out) {
+  if (!out) return FVM_EINVAL;
+  *out = nullptr;
+  if (!valid_params(p)) return FVM_EINVAL;
+  fvm_grid* g = new (std::nothrow) fvm_grid();
+  if (!g) return FVM_EINVAL;
+  g->p = *p;
+  g->nv = fvm_nvar(p->model);
+  g->g = geometry(*p);
+  g->m = model_consts(*p);
+  *out = g;
+  return FVM_OK;
+}
+
+int fvm_destroy(fvm_grid* g) {
+  delete g;
+  return FVM_OK;
+}
+
+int fvm_bind(fvm_grid* g, double* w_a, double* w_b, const double* ug, void* scratch,
+             void* stream) {
+  if (!g || !w_a || !w_b || !scratch || w_a == w_b) return FVM_EINVAL;
+  if ((reinterpret_cast<uintptr_t>(scratch) & 255) != 0) return FVM_EINVAL;
+  if ((reinterpret_cast<uintptr_t>(w_a) & 7) || (reinterpret_cast<uintptr_t>(w_b) & 7))
+    return FVM_EINVAL;
+  if (g->p.model == FVM_SPRAY && !ug) return FVM_EINVAL;
+  if (g->p.model != FVM_SPRAY && ug) return FVM_EINVAL;
+  g->clear_graphs();
+  g->w_a = w_a;
+  g->w_b = w_b;
+  g->cur = w_a;
+  g->ug = ug;
+  g->scr = static_cast<GridScratch*>(scratch);
+  g->stream = static_cast<hipStream_t>(stream);
+  g->bound = true;
+  g->speeds_valid = false;
+  return dev_err(launch_clear_scratch(g->scr, 1, g->stream));
+}
+
+int fvm_set_stream(fvm_grid* g, void* stream) {
+  if (!g) return FVM_EINVAL;
+  g->stream = static_cast<hipStream_t>(stream);
+  return FVM_OK;
+}
+
+int fvm_current(const fvm_grid* g, double** w) {
+  if (!g || !w || !g->bound) return FVM_EINVAL;
+  *w = g->cur;
+  return FVM_OK;
+}
+
+int fvm_set_state(fvm_grid* g, const double* src, int src_on_device) {
+  if (!g || !src || !g->bound) return FVM_EINVAL;
+  const size_t bytes = sizeof(double) * g->nv * g->g.plane;
+  hipError_t e = hipMemcpyAsync(g->cur, src, bytes,
+                                src_on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice,
+                                g->stream);
+  if (e == hipSuccess && !src_on_device) e = hipStreamSynchronize(g->stream);
+  g->speeds_valid = false;
+  return dev_err(e);
+}
+
+int fvm_get_state(fvm_grid* g, double* dst, int dst_on_device) {
+  if (!g || !dst || !g->bound) return FVM_EINVAL;
+  const size_t bytes = sizeof(double) * g->nv * g->g.plane;
+  hipError_t e = hipMemcpyAsync(dst, g->cur, bytes,
+                                dst_on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost,
+                                g->stream);
+  if (e == hipSuccess && !dst_on_device) e = hipStreamSynchronize(g->stream);
+  return dev_err(e);
+}
+
+static int enqueue_cfl(fvm_grid* g, double* dt_dev) {
+  CflArgs a{};
+  a.w = g->cur;
+  a.scr = g->scr;
+  a.dt_out = dt_dev;
+  a.g = g->g;
+  a.m = g->m;
+  const long long cells = static_cast<long long>(g->g.nx) * g->g.ny;
+  a.nblocks = static_cast<int>(std::min<long long>(2048, (cells + 255) / 256));
+  const int rc = dev_err(launch_cfl(a, g->p.model, g->stream));
+  if (rc == FVM_OK) g->speeds_valid = true;
+  return rc;
+}
+
+int fvm_cfl_dt(fvm_grid* g, double* dt_dev) {
+  if (!g || !g->bound) return FVM_EINVAL;
+  return enqueue_cfl(g, dt_dev);
+}
+
+static int read_scratch(fvm_grid* g, GridScratch* host) {
+  hipError_t e = hipStreamSynchronize(g->stream);
+  if (e == hipSuccess) e = hipMemcpy(host, g->scr, sizeof(GridScratch), hipMemcpyDeviceToHost);
+  return dev_err(e);
+}
+
+int fvm_cfl_dt_host(fvm_grid* g, double* dt, double* sx, double* sy) {
+  if (!g || !g->bound || !dt) return FVM_EINVAL;
+  int rc = enqueue_cfl(g, nullptr);
+  if (rc) return rc;
+  GridScratch h;
+  rc = read_scratch(g, &h);
+  if (rc) return rc;
+  *dt = h.dt;
+  if (sx) *sx = h.cur_sx;
+  if (sy) *sy = h.cur_sy;
+  return status_from_bits(h.status);
+}
+
+int fvm_sync(fvm_grid* g) {
+  if (!g || !g->bound) return FVM_EINVAL;
+  GridScratch h;
+  const int rc = read_scratch(g, &h);
+  if (rc) return rc;
+  return status_from_bits(h.status);
+}
+
+int fvm_get_status(fvm_grid* g, int clear) {
+  if (!g || !g->bound) return FVM_EINVAL;
+  GridScratch h;
+  int rc = read_scratch(g, &h);
+  if (rc) return rc;
+  rc = status_from_bits(h.status);
+  if (clear && h.status) {
+    const unsigned int zero = 0;
+    const hipError_t e = hipMemcpy(&g->scr->status, &zero, sizeof(zero), hipMemcpyHostToDevice);
+    if (e != hipSuccess) return FVM_EDEVICE;
+  }
+  return rc;
+}
+
+int fvm_step(fvm_grid* g, double dt) {
+  if (!g || !g->bound) return FVM_EINVAL;
+  if (!(dt > 0.0) || !std::isfinite(dt)) return FVM_EINVAL;
+  int rc = FVM_OK;
+  if (!g->speeds_valid) rc = enqueue_cfl(g, nullptr);
+  if (rc) return rc;
+  StepArgs a = g->step_args(g->cur, g->other(g->cur), kDtFixedCheck);
+  a.dt_arg = dt;
+  rc = dev_err(launch_step(a, g->p.model, g->stream));
+  if (rc == FVM_OK) g->cur = a.wout;
+  return rc;
+}
+
+// Builds (or finds) the graph of `n` consecutive steps starting from buffer
+// `start`, with step k reading its dt according to `mode`.
+static int graph_for(fvm_grid* g, int kind, int n, double* start, const double* dts, int k0,
+                     double* log, int log_cap, hipGraphExec_t* exec) {
+  GraphKey key{kind, n, start, g->other(start), dts, log, k0, g->rows, g->wpb};
+  for (auto it = g->graphs.begin(); it != g->graphs.end(); ++it) {
+    if (it->key == key) {
+      g->graphs.splice(g->graphs.begin(), g->graphs, it);
+      *exec = g->graphs.front().exec;
+      return FVM_OK;
+    }
+  }
+  CachedGraph c;
+  c.key = key;
+  if (hipGraphCreate(&c.graph, 0) != hipSuccess) return FVM_EDEVICE;
+  hipGraphNode_t prev = nullptr;
+  const double* in = start;
+  void* fn = step_kernel_ptr(g->p.model, g->p.bc, g->wpb);
+  std::vector<StepArgs> args(n);
+  for (int s = 0; s < n; ++s) {
+    double* out = g->other(in);
+    args[s] = g->step_args(in, out, kind == 0 ? kDtAdaptive : kDtArray);
+    args[s].dts = dts;
+    args[s].k = k0 + s;
+    args[s].dt_log = log;
+    args[s].dt_log_cap = log_cap;
+    void* kp[] = {&args[s]};
+    hipKernelNodeParams np{};
+    np.func = fn;
+    np.gridDim = dim3(args[s].t.ntiles);
+    np.blockDim = dim3(g->wpb * kWave);
+    np.sharedMemBytes = 0;
+    np.kernelParams = kp;
+    np.extra = nullptr;
+    hipGraphNode_t node;
+    if (hipGraphAddKernelNode(&node, c.graph, prev ? &prev : nullptr, prev ? 1 : 0, &np) !=
+        hipSuccess) {
+      hipGraphDestroy(c.graph);
+      return FVM_EDEVICE;
+    }
+    prev = node;
+    in = out;
+  }
+  if (hipGraphInstantiate(&c.exec, c.graph, nullptr, nullptr, 0) != hipSuccess) {
+    hipGraphDestroy(c.graph);
+    return FVM_EDEVICE;
+  }
+  g->graphs.push_front(c);
+  while (g->graphs.size() > kGraphCacheMax) {
+    auto& b = g->graphs.back();
+    hipGraphExecDestroy(b.exec);
+    hipGraphDestroy(b.graph);
+    g->graphs.pop_back();
+  }
+  *exec = c.exec;
+  return FVM_OK;
+}
+
+static int run_steps(fvm_grid* g, int kind, int nsteps, const double* dts, double* log) {
+  int rc = FVM_OK;
+  if (kind == 0 && !g->speeds_valid) rc = enqueue_cfl(g, nullptr);
+  if (rc) return rc;
+  if (log) rc = dev_err(launch_clear_log_cursor(g->scr, g->stream));
+  if (rc) return rc;
+  int done = 0;
+  while (done < nsteps) {
+    const int n = std::min(kGraphChunk, nsteps - done);
+    hipGraphExec_t exec;
+    rc = graph_for(g, kind, n, g->cur, dts, kind == 1 ? done : 0, log, log ? nsteps : 0, &exec);
+    if (rc) return rc;
+    rc = dev_err(hipGraphLaunch(exec, g->stream));
+    if (rc) return rc;
+    if (n % 2) g->cur = g->other(g->cur);
+    done += n;
+  }
+  g->speeds_valid = true;
+  return FVM_OK;
+}
+
+int fvm_run(fvm_grid* g, int nsteps, double* dts_dev) {
+  if (!g || !g->bound || nsteps < 0) return FVM_EINVAL;
+  return run_steps(g, 0, nsteps, nullptr, dts_dev);
+}
+
+int fvm_run_dts(fvm_grid* g, int nsteps, const double* dts_dev) {
+  if (!g || !g->bound || nsteps < 0 || (nsteps > 0 && !dts_dev)) return FVM_EINVAL;
+  return run_steps(g, 1, nsteps, dts_dev, nullptr);
+}
+
+int fvm_run_ckpt(fvm_grid* g, int nsteps, int ckpt_every, double* const* ckpts,
+                 double* dts_dev) {
+  if (!g || !g->bound || nsteps < 0 || ckpt_every < 1 || !ckpts) return FVM_EINVAL;
+  const int nck = (nsteps + ckpt_every - 1) / ckpt_every;
+  for (int s = 0; s < nck; ++s)
+    if (!ckpts[s] || ckpts[s] == g->w_a || ckpts[s] == g->w_b) return FVM_EINVAL;
+  int rc = FVM_OK;
+  if (!g->speeds_valid) rc = enqueue_cfl(g, nullptr);
+  if (rc) return rc;
+  if (dts_dev) rc = dev_err(launch_clear_log_cursor(g->scr, g->stream));
+  if (rc) return rc;
+  const size_t bytes = sizeof(double) * g->nv * g->g.plane;
+  if (nck > 0) {
+    rc = dev_err(hipMemcpyAsync(ckpts[0], g->cur, bytes, hipMemcpyDeviceToDevice, g->stream));
+    if (rc) return rc;
+  }
+  const double* in = g->cur;
+  for (int k = 0; k < nsteps; ++k) {
+    double* out;
+    if ((k + 1) % ckpt_every == 0 && (k + 1) / ckpt_every < nck)
+      out = ckpts[(k + 1) / ckpt_every];
+    else
+      out = (in == g->w_a) ? g->w_b : g->w_a;
+    StepArgs a = g->step_args(in, out, kDtAdaptive);
+    a.dt_log = dts_dev;
+    a.dt_log_cap = dts_dev ? nsteps : 0;
+    rc = dev_err(launch_step(a, g->p.model, g->stream));
+    if (rc) return rc;
+    in = out;
+  }
+  if (nsteps > 0 && in != g->w_a && in != g->w_b) {
+    // the run ended on a checkpoint buffer: continue from a ping-pong buffer
+    rc = dev_err(hipMemcpyAsync(g->w_a, in, bytes, hipMemcpyDeviceToDevice, g->stream));
+    if (rc) return rc;
+    in = g->w_a;
+  }
+  g->cur = const_cast<double*>(in);
+  return FVM_OK;
+}
+
+int fvm_set_tiling(fvm_grid* g, int rows, int wpb) {
+  if (!g) return FVM_EINVAL;
+  const int r = rows ? rows : g->rows;
+  const int w = wpb ? wpb : g->wpb;
+  if (!valid_tiling(r, w)) return FVM_EINVAL;
+  if (r != g->rows || w != g->wpb) g->clear_graphs();
+  g->rows = r;
+  g->wpb = w;
+  return FVM_OK;
+}
+
+int fvm_get_tiling(const fvm_grid* g, int* rows, int* wpb) {
+  if (!g || !rows || !wpb) return FVM_EINVAL;
+  *rows = g->rows;
+  *wpb = g->wpb;
+  return FVM_OK;
+}
+
+int fvm_adjoint_step(fvm_grid* g, const double* w, double dt, const double* lam_in,
+                     double* lam_out) {
+  if (!g || !g->bound || !w || !lam_in || !lam_out || lam_in == lam_out) return FVM_EINVAL;
+  if (g->p.model == FVM_SPRAY) return FVM_EUNSUPPORTED;
+  if (!(dt >= 0.0) || !std::isfinite(dt)) return FVM_EINVAL;
+  AdjointArgs a{};
+  a.w = w;
+  a.lam_in = lam_in;
+  a.lam_out = lam_out;
+  a.dts = nullptr;
+  a.dt_arg = dt;
+  a.g = g->g;
+  a.t = tiling(g->g, g->rows, g->wpb);
+  a.m = g->m;
+  return dev_err(launch_adjoint(a, g->p.model, g->stream));
+}
+
+int fvm_adjoint_run(fvm_grid* g, double* const* ckpts, int ckpt_every, const double* dts_dev,
+                    int nsteps, double* lam, double* lam_tmp, double* seg_buf) {
+  if (!g || !g->bound || !ckpts || ckpt_every < 1 || !dts_dev || nsteps < 0 || !lam ||
+      !lam_tmp || lam == lam_tmp)
+    return FVM_EINVAL;
+  if (ckpt_every > 1 && !seg_buf) return FVM_EINVAL;
+  if (g->p.model == FVM_SPRAY) return FVM_EUNSUPPORTED;
+  const int nck = (nsteps + ckpt_every - 1) / ckpt_every;
+  for (int s = 0; s < nck; ++s)
+    if (!ckpts[s]) return FVM_EINVAL;
+  const size_t state = g->nv * g->g.plane;
+  double* lin = lam;
+  double* lout = lam_tmp;
+  for (int s = nck - 1; s >= 0; --s) {
+    const int k0 = s * ckpt_every;
+    const int k1 = std::min(nsteps, k0 + ckpt_every);
+    // recompute W^{k0+1} .. W^{k1-1} into seg_buf[0 .. k1-k0-2]
+    const double* in = ckpts[s];
+    for (int k = k0; k + 1 < k1; ++k) {
+      double* out = seg_buf + static_cast<size_t>(k - k0) * state;
+      StepArgs a = g->step_args(in, out, kDtArray);
+      a.dts = dts_dev;
+      a.k = k;
+      int rc = dev_err(launch_step(a, g->p.model, g->stream));
+      if (rc) return rc;
+      in = out;
+    }
+    for (int k = k1 - 1; k >= k0; --k) {
+      const double* wk = (k == k0) ? ckpts[s] : seg_buf + static_cast<size_t>(k - k0 - 1) * state;
+      AdjointArgs a{};
+      a.w = wk;
+      a.lam_in = lin;
+      a.lam_out = lout;
+      a.dts = dts_dev;
+      a.k = k;
+      a.g = g->g;
+      a.t = tiling(g->g, g->rows, g->wpb);
+      a.m = g->m;
+      int rc = dev_err(launch_adjoint(a, g->p.model, g->stream));
+      if (rc) return rc;
+      std::swap(lin, lout);
+    }
+  }
+  // the recompute left the scratch maxima describing a recomputed state
+  g->speeds_valid = false;
+  if (lin != lam) {
+    return dev_err(hipMemcpyAsync(lam, lin, sizeof(double) * state, hipMemcpyDeviceToDevice,
+                                  g->stream));
+  }
+  return FVM_OK;
+}
+
+}  // extern "C"

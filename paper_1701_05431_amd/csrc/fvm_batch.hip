@@ -1,0 +1,477 @@
+// fvm_batch.hip -- many independent grids of uneven sizes advanced together.
+//
+// One persistent launch per time step walks a work list of (grid, tile)
+// items, largest grids first, handed out by an atomic queue, so that the
+// small grids fill the gaps the large ones leave and no launch is smaller
+// than the chip. Each item is the single-grid kernel's tile (same device
+// code, so a grid's result is bit-for-bit the one of a single-grid launch).
+// Each grid keeps its own adaptive dt: the item's workgroup folds its
+// speeds into the grid's maxima and the last item of a grid computes that
+// grid's next dt. The last workgroup of the launch rewinds the queue.
+//
+// The reference schedule -- one launch of the single-grid kernel per grid per
+// time step -- is available as fvm_batch_run_per_grid.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdint>
+#include <list>
+#include <new>
+#include <numeric>
+#include <vector>
+
+#include "../../include/fvm.h"
+#include "fvm_internal.hpp"
+#include "fvm_models.hpp"
+#include "fvm_step.hpp"
+
+namespace fvm {
+
+void* step_kernel_ptr(int model, int bc, int wpb);
+hipError_t launch_cfl(const CflArgs& a, int model, hipStream_t st);
+hipError_t launch_clear_scratch(GridScratch* s, int n, hipStream_t st);
+
+__global__ void batch_clear_kernel(BatchScratch* b, GridScratch* g, int n) {
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k == 0) {
+    BatchScratch z = {};
+    *b = z;
+  }
+  if (k < n) {
+    GridScratch z = {};
+    g[k] = z;
+  }
+}
+
+__global__ void batch_log_rewind_kernel(GridScratch* g, int n) {
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k < n) g[k].nstep = 0;
+}
+
+template <class M, int BC, int WPB>
+__global__ FVM_STEP_BOUNDS(WPB) void batch_kernel(BatchArgs a) {
+  const M m(a.m);
+  __shared__ int s_item;
+  for (;;) {
+    if (threadIdx.x == 0) s_item = static_cast<int>(atomicAdd(&a.bscr->queue, 1u));
+    __syncthreads();
+    const int item = s_item;
+    __syncthreads();
+    if (item >= a.nitems) break;
+    int lo = 0, hi = a.ngrids - 1;
+    while (lo < hi) {
+      const int mid = (lo + hi + 1) >> 1;
+      if (a.grids[mid].item0 <= item) lo = mid; else hi = mid - 1;
+    }
+    const BatchGrid G = a.grids[lo];
+    GridScratch* s = a.gscr + lo;
+    const double dt = s->dt;
+    const double mux = dt / G.g.dx, muy = dt / G.g.dy;
+    const int tile = item - G.item0;
+    const int tx = tile % G.tiles_x, ty = tile / G.tiles_x;
+    const int wave = threadIdx.x / kWave;
+    const int xs = (tx * WPB + wave) * kOutPerWave;
+    const int j0 = ty * a.rows;
+    const int j1 = min(j0 + a.rows, G.g.ny);
+    unsigned long long bx = 0, by = 0;
+    if (xs < G.g.nx)
+      march_strip<M, BC>(m, a.win + G.offset, a.wout + G.offset, nullptr, G.g, xs, j0, j1, mux,
+                         muy, dt, bx, by);
+    if (block_commit<WPB>(bx, by, s, static_cast<unsigned int>(G.ntiles)) && threadIdx.x == 0)
+      finalize_grid(s, G.g, dt, a.dt_log ? a.dt_log + G.user : nullptr, a.dt_log_cap, a.ngrids,
+                    nullptr);
+  }
+  if (threadIdx.x == 0) {
+    __threadfence();
+    const unsigned int t = atomicAdd(&a.bscr->arrive, 1u);
+    if (t == gridDim.x - 1) {
+      atomicExch(&a.bscr->queue, 0u);
+      atomicExch(&a.bscr->arrive, 0u);
+    }
+  }
+}
+
+template <class M, int BC>
+static void* batch_fn_wpb(int wpb) {
+  switch (wpb) {
+    case 1: return reinterpret_cast<void*>(&batch_kernel<M, BC, 1>);
+    case 2: return reinterpret_cast<void*>(&batch_kernel<M, BC, 2>);
+    case 4: return reinterpret_cast<void*>(&batch_kernel<M, BC, 4>);
+    case 8: return reinterpret_cast<void*>(&batch_kernel<M, BC, 8>);
+    default: return nullptr;
+  }
+}
+
+static void* batch_kernel_ptr(int model, int bc, int wpb) {
+  if (model == 0) return bc == 0 ? batch_fn_wpb<Adv, 0>(wpb) : batch_fn_wpb<Adv, 1>(wpb);
+  if (model == 1) return bc == 0 ? batch_fn_wpb<Euler, 0>(wpb) : batch_fn_wpb<Euler, 1>(wpb);
+  return nullptr;
+}
+
+}  // namespace fvm
+
+using namespace fvm;
+
+namespace {
+
+int berr(hipError_t e) { return e == hipSuccess ? FVM_OK : FVM_EDEVICE; }
+
+struct BatchGraph {
+  int kind;  // 0 persistent, 1 per grid
+  int nsteps;
+  const double* start;
+  const double* log;
+  int rows, wpb;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+};
+
+}  // namespace
+
+struct fvm_batch {
+  int n = 0;
+  int model = 0, bc = 0, nv = 0;
+  std::vector<fvm_params> p;
+  std::vector<size_t> offsets;
+  std::vector<int> order;        // processing order (largest first)
+  ModelConsts m{};
+  int rows = 32, wpb = 2;
+  double* w_a = nullptr;
+  double* w_b = nullptr;
+  double* cur = nullptr;
+  unsigned char* scratch = nullptr;
+  hipStream_t stream = nullptr;
+  bool bound = false, speeds_valid = false;
+  int nitems = 0;
+  int nblocks = 0;               // persistent workgroups
+  std::vector<BatchGrid> recs;   // in processing order
+  std::list<BatchGraph> graphs;
+
+  ~fvm_batch() { clear_graphs(); }
+  void clear_graphs() {
+    for (auto& c : graphs) {
+      if (c.exec) (void)hipGraphExecDestroy(c.exec);
+      if (c.graph) (void)hipGraphDestroy(c.graph);
+    }
+    graphs.clear();
+  }
+  BatchScratch* bscr() const { return reinterpret_cast<BatchScratch*>(scratch); }
+  GridScratch* gscr() const {
+    return reinterpret_cast<GridScratch*>(scratch + sizeof(BatchScratch));
+  }
+  BatchGrid* drecs() const {
+    return reinterpret_cast<BatchGrid*>(scratch + sizeof(BatchScratch) +
+                                        sizeof(GridScratch) * static_cast<size_t>(n));
+  }
+  double* other(const double* w) const { return w == w_a ? w_b : w_a; }
+
+  // (re)builds the work list for the current tiling
+  void plan() {
+    recs.clear();
+    int item = 0;
+    for (int k : order) {
+      BatchGrid r{};
+      r.offset = offsets[k];
+      r.user = k;
+      GridGeom g{};
+      g.nx = p[k].nx;
+      g.ny = p[k].ny;
+      g.ld = p[k].ld;
+      g.bc = p[k].bc;
+      g.plane = static_cast<size_t>(p[k].ld) * p[k].ny;
+      g.dx = p[k].lx / p[k].nx;
+      g.dy = p[k].ly / p[k].ny;
+      g.cfl = p[k].cfl;
+      g.dt_max = p[k].dt_max;
+      g.hmin = g.dx < g.dy ? g.dx : g.dy;
+      r.g = g;
+      r.tiles_x = (g.nx + kOutPerWave * wpb - 1) / (kOutPerWave * wpb);
+      r.tiles_y = (g.ny + rows - 1) / rows;
+      r.ntiles = r.tiles_x * r.tiles_y;
+      r.item0 = item;
+      item += r.ntiles;
+      recs.push_back(r);
+    }
+    nitems = item;
+  }
+};
+
+extern "C" {
+
+int fvm_batch_create(int n, const fvm_params* p, const size_t* offsets, fvm_batch** out) {
+  if (!out) return FVM_EINVAL;
+  *out = nullptr;
+  if (n < 1 || !p || !offsets) return FVM_EINVAL;
+  for (int k = 0; k < n; ++k) {
+    if (fvm_validate(&p[k]) != FVM_OK) return FVM_EINVAL;
+    if (p[k].model == FVM_SPRAY) return FVM_EUNSUPPORTED;
+    if (p[k].model != p[0].model || p[k].bc != p[0].bc) return FVM_EINVAL;
+    if (p[k].gamma != p[0].gamma || p[k].ax != p[0].ax || p[k].ay != p[0].ay) return FVM_EINVAL;
+    if (offsets[k] % 32 != 0) return FVM_EINVAL;
+  }
+  const int nv = fvm_nvar(p[0].model);
+  // the grids must not overlap
+  std::vector<int> by_off(n);
+  std::iota(by_off.begin(), by_off.end(), 0);
+  std::sort(by_off.begin(), by_off.end(), [&](int a, int b) { return offsets[a] < offsets[b]; });
+  for (int q = 0; q + 1 < n; ++q) {
+    const int a = by_off[q], b = by_off[q + 1];
+    const size_t end = offsets[a] + static_cast<size_t>(nv) * p[a].ld * p[a].ny;
+    if (end > offsets[b]) return FVM_EINVAL;
+  }
+  fvm_batch* b = new (std::nothrow) fvm_batch();
+  if (!b) return FVM_EINVAL;
+  b->n = n;
+  b->model = p[0].model;
+  b->bc = p[0].bc;
+  b->nv = nv;
+  b->p.assign(p, p + n);
+  b->offsets.assign(offsets, offsets + n);
+  b->order.resize(n);
+  std::iota(b->order.begin(), b->order.end(), 0);
+  std::stable_sort(b->order.begin(), b->order.end(), [&](int x, int y) {
+    return static_cast<long long>(p[x].nx) * p[x].ny > static_cast<long long>(p[y].nx) * p[y].ny;
+  });
+  fvm_params q = p[0];
+  ModelConsts m{};
+  m.gamma = q.gamma;
+  m.gm1 = q.gamma - 1.0;
+  m.ax = q.ax;
+  m.ay = q.ay;
+  b->m = m;
+  b->plan();
+  *out = b;
+  return FVM_OK;
+}
+
+int fvm_batch_destroy(fvm_batch* b) {
+  delete b;
+  return FVM_OK;
+}
+
+size_t fvm_batch_scratch_bytes(const fvm_batch* b) {
+  if (!b) return 0;
+  size_t s = sizeof(BatchScratch) + sizeof(GridScratch) * static_cast<size_t>(b->n) +
+             sizeof(BatchGrid) * static_cast<size_t>(b->n);
+  return (s + 255) / 256 * 256;
+}
+
+static int upload_records(fvm_batch* b) {
+  hipError_t e = hipMemcpyAsync(b->drecs(), b->recs.data(), sizeof(BatchGrid) * b->recs.size(),
+                                hipMemcpyHostToDevice, b->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(b->stream);
+  return berr(e);
+}
+
+int fvm_batch_bind(fvm_batch* b, double* w_a, double* w_b, void* scratch, void* stream) {
+  if (!b || !w_a || !w_b || !scratch || w_a == w_b) return FVM_EINVAL;
+  if (reinterpret_cast<uintptr_t>(scratch) & 255) return FVM_EINVAL;
+  if ((reinterpret_cast<uintptr_t>(w_a) & 255) || (reinterpret_cast<uintptr_t>(w_b) & 255))
+    return FVM_EINVAL;
+  b->clear_graphs();
+  b->w_a = w_a;
+  b->w_b = w_b;
+  b->cur = w_a;
+  b->scratch = static_cast<unsigned char*>(scratch);
+  b->stream = static_cast<hipStream_t>(stream);
+  b->bound = true;
+  b->speeds_valid = false;
+  int dev = 0, cus = 0, per_cu = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return FVM_EDEVICE;
+  if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+    return FVM_EDEVICE;
+  void* f = batch_kernel_ptr(b->model, b->bc, b->wpb);
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, f, b->wpb * kWave, 0) != hipSuccess)
+    return FVM_EDEVICE;
+  b->nblocks = std::max(1, cus * std::max(1, per_cu));
+  hipLaunchKernelGGL(batch_clear_kernel, dim3((b->n + 63) / 64), dim3(64), 0, b->stream,
+                     b->bscr(), b->gscr(), b->n);
+  if (hipGetLastError() != hipSuccess) return FVM_EDEVICE;
+  return upload_records(b);
+}
+
+int fvm_batch_set_tiling(fvm_batch* b, int rows, int wpb) {
+  if (!b) return FVM_EINVAL;
+  const int r = rows ? rows : b->rows;
+  const int w = wpb ? wpb : b->wpb;
+  if (r < 1 || r > 4096 || !(w == 1 || w == 2 || w == 4 || w == 8)) return FVM_EINVAL;
+  b->clear_graphs();
+  b->rows = r;
+  b->wpb = w;
+  b->plan();
+  if (!b->bound) return FVM_OK;
+  int dev = 0, cus = 0, per_cu = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return FVM_EDEVICE;
+  if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+    return FVM_EDEVICE;
+  void* f = batch_kernel_ptr(b->model, b->bc, b->wpb);
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, f, b->wpb * kWave, 0) != hipSuccess)
+    return FVM_EDEVICE;
+  b->nblocks = std::max(1, cus * std::max(1, per_cu));
+  return upload_records(b);
+}
+
+int fvm_batch_cfl(fvm_batch* b) {
+  if (!b || !b->bound) return FVM_EINVAL;
+  for (int q = 0; q < b->n; ++q) {
+    const BatchGrid& r = b->recs[q];
+    CflArgs a{};
+    a.w = b->cur + r.offset;
+    a.scr = b->gscr() + q;
+    a.g = r.g;
+    a.m = b->m;
+    const long long cells = static_cast<long long>(r.g.nx) * r.g.ny;
+    a.nblocks = static_cast<int>(std::min<long long>(1024, (cells + 255) / 256));
+    if (launch_cfl(a, b->model, b->stream) != hipSuccess) return FVM_EDEVICE;
+  }
+  b->speeds_valid = true;
+  return FVM_OK;
+}
+
+static int batch_graph(fvm_batch* b, int kind, int nsteps, double* log, int log_cap,
+                       hipGraphExec_t* exec) {
+  for (auto it = b->graphs.begin(); it != b->graphs.end(); ++it) {
+    if (it->kind == kind && it->nsteps == nsteps && it->start == b->cur && it->log == log &&
+        it->rows == b->rows && it->wpb == b->wpb) {
+      b->graphs.splice(b->graphs.begin(), b->graphs, it);
+      *exec = b->graphs.front().exec;
+      return FVM_OK;
+    }
+  }
+  BatchGraph c;
+  c.kind = kind;
+  c.nsteps = nsteps;
+  c.start = b->cur;
+  c.log = log;
+  c.rows = b->rows;
+  c.wpb = b->wpb;
+  if (hipGraphCreate(&c.graph, 0) != hipSuccess) return FVM_EDEVICE;
+  hipGraphNode_t prev = nullptr;
+  const double* in = b->cur;
+  auto add = [&](void* fn, dim3 grid, dim3 block, void* arg) -> bool {
+    void* kp[] = {arg};
+    hipKernelNodeParams np{};
+    np.func = fn;
+    np.gridDim = grid;
+    np.blockDim = block;
+    np.sharedMemBytes = 0;
+    np.kernelParams = kp;
+    np.extra = nullptr;
+    hipGraphNode_t node;
+    if (hipGraphAddKernelNode(&node, c.graph, prev ? &prev : nullptr, prev ? 1 : 0, &np) !=
+        hipSuccess)
+      return false;
+    prev = node;
+    return true;
+  };
+  bool ok = true;
+  for (int s = 0; s < nsteps && ok; ++s) {
+    double* out = b->other(in);
+    if (kind == 0) {
+      BatchArgs a{};
+      a.win = in;
+      a.wout = out;
+      a.grids = b->drecs();
+      a.gscr = b->gscr();
+      a.bscr = b->bscr();
+      a.dt_log = log;
+      a.dt_log_cap = log_cap;
+      a.ngrids = b->n;
+      a.nitems = b->nitems;
+      a.rows = b->rows;
+      a.m = b->m;
+      ok = add(batch_kernel_ptr(b->model, b->bc, b->wpb), dim3(std::min(b->nblocks, b->nitems)),
+               dim3(b->wpb * kWave), &a);
+    } else {
+      for (int q = 0; q < b->n && ok; ++q) {
+        const BatchGrid& r = b->recs[q];
+        StepArgs a{};
+        a.win = in + r.offset;
+        a.wout = out + r.offset;
+        a.scr = b->gscr() + q;
+        a.dt_log = log ? log + r.user : nullptr;
+        a.dt_log_cap = log_cap;
+        a.dt_log_stride = b->n;
+        a.mode = kDtAdaptive;
+        a.g = r.g;
+        a.t.rows = b->rows;
+        a.t.wpb = b->wpb;
+        a.t.tiles_x = r.tiles_x;
+        a.t.tiles_y = r.tiles_y;
+        a.t.ntiles = r.ntiles;
+        a.m = b->m;
+        ok = add(step_kernel_ptr(b->model, b->bc, b->wpb), dim3(r.ntiles), dim3(b->wpb * kWave),
+                 &a);
+      }
+    }
+    in = out;
+  }
+  if (!ok || hipGraphInstantiate(&c.exec, c.graph, nullptr, nullptr, 0) != hipSuccess) {
+    hipGraphDestroy(c.graph);
+    return FVM_EDEVICE;
+  }
+  b->graphs.push_front(c);
+  while (b->graphs.size() > 8) {
+    auto& x = b->graphs.back();
+    hipGraphExecDestroy(x.exec);
+    hipGraphDestroy(x.graph);
+    b->graphs.pop_back();
+  }
+  *exec = c.exec;
+  return FVM_OK;
+}
+
+static int batch_run(fvm_batch* b, int kind, int nsteps, double* log) {
+  if (!b || !b->bound || nsteps < 0) return FVM_EINVAL;
+  int rc = FVM_OK;
+  if (!b->speeds_valid) rc = fvm_batch_cfl(b);
+  if (rc) return rc;
+  if (log) {
+    hipLaunchKernelGGL(batch_log_rewind_kernel, dim3((b->n + 63) / 64), dim3(64), 0, b->stream,
+                       b->gscr(), b->n);
+    if (hipGetLastError() != hipSuccess) return FVM_EDEVICE;
+  }
+  const int chunk = kind == 0 ? 32 : 2;
+  int done = 0;
+  while (done < nsteps) {
+    const int n = std::min(chunk, nsteps - done);
+    hipGraphExec_t exec;
+    rc = batch_graph(b, kind, n, log, log ? nsteps : 0, &exec);
+    if (rc) return rc;
+    if (hipGraphLaunch(exec, b->stream) != hipSuccess) return FVM_EDEVICE;
+    if (n % 2) b->cur = b->other(b->cur);
+    done += n;
+  }
+  return FVM_OK;
+}
+
+int fvm_batch_run(fvm_batch* b, int nsteps, double* dts_dev) {
+  return batch_run(b, 0, nsteps, dts_dev);
+}
+
+int fvm_batch_run_per_grid(fvm_batch* b, int nsteps, double* dts_dev) {
+  return batch_run(b, 1, nsteps, dts_dev);
+}
+
+int fvm_batch_current(const fvm_batch* b, double** w) {
+  if (!b || !w || !b->bound) return FVM_EINVAL;
+  *w = b->cur;
+  return FVM_OK;
+}
+
+int fvm_batch_sync(fvm_batch* b) {
+  if (!b || !b->bound) return FVM_EINVAL;
+  if (hipStreamSynchronize(b->stream) != hipSuccess) return FVM_EDEVICE;
+  std::vector<GridScratch> h(b->n);
+  if (hipMemcpy(h.data(), b->gscr(), sizeof(GridScratch) * b->n, hipMemcpyDeviceToHost) !=
+      hipSuccess)
+    return FVM_EDEVICE;
+  unsigned int st = 0;
+  for (const auto& x : h) st |= x.status;
+  if (st & kStatusNonFinite) return FVM_ENONFINITE;
+  if (st & kStatusDt) return FVM_EINVAL;
+  return FVM_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,137 @@
+// fvm_internal.hpp -- launch-argument structures shared by the host library
+// and the kernels. Plain data only (passed to kernels by value).
+#pragma once
+
+#include <cstddef>
+#include <cstdint>
+
+namespace fvm {
+
+constexpr int kWave = 64;       // CDNA wavefront width
+constexpr int kOutPerWave = 62; // cells a 64-lane wave strip updates (2 halo lanes)
+
+// Sticky device status bits.
+enum : unsigned int {
+  kStatusNonFinite = 1u,  // NaN/inf speed or a non-physical cell
+  kStatusCfl = 2u,        // fixed-dt step failed the CFL check
+  kStatusDt = 4u,         // adaptive dt not positive (all speeds zero, no dt_max)
+};
+
+// Time-step source of a step launch.
+enum : int {
+  kDtAdaptive = 0,  // dt from the device scratch (previous finalize)
+  kDtFixedCheck = 1,// dt from the argument, checked against eq. CFL_cond
+  kDtArray = 2,     // dt = dts[k]
+};
+
+// Per-grid device scratch (256-byte aligned, cleared by the init kernel).
+struct alignas(256) GridScratch {
+  unsigned long long smax[2];  // running maxima (bit patterns) of the state being produced
+  unsigned int arrive;         // arrival counter of the current launch
+  unsigned int status;         // sticky status bits
+  unsigned int nstep;          // dt-log cursor
+  unsigned int pad0;
+  double dt;                   // dt of the next adaptive step
+  double cur_sx, cur_sy;       // finalized maxima of the current state
+  double pad1[2];
+};
+static_assert(sizeof(GridScratch) == 256, "scratch layout");
+
+// Model constants.
+struct ModelConsts {
+  double gamma, gm1;          // Euler
+  double ax, ay;              // advection
+  double K, inv_theta;        // spray (inv_theta = 0 for no drag)
+  double s_eps, log_s_eps;    // spray closure
+};
+
+// Geometry and policy of one grid.
+struct GridGeom {
+  int nx, ny, ld, bc;
+  size_t plane;               // ld * ny
+  double dx, dy;              // lx/nx, ly/ny
+  double cfl, dt_max;
+  double hmin;                // min(dx, dy) for the fixed-dt check
+};
+
+// Tile decomposition of one grid for a launch.
+struct Tiling {
+  int rows;        // rows marched per strip
+  int wpb;         // wave strips per workgroup
+  int tiles_x;     // ceil(nx / (62 * wpb))
+  int tiles_y;     // ceil(ny / rows)
+  int ntiles;
+};
+
+struct StepArgs {
+  const double* win;
+  double* wout;
+  const double* ug;           // spray gas velocity (2 planes) or null
+  GridScratch* scr;
+  double* dt_log;             // nullable
+  int dt_log_cap;
+  int mode;
+  double dt_arg;              // kDtFixedCheck
+  const double* dts;          // kDtArray
+  int k;                      // kDtArray index
+  int dt_log_stride;          // elements between consecutive logged dts
+  GridGeom g;
+  Tiling t;
+  ModelConsts m;
+};
+
+struct CflArgs {
+  const double* w;
+  GridScratch* scr;
+  double* dt_out;             // nullable device pointer
+  GridGeom g;
+  ModelConsts m;
+  int nblocks;
+};
+
+struct AdjointArgs {
+  const double* w;            // forward state W^n
+  const double* lam_in;       // lambda^{n+1}
+  double* lam_out;            // lambda^n
+  const double* dts;          // dt = dts[k] if dts != null, else dt_arg
+  int k;
+  int pad;
+  double dt_arg;
+  GridGeom g;
+  Tiling t;
+  ModelConsts m;
+};
+
+// ---- batches ---------------------------------------------------------------
+
+struct BatchGrid {            // per-grid record in device memory
+  size_t offset;              // element offset of the grid inside the packed buffers
+  GridGeom g;
+  int tiles_x, tiles_y, ntiles, item0;  // item0: first work item of the grid
+  int user, pad;                       // the caller's index of the grid
+};
+
+struct BatchScratch {         // header of the batch scratch
+  unsigned int queue;         // next work item
+  unsigned int arrive;        // blocks done with the launch
+  unsigned int status;
+  unsigned int nstep;
+  unsigned int pad[60];
+};
+static_assert(sizeof(BatchScratch) == 256, "batch scratch layout");
+
+struct BatchArgs {
+  const double* win;
+  double* wout;
+  const BatchGrid* grids;     // device array of n records
+  GridScratch* gscr;          // device array of n per-grid scratch blocks
+  BatchScratch* bscr;
+  double* dt_log;             // nullable, dt_log[step * ngrids + grid]
+  int dt_log_cap;             // steps the log can hold
+  int ngrids;                 // records sorted by item0 (largest grids first)
+  int nitems;
+  int rows;
+  ModelConsts m;
+};
+
+}  // namespace fvm

@@ -1,0 +1,149 @@
+// fvm_kernels.hip -- gfx950 kernels of the fused first-order finite-volume step.
+//
+// One launch performs one whole time step (Sec. 2.2.1 eq. VF_scheme + the
+// split source of Sec. 2.2.2 + the time-step reduction of eq. CFL_cond) on
+// a grid held as FP64 structure-of-arrays planes in HBM.
+//
+// Work decomposition. A wave (64 lanes) owns a strip of 64 consecutive
+// columns [xs-1, xs+62] and marches up a range of rows. Lane l holds the
+// state of column xs-1+l for the current row and the next row in registers;
+// the rows below and above come from the march (each y-face flux is computed
+// once and carried to the next row), and the left/right neighbours come from
+// the adjacent lanes by DPP moves (each x-face flux is computed once by the
+// lane on its left and handed to the lane on its right). Lanes 1..62 write
+// their updated cells; lanes 0 and 63 only supply the halo. This replaces the
+// paper's overlap strips and its copyOverlaps / internalResiduals /
+// borderResiduals / update tasks: a subdomain border is an ordinary neighbour
+// read straight from HBM, and every cell goes through the same code path, so
+// the result does not depend on how the grid is split into subdomains or
+// tiles.
+//
+// Each state is read once and written once per step (plus the halo rows and
+// columns of each strip). The new state's speeds are reduced in the same
+// pass (wave shuffle, workgroup LDS, one 64-bit atomicMax per workgroup on
+// the bit patterns, which orders non-negative doubles and puts NaN above
+// +inf), and the last workgroup to arrive computes the next time step on the
+// device.
+#include <hip/hip_runtime.h>
+
+#include <cfloat>
+#include <cstdint>
+
+#include "fvm_internal.hpp"
+#include "fvm_models.hpp"
+#include "fvm_step.hpp"
+
+namespace fvm {
+
+template <class M, int BC, int WPB>
+__global__ FVM_STEP_BOUNDS(WPB) void step_kernel(StepArgs a) {
+  const M m(a.m);
+  bool cfl_fail;
+  const double dt = launch_dt(a, cfl_fail);
+  const double dt_eff = cfl_fail ? 0.0 : dt;
+  const double mux = dt_eff / a.g.dx, muy = dt_eff / a.g.dy;
+  const int tile = xcd_tile(blockIdx.x, a.t.ntiles);
+  const int tx = tile % a.t.tiles_x, ty = tile / a.t.tiles_x;
+  const int wave = threadIdx.x / kWave;
+  const int xs = (tx * WPB + wave) * kOutPerWave;
+  const int j0 = ty * a.t.rows;
+  const int j1 = min(j0 + a.t.rows, a.g.ny);
+  unsigned long long bx = 0, by = 0;
+  if (xs < a.g.nx) march_strip<M, BC>(m, a.win, a.wout, a.ug, a.g, xs, j0, j1, mux, muy, dt_eff, bx, by);
+  if (block_commit<WPB>(bx, by, a.scr, gridDim.x) && threadIdx.x == 0) {
+    if (cfl_fail) atomicOr(&a.scr->status, kStatusCfl);
+    finalize_grid(a.scr, a.g, dt_eff, a.dt_log, a.dt_log_cap, a.dt_log_stride, nullptr);
+  }
+}
+
+// Speed maxima of a state and the adaptive dt (the checkTimeStep task).
+template <class M>
+__global__ __launch_bounds__(256) void cfl_kernel(CflArgs a) {
+  const M m(a.m);
+  unsigned long long bx = 0, by = 0;
+  const long long ncell = static_cast<long long>(a.g.nx) * a.g.ny;
+  for (long long c = blockIdx.x * 256ll + threadIdx.x; c < ncell; c += 256ll * gridDim.x) {
+    const int j = static_cast<int>(c / a.g.nx), i = static_cast<int>(c % a.g.nx);
+    double w[M::NV];
+#pragma unroll
+    for (int v = 0; v < M::NV; ++v) w[v] = a.w[v * a.g.plane + static_cast<size_t>(j) * a.g.ld + i];
+    double sx, sy;
+    m.speeds(w, sx, sy);
+    bx = umax64(bx, bits(sx));
+    by = umax64(by, bits(sy));
+  }
+  if (block_commit<4>(bx, by, a.scr, gridDim.x) && threadIdx.x == 0)
+    finalize_grid(a.scr, a.g, 0.0, nullptr, 0, 1, a.dt_out);
+}
+
+__global__ void clear_scratch_kernel(GridScratch* s, int n) {
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k < n) {
+    GridScratch z = {};
+    s[k] = z;
+  }
+}
+
+__global__ void clear_log_cursor_kernel(GridScratch* s) { s->nstep = 0; }
+
+}  // namespace fvm
+
+// ---- host-side launch helpers (used by fvm_api.hip) --------------------------------
+namespace fvm {
+
+using StepFn = void (*)(StepArgs);
+
+template <class M, int BC>
+static StepFn step_fn_wpb(int wpb) {
+  switch (wpb) {
+    case 1: return &step_kernel<M, BC, 1>;
+    case 2: return &step_kernel<M, BC, 2>;
+    case 4: return &step_kernel<M, BC, 4>;
+    case 8: return &step_kernel<M, BC, 8>;
+    default: return nullptr;
+  }
+}
+
+template <class M>
+static StepFn step_fn_bc(int bc, int wpb) {
+  return bc == 0 ? step_fn_wpb<M, 0>(wpb) : step_fn_wpb<M, 1>(wpb);
+}
+
+void* step_kernel_ptr(int model, int bc, int wpb) {
+  StepFn f = nullptr;
+  if (model == 0) f = step_fn_bc<Adv>(bc, wpb);
+  else if (model == 1) f = step_fn_bc<Euler>(bc, wpb);
+  else if (model == 2) f = step_fn_bc<Spray>(bc, wpb);
+  return reinterpret_cast<void*>(f);
+}
+
+hipError_t launch_step(const StepArgs& a, int model, hipStream_t st) {
+  void* f = step_kernel_ptr(model, a.g.bc, a.t.wpb);
+  if (!f) return hipErrorInvalidValue;
+  StepArgs copy = a;
+  void* args[] = {&copy};
+  return hipLaunchKernel(f, dim3(a.t.ntiles), dim3(a.t.wpb * kWave), args, 0, st);
+}
+
+hipError_t launch_cfl(const CflArgs& a, int model, hipStream_t st) {
+  CflArgs copy = a;
+  void* args[] = {&copy};
+  void* f = nullptr;
+  if (model == 0) f = reinterpret_cast<void*>(&cfl_kernel<Adv>);
+  else if (model == 1) f = reinterpret_cast<void*>(&cfl_kernel<Euler>);
+  else if (model == 2) f = reinterpret_cast<void*>(&cfl_kernel<Spray>);
+  if (!f) return hipErrorInvalidValue;
+  return hipLaunchKernel(f, dim3(a.nblocks), dim3(256), args, 0, st);
+}
+
+hipError_t launch_clear_scratch(GridScratch* s, int n, hipStream_t st) {
+  hipLaunchKernelGGL(clear_scratch_kernel, dim3((n + 63) / 64), dim3(64), 0, st, s, n);
+  return hipGetLastError();
+}
+
+hipError_t launch_clear_log_cursor(GridScratch* s, hipStream_t st) {
+  hipLaunchKernelGGL(clear_log_cursor_kernel, dim3(1), dim3(1), 0, st, s);
+  return hipGetLastError();
+}
+
+}  // namespace fvm

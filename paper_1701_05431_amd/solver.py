@@ -1,0 +1,298 @@
+"""Python front end over the C ABI: single grids, batches of grids, and the
+differentiable run (torch.autograd.Function over the hand-written adjoint).
+
+PyTorch only provides device memory and the stream; all arithmetic of the
+method runs in the library's HIP kernels.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import math
+
+import numpy as np
+import torch
+
+from . import _lib
+from ._lib import check, lib
+
+
+def params_from(preset=None, **kw) -> _lib.Params:
+    """fvm_params from a workload preset (or keyword arguments)."""
+    d = dict(model=None, bc=_lib.FVM_PERIODIC, nx=None, ny=None, npart_x=1, npart_y=1,
+             ld=None, lx=1.0, ly=1.0, gamma=1.4, ax=0.0, ay=0.0, K=1.0, theta=0.1,
+             s_eps=0.01, cfl=0.45, dt_max=0.0)
+    if preset is not None:
+        for k in ("model", "bc", "nx", "ny", "npart_x", "npart_y", "lx", "ly", "gamma", "ax",
+                  "ay", "K", "theta", "s_eps", "cfl", "dt_max"):
+            d[k] = getattr(preset, k)
+    d.update(kw)
+    if d["ld"] is None:
+        d["ld"] = d["nx"]
+    p = _lib.Params()
+    for k, v in d.items():
+        setattr(p, k, v)
+    p.reserved = 0
+    return p
+
+
+def _ptr(t: torch.Tensor | None):
+    return None if t is None else C.c_void_p(t.data_ptr())
+
+
+def _stream_handle(device) -> C.c_void_p:
+    return C.c_void_p(torch.cuda.current_stream(device).cuda_stream)
+
+
+class Solver:
+    """One grid: two ping-pong state buffers [nVar, Ny, ld] (float64), the
+    spray gas velocity if any, and the scratch, all allocated by torch."""
+
+    def __init__(self, p: _lib.Params, device="cuda", ug=None):
+        L = lib()
+        check(L.fvm_validate(C.byref(p)), "fvm_validate")
+        self.p = p
+        self.device = torch.device(device)
+        self.nv = L.fvm_nvar(p.model)
+        shape = (self.nv, p.ny, p.ld)
+        self.wa = torch.zeros(shape, dtype=torch.float64, device=self.device)
+        self.wb = torch.zeros(shape, dtype=torch.float64, device=self.device)
+        self.ug = None
+        if p.model == _lib.FVM_SPRAY:
+            if ug is None:
+                raise ValueError("the spray model needs the gas velocity field ug")
+            self.ug = self._as_state(ug, 2)
+        nbytes = int(L.fvm_scratch_bytes(C.byref(p)))
+        self.scratch = torch.zeros(nbytes + 256, dtype=torch.uint8, device=self.device)
+        off = (-self.scratch.data_ptr()) % 256
+        self.scratch_view = self.scratch[off:off + nbytes]
+        h = C.c_void_p()
+        check(L.fvm_create(C.byref(p), C.byref(h)), "fvm_create")
+        self.h = h
+        check(L.fvm_bind(self.h, _ptr(self.wa), _ptr(self.wb), _ptr(self.ug),
+                         _ptr(self.scratch_view), _stream_handle(self.device)), "fvm_bind")
+
+    def __del__(self):
+        h = getattr(self, "h", None)
+        if h is not None and h.value:
+            try:
+                lib().fvm_destroy(h)
+            except Exception:
+                pass
+            self.h = None
+
+    # ---- state -------------------------------------------------------------
+    def _as_state(self, W, nv=None) -> torch.Tensor:
+        nv = self.nv if nv is None else nv
+        p = self.p
+        if isinstance(W, np.ndarray):
+            W = torch.from_numpy(np.ascontiguousarray(W, dtype=np.float64))
+        W = W.to(device=self.device, dtype=torch.float64)
+        if W.shape == (nv, p.ny, p.nx) and p.ld != p.nx:
+            out = torch.zeros((nv, p.ny, p.ld), dtype=torch.float64, device=self.device)
+            out[:, :, :p.nx] = W
+            W = out
+        if W.shape != (nv, p.ny, p.ld):
+            raise ValueError(f"state shape {tuple(W.shape)} does not match ({nv}, {p.ny}, {p.ld})")
+        return W.contiguous()
+
+    def _bind_stream(self):
+        lib().fvm_set_stream(self.h, _stream_handle(self.device))
+
+    def set_state(self, W) -> None:
+        src = self._as_state(W)
+        self._bind_stream()
+        check(lib().fvm_set_state(self.h, _ptr(src), 1), "fvm_set_state")
+        self._keep = src  # keep the source alive until the copy has run
+
+    def current(self) -> torch.Tensor:
+        """The buffer holding the current state (a view; the next step
+        overwrites the other buffer, not this one)."""
+        ptr = C.c_void_p()
+        check(lib().fvm_current(self.h, C.byref(ptr)), "fvm_current")
+        return self.wa if ptr.value == self.wa.data_ptr() else self.wb
+
+    def state(self) -> torch.Tensor:
+        """A copy of the current state, shape (nVar, Ny, Nx)."""
+        return self.current()[:, :, :self.p.nx].clone()
+
+    # ---- stepping ------------------------------------------------------------
+    def cfl_dt(self):
+        """(dt, Sx, Sy) of the current state (synchronises)."""
+        self._bind_stream()
+        dt, sx, sy = C.c_double(), C.c_double(), C.c_double()
+        check(lib().fvm_cfl_dt_host(self.h, C.byref(dt), C.byref(sx), C.byref(sy)), "fvm_cfl_dt")
+        return dt.value, sx.value, sy.value
+
+    def step(self, dt: float) -> None:
+        self._bind_stream()
+        check(lib().fvm_step(self.h, float(dt)), "fvm_step")
+
+    def run(self, nsteps: int, record_dt: bool = False):
+        self._bind_stream()
+        dts = torch.zeros(max(nsteps, 1), dtype=torch.float64, device=self.device) if record_dt else None
+        check(lib().fvm_run(self.h, int(nsteps), _ptr(dts)), "fvm_run")
+        return dts[:nsteps] if record_dt else None
+
+    def run_dts(self, dts) -> None:
+        dts = torch.as_tensor(dts, dtype=torch.float64).to(self.device).contiguous()
+        self._bind_stream()
+        check(lib().fvm_run_dts(self.h, int(dts.numel()), _ptr(dts)), "fvm_run_dts")
+        self._keep = dts
+
+    def run_ckpt(self, nsteps: int, every: int):
+        """Adaptive run that stores W^0, W^every, ...; returns (ckpts, dts)."""
+        nck = (nsteps + every - 1) // every
+        ck = [torch.empty_like(self.wa) for _ in range(nck)]
+        dts = torch.zeros(max(nsteps, 1), dtype=torch.float64, device=self.device)
+        arr = (C.c_void_p * max(nck, 1))(*[t.data_ptr() for t in ck])
+        self._bind_stream()
+        check(lib().fvm_run_ckpt(self.h, int(nsteps), int(every), arr, _ptr(dts)), "fvm_run_ckpt")
+        return ck, dts[:nsteps]
+
+    def adjoint(self, ckpts, every: int, dts: torch.Tensor, lam: torch.Tensor) -> torch.Tensor:
+        """dL/dW^0 from dL/dW^N (lam, shape (nVar, Ny, ld)) through len(dts)
+        steps with the given checkpoints."""
+        lam = self._as_state(lam).clone()
+        tmp = torch.empty_like(lam)
+        seg = torch.empty((max(every - 1, 1),) + tuple(lam.shape), dtype=torch.float64,
+                          device=self.device)
+        arr = (C.c_void_p * max(len(ckpts), 1))(*[t.data_ptr() for t in ckpts])
+        self._bind_stream()
+        check(lib().fvm_adjoint_run(self.h, arr, int(every), _ptr(dts), int(dts.numel()),
+                                    _ptr(lam), _ptr(tmp), _ptr(seg)), "fvm_adjoint_run")
+        self._keep = (tmp, seg)
+        return lam
+
+    def adjoint_step(self, W, dt: float, lam) -> torch.Tensor:
+        W = self._as_state(W)
+        lam = self._as_state(lam)
+        out = torch.empty_like(lam)
+        self._bind_stream()
+        check(lib().fvm_adjoint_step(self.h, _ptr(W), float(dt), _ptr(lam), _ptr(out)),
+              "fvm_adjoint_step")
+        self._keep = (W, lam)
+        return out
+
+    def sync(self) -> int:
+        return int(lib().fvm_sync(self.h))
+
+    def status(self, clear: bool = False) -> int:
+        return int(lib().fvm_get_status(self.h, int(clear)))
+
+    def set_tiling(self, rows: int = 0, waves_per_block: int = 0) -> None:
+        check(lib().fvm_set_tiling(self.h, int(rows), int(waves_per_block)), "fvm_set_tiling")
+
+    def tiling(self):
+        r, w = C.c_int(), C.c_int()
+        check(lib().fvm_get_tiling(self.h, C.byref(r), C.byref(w)), "fvm_get_tiling")
+        return r.value, w.value
+
+
+class Batch:
+    """Many independent grids packed in one buffer per ping-pong side, each
+    at a 256-byte aligned offset."""
+
+    def __init__(self, plist, device="cuda"):
+        L = lib()
+        self.device = torch.device(device)
+        n = len(plist)
+        self.n = n
+        self.plist = list(plist)
+        self.nv = L.fvm_nvar(plist[0].model)
+        offs, o = [], 0
+        for p in plist:
+            offs.append(o)
+            o += self.nv * p.ny * p.ld
+            o = (o + 31) // 32 * 32
+        self.offsets = offs
+        self.total = o
+        self.wa = torch.zeros(o, dtype=torch.float64, device=self.device)
+        self.wb = torch.zeros(o, dtype=torch.float64, device=self.device)
+        parr = (_lib.Params * n)(*plist)
+        oarr = (C.c_size_t * n)(*offs)
+        h = C.c_void_p()
+        check(L.fvm_batch_create(n, parr, oarr, C.byref(h)), "fvm_batch_create")
+        self.h = h
+        nbytes = int(L.fvm_batch_scratch_bytes(self.h))
+        self.scratch = torch.zeros(nbytes + 256, dtype=torch.uint8, device=self.device)
+        off = (-self.scratch.data_ptr()) % 256
+        self.scratch_view = self.scratch[off:off + nbytes]
+        check(L.fvm_batch_bind(self.h, _ptr(self.wa), _ptr(self.wb), _ptr(self.scratch_view),
+                               _stream_handle(self.device)), "fvm_batch_bind")
+
+    def __del__(self):
+        h = getattr(self, "h", None)
+        if h is not None and h.value:
+            try:
+                lib().fvm_batch_destroy(h)
+            except Exception:
+                pass
+            self.h = None
+
+    def current(self) -> torch.Tensor:
+        ptr = C.c_void_p()
+        check(lib().fvm_batch_current(self.h, C.byref(ptr)), "fvm_batch_current")
+        return self.wa if ptr.value == self.wa.data_ptr() else self.wb
+
+    def view(self, buf: torch.Tensor, k: int) -> torch.Tensor:
+        p = self.plist[k]
+        n = self.nv * p.ny * p.ld
+        return buf[self.offsets[k]:self.offsets[k] + n].view(self.nv, p.ny, p.ld)
+
+    def set_states(self, states) -> None:
+        cur = self.current()
+        for k, W in enumerate(states):
+            p = self.plist[k]
+            if isinstance(W, np.ndarray):
+                W = torch.from_numpy(np.ascontiguousarray(W))
+            self.view(cur, k)[:, :, :p.nx].copy_(W.to(self.device, torch.float64))
+        # the maxima of the new states are unknown until the next cfl
+        check(lib().fvm_batch_cfl(self.h), "fvm_batch_cfl")
+
+    def states(self):
+        cur = self.current()
+        return [self.view(cur, k)[:, :, :self.plist[k].nx].clone() for k in range(self.n)]
+
+    def run(self, nsteps: int, record_dt: bool = False, per_grid: bool = False):
+        dts = (torch.zeros(max(nsteps, 1) * self.n, dtype=torch.float64, device=self.device)
+               if record_dt else None)
+        f = lib().fvm_batch_run_per_grid if per_grid else lib().fvm_batch_run
+        check(f(self.h, int(nsteps), _ptr(dts)), "fvm_batch_run")
+        return dts[:nsteps * self.n].view(nsteps, self.n) if record_dt else None
+
+    def set_tiling(self, rows: int = 0, waves_per_block: int = 0) -> None:
+        check(lib().fvm_batch_set_tiling(self.h, int(rows), int(waves_per_block)),
+              "fvm_batch_set_tiling")
+
+    def sync(self) -> int:
+        return int(lib().fvm_batch_sync(self.h))
+
+
+class FVRun(torch.autograd.Function):
+    """W^N = run(W^0) with adaptive time steps; backward is the hand-written
+    discrete adjoint with the forward dts held fixed, recomputing each
+    segment of `every` steps from its checkpoint.
+
+    FVRun.apply(W0, solver, nsteps, every) with W0 of shape (nVar, Ny, Nx).
+    """
+
+    @staticmethod
+    def forward(ctx, W0, solver: Solver, nsteps: int, every: int):
+        solver.set_state(W0.detach())
+        ck, dts = solver.run_ckpt(nsteps, every)
+        ctx.solver = solver
+        ctx.every = every
+        ctx.ckpts = ck
+        ctx.dts = dts
+        return solver.state()
+
+    @staticmethod
+    def backward(ctx, gN):
+        s = ctx.solver
+        lam = s.adjoint(ctx.ckpts, ctx.every, ctx.dts, gN.detach().contiguous())
+        return lam[:, :, :s.p.nx].clone(), None, None, None
+
+
+def fvrun(W0: torch.Tensor, solver: Solver, nsteps: int, every: int | None = None):
+    every = every or max(1, int(round(math.sqrt(nsteps))))
+    return FVRun.apply(W0, solver, nsteps, every)

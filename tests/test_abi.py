@@ -1,0 +1,114 @@
+"""The C ABI without a GPU: the library loads, exports every symbol that
+include/fvm.h declares, and rejects invalid parameters on the host."""
+import ctypes as C
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "fvm.h")
+
+
+@pytest.fixture(scope="module")
+def L():
+    from paper_1701_05431_amd import _lib
+    if not os.path.exists(_lib.LIB_PATH):
+        from paper_1701_05431_amd import build
+        build.build()
+    return _lib.lib()
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(fvm_[a-z_0-9]+)\s*\(", text)))
+
+
+def test_every_declared_symbol_is_exported(L):
+    names = declared_functions()
+    assert len(names) >= 30
+    for n in names:
+        assert hasattr(L, n), n
+
+
+def test_binding_covers_the_header():
+    from paper_1701_05431_amd import _lib
+    assert set(declared_functions()) == set(_lib.SIGNATURES)
+
+
+def test_params_struct_layout():
+    from paper_1701_05431_amd import _lib
+    # 8 ints followed by 10 doubles, no padding
+    assert C.sizeof(_lib.Params) == 8 * 4 + 10 * 8
+
+
+def test_validation_on_host(L):
+    from paper_1701_05431_amd import _lib
+    from paper_1701_05431_amd.solver import params_from
+    ok = params_from(model=1, nx=64, ny=32, npart_x=8, npart_y=4)
+    assert L.fvm_validate(ok) == _lib.FVM_OK
+    assert L.fvm_scratch_bytes(ok) % 256 == 0 and L.fvm_scratch_bytes(ok) > 0
+    cases = [
+        dict(npart_x=3),            # unbalanced subdomains
+        dict(ld=63),                # pitch below nx
+        dict(nx=0),
+        dict(model=9),
+        dict(bc=5),
+        dict(gamma=1.0),
+        dict(cfl=0.0),
+        dict(cfl=float("nan")),
+        dict(lx=-1.0),
+        dict(dt_max=-1.0),
+    ]
+    for c in cases:
+        kw = dict(model=1, nx=64, ny=32, npart_x=8, npart_y=4)
+        kw.update(c)
+        p = params_from(**kw)
+        assert L.fvm_validate(p) == _lib.FVM_EINVAL, c
+        assert L.fvm_scratch_bytes(p) == 0, c
+        h = C.c_void_p()
+        assert L.fvm_create(p, C.byref(h)) == _lib.FVM_EINVAL, c
+        assert not h.value
+    sp = params_from(model=2, nx=8, ny=8, theta=0.0)
+    assert L.fvm_validate(sp) == _lib.FVM_EINVAL
+    sp = params_from(model=2, nx=8, ny=8, s_eps=1.5)
+    assert L.fvm_validate(sp) == _lib.FVM_EINVAL
+
+
+def test_create_destroy_and_unbound_calls(L):
+    from paper_1701_05431_amd import _lib
+    from paper_1701_05431_amd.solver import params_from
+    p = params_from(model=1, nx=64, ny=32)
+    h = C.c_void_p()
+    assert L.fvm_create(p, C.byref(h)) == _lib.FVM_OK and h.value
+    # nothing is bound: every device call is refused before touching HIP
+    assert L.fvm_run(h, 3, None) == _lib.FVM_EINVAL
+    assert L.fvm_step(h, 0.1) == _lib.FVM_EINVAL
+    assert L.fvm_sync(h) == _lib.FVM_EINVAL
+    r, w = C.c_int(), C.c_int()
+    assert L.fvm_get_tiling(h, C.byref(r), C.byref(w)) == _lib.FVM_OK
+    assert L.fvm_set_tiling(h, 16, 2) == _lib.FVM_OK
+    assert L.fvm_set_tiling(h, 16, 3) == _lib.FVM_EINVAL
+    assert L.fvm_set_tiling(h, -1, 2) == _lib.FVM_EINVAL
+    assert L.fvm_destroy(h) == _lib.FVM_OK
+    assert L.fvm_destroy(None) == _lib.FVM_OK
+    assert L.fvm_strerror(-4) == b"non-finite or non-physical state"
+    assert L.fvm_nvar(2) == 6 and L.fvm_nvar(7) == 0
+
+
+def test_batch_create_validation(L):
+    from paper_1701_05431_amd import _lib
+    from paper_1701_05431_amd.solver import params_from
+    ps = [params_from(model=1, bc=1, nx=n, ny=n) for n in (64, 100)]
+    arr = (_lib.Params * 2)(*ps)
+    h = C.c_void_p()
+    assert L.fvm_batch_create(2, arr, (C.c_size_t * 2)(0, 4 * 64 * 64), C.byref(h)) == 0
+    assert L.fvm_batch_scratch_bytes(h) % 256 == 0
+    assert L.fvm_batch_destroy(h) == 0
+    # overlapping grids
+    assert L.fvm_batch_create(2, arr, (C.c_size_t * 2)(0, 32), C.byref(h)) == _lib.FVM_EINVAL
+    # misaligned offset
+    assert L.fvm_batch_create(2, arr, (C.c_size_t * 2)(0, 4 * 64 * 64 + 8), C.byref(h)) == _lib.FVM_EINVAL
+    sp = (_lib.Params * 1)(params_from(model=2, nx=8, ny=8))
+    assert L.fvm_batch_create(1, sp, (C.c_size_t * 1)(0), C.byref(h)) == _lib.FVM_EUNSUPPORTED
