@@ -205,6 +205,14 @@ int fvm_adjoint_step(fvm_grid* g, const double* w, double dt,
 int fvm_set_tiling(fvm_grid* g, int rows_per_strip, int waves_per_block);
 int fvm_get_tiling(const fvm_grid* g, int* rows_per_strip, int* waves_per_block);
 
+/* Lane layout of the fused step: 1 = one cell per lane (any pitch), 2 = two
+ * adjacent cells per lane with 16-byte accesses (needs an even ld and 16-byte
+ * aligned buffers; otherwise the call falls back to 1), 0 = the model's
+ * default. Results are bitwise identical for every layout. fvm_get returns
+ * the layout in use. */
+int fvm_set_cells_per_lane(fvm_grid* g, int cells_per_lane);
+int fvm_get_cells_per_lane(const fvm_grid* g);
+
 /* ---- batches of independent grids -------------------------------------- */
 
 /* Creates a plan for n independent grids solved together, one persistent

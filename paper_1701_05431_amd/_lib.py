@@ -63,6 +63,8 @@ SIGNATURES = {
     "fvm_adjoint_step": (C.c_int, [_V, _V, C.c_double, _V, _V]),
     "fvm_set_tiling": (C.c_int, [_V, C.c_int, C.c_int]),
     "fvm_get_tiling": (C.c_int, [_V, C.POINTER(C.c_int), C.POINTER(C.c_int)]),
+    "fvm_set_cells_per_lane": (C.c_int, [_V, C.c_int]),
+    "fvm_get_cells_per_lane": (C.c_int, [_V]),
     "fvm_batch_create": (C.c_int, [C.c_int, _P, C.POINTER(C.c_size_t), C.POINTER(_V)]),
     "fvm_batch_destroy": (C.c_int, [_V]),
     "fvm_batch_scratch_bytes": (C.c_size_t, [_V]),

@@ -166,7 +166,7 @@ __global__ __launch_bounds__(WPB * kWave) void adjoint_kernel(AdjointArgs a) {
   const double mux = dt / a.g.dx, muy = dt / a.g.dy;
   const int tile = blockIdx.x;
   const int tx = tile % a.t.tiles_x, ty = tile / a.t.tiles_x;
-  const int wave = threadIdx.x / kWave;
+  const int wave = wave_index();
   const int lane = threadIdx.x & (kWave - 1);
   const int xs = (tx * WPB + wave) * kOutPerWave;
   if (xs >= a.g.nx) return;

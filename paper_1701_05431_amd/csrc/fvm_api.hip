@@ -16,7 +16,7 @@
 #include "fvm_internal.hpp"
 
 namespace fvm {
-void* step_kernel_ptr(int model, int bc, int wpb);
+void* step_kernel_ptr(int model, int bc, int wpb, int cpl);
 hipError_t launch_step(const StepArgs& a, int model, hipStream_t st);
 hipError_t launch_cfl(const CflArgs& a, int model, hipStream_t st);
 hipError_t launch_clear_scratch(GridScratch* s, int n, hipStream_t st);
@@ -83,11 +83,13 @@ GridGeom geometry(const fvm_params& p) {
   return g;
 }
 
-Tiling tiling(const GridGeom& g, int rows, int wpb) {
+Tiling tiling(const GridGeom& g, int rows, int wpb, int cpl) {
   Tiling t{};
   t.rows = rows;
   t.wpb = wpb;
-  t.tiles_x = (g.nx + kOutPerWave * wpb - 1) / (kOutPerWave * wpb);
+  t.cpl = cpl;
+  const int w = strip_width(cpl) * wpb;
+  t.tiles_x = (g.nx + w - 1) / w;
   t.tiles_y = (g.ny + rows - 1) / rows;
   t.ntiles = t.tiles_x * t.tiles_y;
   return t;
@@ -114,10 +116,11 @@ struct GraphKey {
   const double* dts;
   const double* log;
   int k0;
-  int rows, wpb;
+  int rows, wpb, cpl;
   bool operator==(const GraphKey& o) const {
     return kind == o.kind && nsteps == o.nsteps && start == o.start && other == o.other &&
-           dts == o.dts && log == o.log && k0 == o.k0 && rows == o.rows && wpb == o.wpb;
+           dts == o.dts && log == o.log && k0 == o.k0 && rows == o.rows && wpb == o.wpb &&
+           cpl == o.cpl;
   }
 };
 
@@ -135,6 +138,8 @@ struct fvm_grid {
   GridGeom g{};
   ModelConsts m{};
   int rows = kDefaultRows, wpb = kDefaultWpb;
+  int cpl_req = 0;   // requested cells per lane (0: the widest the buffers allow)
+  int cpl = 1;       // layout in use
   double* w_a = nullptr;
   double* w_b = nullptr;
   double* cur = nullptr;
@@ -164,7 +169,7 @@ struct fvm_grid {
     a.mode = mode;
     a.dt_log_stride = 1;
     a.g = g;
-    a.t = tiling(g, rows, wpb);
+    a.t = tiling(g, rows, wpb, cpl);
     a.m = m;
     return a;
   }
@@ -208,6 +213,16 @@ int fvm_create(const fvm_params* p, fvm_grid** out) {
   if (!g) return FVM_EINVAL;
   g->p = *p;
   g->nv = fvm_nvar(p->model);
+  // measured defaults on MI355X (two cells per lane): Euler 4096^2 is
+  // fastest with 64-row strips in 8-wave workgroups, the spray model (more
+  // registers per lane) with 32-row strips in 4-wave workgroups
+  if (p->model == FVM_EULER) {
+    g->rows = 64;
+    g->wpb = 8;
+  } else if (p->model == FVM_SPRAY) {
+    g->rows = 32;
+    g->wpb = 4;
+  }
   g->g = geometry(*p);
   g->m = model_consts(*p);
   *out = g;
@@ -217,6 +232,19 @@ int fvm_create(const fvm_params* p, fvm_grid** out) {
 int fvm_destroy(fvm_grid* g) {
   delete g;
   return FVM_OK;
+}
+
+// Two cells per lane needs an even pitch and 16-byte aligned buffers.
+static bool wide_layout_ok(const fvm_grid* g) {
+  auto al = [](const void* p) { return (reinterpret_cast<uintptr_t>(p) & 15) == 0; };
+  return g->p.ld % 2 == 0 && al(g->w_a) && al(g->w_b) && (!g->ug || al(g->ug));
+}
+
+static void choose_layout(fvm_grid* g) {
+  const int want = g->cpl_req ? g->cpl_req : 2;
+  const int cpl = (want == 2 && g->bound && wide_layout_ok(g)) ? 2 : 1;
+  if (cpl != g->cpl) g->clear_graphs();
+  g->cpl = cpl;
 }
 
 int fvm_bind(fvm_grid* g, double* w_a, double* w_b, const double* ug, void* scratch,
@@ -235,6 +263,7 @@ int fvm_bind(fvm_grid* g, double* w_a, double* w_b, const double* ug, void* scra
   g->scr = static_cast<GridScratch*>(scratch);
   g->stream = static_cast<hipStream_t>(stream);
   g->bound = true;
+  choose_layout(g);
   g->speeds_valid = false;
   return dev_err(launch_clear_scratch(g->scr, 1, g->stream));
 }
@@ -349,7 +378,7 @@ int fvm_step(fvm_grid* g, double dt) {
 // `start`, with step k reading its dt according to `mode`.
 static int graph_for(fvm_grid* g, int kind, int n, double* start, const double* dts, int k0,
                      double* log, int log_cap, hipGraphExec_t* exec) {
-  GraphKey key{kind, n, start, g->other(start), dts, log, k0, g->rows, g->wpb};
+  GraphKey key{kind, n, start, g->other(start), dts, log, k0, g->rows, g->wpb, g->cpl};
   for (auto it = g->graphs.begin(); it != g->graphs.end(); ++it) {
     if (it->key == key) {
       g->graphs.splice(g->graphs.begin(), g->graphs, it);
@@ -362,7 +391,7 @@ static int graph_for(fvm_grid* g, int kind, int n, double* start, const double* 
   if (hipGraphCreate(&c.graph, 0) != hipSuccess) return FVM_EDEVICE;
   hipGraphNode_t prev = nullptr;
   const double* in = start;
-  void* fn = step_kernel_ptr(g->p.model, g->p.bc, g->wpb);
+  void* fn = step_kernel_ptr(g->p.model, g->p.bc, g->wpb, g->cpl);
   std::vector<StepArgs> args(n);
   for (int s = 0; s < n; ++s) {
     double* out = g->other(in);
@@ -485,6 +514,15 @@ int fvm_set_tiling(fvm_grid* g, int rows, int wpb) {
   return FVM_OK;
 }
 
+int fvm_set_cells_per_lane(fvm_grid* g, int cpl) {
+  if (!g || cpl < 0 || cpl > 2) return FVM_EINVAL;
+  g->cpl_req = cpl;
+  choose_layout(g);
+  return FVM_OK;
+}
+
+int fvm_get_cells_per_lane(const fvm_grid* g) { return g ? g->cpl : 0; }
+
 int fvm_get_tiling(const fvm_grid* g, int* rows, int* wpb) {
   if (!g || !rows || !wpb) return FVM_EINVAL;
   *rows = g->rows;
@@ -504,7 +542,7 @@ int fvm_adjoint_step(fvm_grid* g, const double* w, double dt, const double* lam_
   a.dts = nullptr;
   a.dt_arg = dt;
   a.g = g->g;
-  a.t = tiling(g->g, g->rows, g->wpb);
+  a.t = tiling(g->g, g->rows, g->wpb, 1);
   a.m = g->m;
   return dev_err(launch_adjoint(a, g->p.model, g->stream));
 }
@@ -545,7 +583,7 @@ int fvm_adjoint_run(fvm_grid* g, double* const* ckpts, int ckpt_every, const dou
       a.dts = dts_dev;
       a.k = k;
       a.g = g->g;
-      a.t = tiling(g->g, g->rows, g->wpb);
+      a.t = tiling(g->g, g->rows, g->wpb, 1);
       a.m = g->m;
       int rc = dev_err(launch_adjoint(a, g->p.model, g->stream));
       if (rc) return rc;

@@ -28,7 +28,7 @@
 
 namespace fvm {
 
-void* step_kernel_ptr(int model, int bc, int wpb);
+void* step_kernel_ptr(int model, int bc, int wpb, int cpl);
 hipError_t launch_cfl(const CflArgs& a, int model, hipStream_t st);
 hipError_t launch_clear_scratch(GridScratch* s, int n, hipStream_t st);
 
@@ -49,7 +49,7 @@ __global__ void batch_log_rewind_kernel(GridScratch* g, int n) {
   if (k < n) g[k].nstep = 0;
 }
 
-template <class M, int BC, int WPB>
+template <class M, int BC, int WPB, int CPL>
 __global__ FVM_STEP_BOUNDS(WPB) void batch_kernel(BatchArgs a) {
   const M m(a.m);
   __shared__ int s_item;
@@ -70,14 +70,22 @@ __global__ FVM_STEP_BOUNDS(WPB) void batch_kernel(BatchArgs a) {
     const double mux = dt / G.g.dx, muy = dt / G.g.dy;
     const int tile = item - G.item0;
     const int tx = tile % G.tiles_x, ty = tile / G.tiles_x;
-    const int wave = threadIdx.x / kWave;
-    const int xs = (tx * WPB + wave) * kOutPerWave;
+    const int wave = wave_index();
+    const int xs = (tx * WPB + wave) * strip_width(CPL);
     const int j0 = ty * a.rows;
     const int j1 = min(j0 + a.rows, G.g.ny);
     unsigned long long bx = 0, by = 0;
-    if (xs < G.g.nx)
-      march_strip<M, BC>(m, a.win + G.offset, a.wout + G.offset, nullptr, G.g, xs, j0, j1, mux,
-                         muy, dt, bx, by);
+    if (xs < G.g.nx) {
+      if (CPL == 1)
+        march_strip<M, BC>(m, a.win + G.offset, a.wout + G.offset, nullptr, G.g, xs, j0, j1, mux,
+                           muy, dt, bx, by);
+      else if (xs + 2 * kWave <= G.g.nx)
+        march_strip2<M, BC, false>(m, a.win + G.offset, a.wout + G.offset, nullptr, G.g, xs, j0,
+                                   j1, mux, muy, dt, bx, by);
+      else
+        march_strip2<M, BC, true>(m, a.win + G.offset, a.wout + G.offset, nullptr, G.g, xs, j0,
+                                  j1, mux, muy, dt, bx, by);
+    }
     if (block_commit<WPB>(bx, by, s, static_cast<unsigned int>(G.ntiles)) && threadIdx.x == 0)
       finalize_grid(s, G.g, dt, a.dt_log ? a.dt_log + G.user : nullptr, a.dt_log_cap, a.ngrids,
                     nullptr);
@@ -92,20 +100,26 @@ __global__ FVM_STEP_BOUNDS(WPB) void batch_kernel(BatchArgs a) {
   }
 }
 
-template <class M, int BC>
+template <class M, int BC, int CPL>
 static void* batch_fn_wpb(int wpb) {
   switch (wpb) {
-    case 1: return reinterpret_cast<void*>(&batch_kernel<M, BC, 1>);
-    case 2: return reinterpret_cast<void*>(&batch_kernel<M, BC, 2>);
-    case 4: return reinterpret_cast<void*>(&batch_kernel<M, BC, 4>);
-    case 8: return reinterpret_cast<void*>(&batch_kernel<M, BC, 8>);
+    case 1: return reinterpret_cast<void*>(&batch_kernel<M, BC, 1, CPL>);
+    case 2: return reinterpret_cast<void*>(&batch_kernel<M, BC, 2, CPL>);
+    case 4: return reinterpret_cast<void*>(&batch_kernel<M, BC, 4, CPL>);
+    case 8: return reinterpret_cast<void*>(&batch_kernel<M, BC, 8, CPL>);
     default: return nullptr;
   }
 }
 
-static void* batch_kernel_ptr(int model, int bc, int wpb) {
-  if (model == 0) return bc == 0 ? batch_fn_wpb<Adv, 0>(wpb) : batch_fn_wpb<Adv, 1>(wpb);
-  if (model == 1) return bc == 0 ? batch_fn_wpb<Euler, 0>(wpb) : batch_fn_wpb<Euler, 1>(wpb);
+template <class M>
+static void* batch_fn_bc(int bc, int wpb, int cpl) {
+  if (cpl == 2) return bc == 0 ? batch_fn_wpb<M, 0, 2>(wpb) : batch_fn_wpb<M, 1, 2>(wpb);
+  return bc == 0 ? batch_fn_wpb<M, 0, 1>(wpb) : batch_fn_wpb<M, 1, 1>(wpb);
+}
+
+static void* batch_kernel_ptr(int model, int bc, int wpb, int cpl) {
+  if (model == 0) return batch_fn_bc<Adv>(bc, wpb, cpl);
+  if (model == 1) return batch_fn_bc<Euler>(bc, wpb, cpl);
   return nullptr;
 }
 
@@ -122,7 +136,7 @@ struct BatchGraph {
   int nsteps;
   const double* start;
   const double* log;
-  int rows, wpb;
+  int rows, wpb, cpl;
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
 };
@@ -137,6 +151,7 @@ struct fvm_batch {
   std::vector<int> order;        // processing order (largest first)
   ModelConsts m{};
   int rows = 32, wpb = 2;
+  int cpl = 1;                   // 2 when every grid has an even pitch
   double* w_a = nullptr;
   double* w_b = nullptr;
   double* cur = nullptr;
@@ -186,7 +201,7 @@ struct fvm_batch {
       g.dt_max = p[k].dt_max;
       g.hmin = g.dx < g.dy ? g.dx : g.dy;
       r.g = g;
-      r.tiles_x = (g.nx + kOutPerWave * wpb - 1) / (kOutPerWave * wpb);
+      r.tiles_x = (g.nx + strip_width(cpl) * wpb - 1) / (strip_width(cpl) * wpb);
       r.tiles_y = (g.ny + rows - 1) / rows;
       r.ntiles = r.tiles_x * r.tiles_y;
       r.item0 = item;
@@ -240,6 +255,9 @@ int fvm_batch_create(int n, const fvm_params* p, const size_t* offsets, fvm_batc
   m.ax = q.ax;
   m.ay = q.ay;
   b->m = m;
+  bool even = true;
+  for (int k = 0; k < n; ++k) even = even && (p[k].ld % 2 == 0);
+  b->cpl = even ? 2 : 1;
   b->plan();
   *out = b;
   return FVM_OK;
@@ -281,7 +299,7 @@ int fvm_batch_bind(fvm_batch* b, double* w_a, double* w_b, void* scratch, void* 
   if (hipGetDevice(&dev) != hipSuccess) return FVM_EDEVICE;
   if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
     return FVM_EDEVICE;
-  void* f = batch_kernel_ptr(b->model, b->bc, b->wpb);
+  void* f = batch_kernel_ptr(b->model, b->bc, b->wpb, b->cpl);
   if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, f, b->wpb * kWave, 0) != hipSuccess)
     return FVM_EDEVICE;
   b->nblocks = std::max(1, cus * std::max(1, per_cu));
@@ -305,7 +323,7 @@ int fvm_batch_set_tiling(fvm_batch* b, int rows, int wpb) {
   if (hipGetDevice(&dev) != hipSuccess) return FVM_EDEVICE;
   if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
     return FVM_EDEVICE;
-  void* f = batch_kernel_ptr(b->model, b->bc, b->wpb);
+  void* f = batch_kernel_ptr(b->model, b->bc, b->wpb, b->cpl);
   if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, f, b->wpb * kWave, 0) != hipSuccess)
     return FVM_EDEVICE;
   b->nblocks = std::max(1, cus * std::max(1, per_cu));
@@ -333,7 +351,7 @@ static int batch_graph(fvm_batch* b, int kind, int nsteps, double* log, int log_
                        hipGraphExec_t* exec) {
   for (auto it = b->graphs.begin(); it != b->graphs.end(); ++it) {
     if (it->kind == kind && it->nsteps == nsteps && it->start == b->cur && it->log == log &&
-        it->rows == b->rows && it->wpb == b->wpb) {
+        it->rows == b->rows && it->wpb == b->wpb && it->cpl == b->cpl) {
       b->graphs.splice(b->graphs.begin(), b->graphs, it);
       *exec = b->graphs.front().exec;
       return FVM_OK;
@@ -346,6 +364,7 @@ static int batch_graph(fvm_batch* b, int kind, int nsteps, double* log, int log_
   c.log = log;
   c.rows = b->rows;
   c.wpb = b->wpb;
+  c.cpl = b->cpl;
   if (hipGraphCreate(&c.graph, 0) != hipSuccess) return FVM_EDEVICE;
   hipGraphNode_t prev = nullptr;
   const double* in = b->cur;
@@ -381,7 +400,8 @@ static int batch_graph(fvm_batch* b, int kind, int nsteps, double* log, int log_
       a.nitems = b->nitems;
       a.rows = b->rows;
       a.m = b->m;
-      ok = add(batch_kernel_ptr(b->model, b->bc, b->wpb), dim3(std::min(b->nblocks, b->nitems)),
+      ok = add(batch_kernel_ptr(b->model, b->bc, b->wpb, b->cpl),
+               dim3(std::min(b->nblocks, b->nitems)),
                dim3(b->wpb * kWave), &a);
     } else {
       for (int q = 0; q < b->n && ok; ++q) {
@@ -397,11 +417,13 @@ static int batch_graph(fvm_batch* b, int kind, int nsteps, double* log, int log_
         a.g = r.g;
         a.t.rows = b->rows;
         a.t.wpb = b->wpb;
+        a.t.cpl = b->cpl;
         a.t.tiles_x = r.tiles_x;
         a.t.tiles_y = r.tiles_y;
         a.t.ntiles = r.ntiles;
         a.m = b->m;
-        ok = add(step_kernel_ptr(b->model, b->bc, b->wpb), dim3(r.ntiles), dim3(b->wpb * kWave),
+        ok = add(step_kernel_ptr(b->model, b->bc, b->wpb, b->cpl), dim3(r.ntiles),
+                 dim3(b->wpb * kWave),
                  &a);
       }
     }

@@ -2,6 +2,8 @@
 // and the kernels. Plain data only (passed to kernels by value).
 #pragma once
 
+#include <hip/hip_runtime.h>
+
 #include <cstddef>
 #include <cstdint>
 
@@ -54,11 +56,16 @@ struct GridGeom {
   double hmin;                // min(dx, dy) for the fixed-dt check
 };
 
+// Cells a wave strip updates: 62 with one cell per lane (lanes 0 and 63 are
+// the halo), 128 with two cells per lane.
+__host__ __device__ constexpr int strip_width(int cpl) { return cpl == 2 ? 2 * kWave : kOutPerWave; }
+
 // Tile decomposition of one grid for a launch.
 struct Tiling {
   int rows;        // rows marched per strip
   int wpb;         // wave strips per workgroup
-  int tiles_x;     // ceil(nx / (62 * wpb))
+  int cpl;         // cells per lane (1 or 2)
+  int tiles_x;     // ceil(nx / (strip_width * wpb))
   int tiles_y;     // ceil(ny / rows)
   int ntiles;
 };

@@ -35,7 +35,25 @@
 
 namespace fvm {
 
-template <class M, int BC, int WPB>
+// One wave strip of the CPL layout (1: 62 cells per wave, any pitch; 2: 128
+// cells per wave, 16-byte aligned accesses).
+template <class M, int BC, int CPL>
+__device__ __forceinline__ void strip(const M& m, const double* __restrict__ win,
+                                      double* __restrict__ wout, const double* __restrict__ ug,
+                                      const GridGeom& g, int xs, int j0, int j1, double mux,
+                                      double muy, double dt, unsigned long long& bx,
+                                      unsigned long long& by) {
+  if (xs >= g.nx) return;
+  if (CPL == 1) {
+    march_strip<M, BC>(m, win, wout, ug, g, xs, j0, j1, mux, muy, dt, bx, by);
+  } else if (xs + 2 * kWave <= g.nx) {
+    march_strip2<M, BC, false>(m, win, wout, ug, g, xs, j0, j1, mux, muy, dt, bx, by);
+  } else {
+    march_strip2<M, BC, true>(m, win, wout, ug, g, xs, j0, j1, mux, muy, dt, bx, by);
+  }
+}
+
+template <class M, int BC, int WPB, int CPL>
 __global__ FVM_STEP_BOUNDS(WPB) void step_kernel(StepArgs a) {
   const M m(a.m);
   bool cfl_fail;
@@ -44,12 +62,12 @@ __global__ FVM_STEP_BOUNDS(WPB) void step_kernel(StepArgs a) {
   const double mux = dt_eff / a.g.dx, muy = dt_eff / a.g.dy;
   const int tile = xcd_tile(blockIdx.x, a.t.ntiles);
   const int tx = tile % a.t.tiles_x, ty = tile / a.t.tiles_x;
-  const int wave = threadIdx.x / kWave;
-  const int xs = (tx * WPB + wave) * kOutPerWave;
+  const int wave = wave_index();
+  const int xs = (tx * WPB + wave) * strip_width(CPL);
   const int j0 = ty * a.t.rows;
   const int j1 = min(j0 + a.t.rows, a.g.ny);
   unsigned long long bx = 0, by = 0;
-  if (xs < a.g.nx) march_strip<M, BC>(m, a.win, a.wout, a.ug, a.g, xs, j0, j1, mux, muy, dt_eff, bx, by);
+  strip<M, BC, CPL>(m, a.win, a.wout, a.ug, a.g, xs, j0, j1, mux, muy, dt_eff, bx, by);
   if (block_commit<WPB>(bx, by, a.scr, gridDim.x) && threadIdx.x == 0) {
     if (cfl_fail) atomicOr(&a.scr->status, kStatusCfl);
     finalize_grid(a.scr, a.g, dt_eff, a.dt_log, a.dt_log_cap, a.dt_log_stride, nullptr);
@@ -93,32 +111,33 @@ namespace fvm {
 
 using StepFn = void (*)(StepArgs);
 
-template <class M, int BC>
+template <class M, int BC, int CPL>
 static StepFn step_fn_wpb(int wpb) {
   switch (wpb) {
-    case 1: return &step_kernel<M, BC, 1>;
-    case 2: return &step_kernel<M, BC, 2>;
-    case 4: return &step_kernel<M, BC, 4>;
-    case 8: return &step_kernel<M, BC, 8>;
+    case 1: return &step_kernel<M, BC, 1, CPL>;
+    case 2: return &step_kernel<M, BC, 2, CPL>;
+    case 4: return &step_kernel<M, BC, 4, CPL>;
+    case 8: return &step_kernel<M, BC, 8, CPL>;
     default: return nullptr;
   }
 }
 
 template <class M>
-static StepFn step_fn_bc(int bc, int wpb) {
-  return bc == 0 ? step_fn_wpb<M, 0>(wpb) : step_fn_wpb<M, 1>(wpb);
+static StepFn step_fn_bc(int bc, int wpb, int cpl) {
+  if (cpl == 2) return bc == 0 ? step_fn_wpb<M, 0, 2>(wpb) : step_fn_wpb<M, 1, 2>(wpb);
+  return bc == 0 ? step_fn_wpb<M, 0, 1>(wpb) : step_fn_wpb<M, 1, 1>(wpb);
 }
 
-void* step_kernel_ptr(int model, int bc, int wpb) {
+void* step_kernel_ptr(int model, int bc, int wpb, int cpl) {
   StepFn f = nullptr;
-  if (model == 0) f = step_fn_bc<Adv>(bc, wpb);
-  else if (model == 1) f = step_fn_bc<Euler>(bc, wpb);
-  else if (model == 2) f = step_fn_bc<Spray>(bc, wpb);
+  if (model == 0) f = step_fn_bc<Adv>(bc, wpb, cpl);
+  else if (model == 1) f = step_fn_bc<Euler>(bc, wpb, cpl);
+  else if (model == 2) f = step_fn_bc<Spray>(bc, wpb, cpl);
   return reinterpret_cast<void*>(f);
 }
 
 hipError_t launch_step(const StepArgs& a, int model, hipStream_t st) {
-  void* f = step_kernel_ptr(model, a.g.bc, a.t.wpb);
+  void* f = step_kernel_ptr(model, a.g.bc, a.t.wpb, a.t.cpl);
   if (!f) return hipErrorInvalidValue;
   StepArgs copy = a;
   void* args[] = {&copy};

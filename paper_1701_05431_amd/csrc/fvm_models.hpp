@@ -25,6 +25,16 @@
 #ifndef FVM_PREFETCH_SPRAY
 #define FVM_PREFETCH_SPRAY 2
 #endif
+// ... and for the two-cells-per-lane layout
+#ifndef FVM_PREFETCH2_ADV
+#define FVM_PREFETCH2_ADV 2
+#endif
+#ifndef FVM_PREFETCH2_EULER
+#define FVM_PREFETCH2_EULER 1
+#endif
+#ifndef FVM_PREFETCH2_SPRAY
+#define FVM_PREFETCH2_SPRAY 1
+#endif
 
 namespace fvm {
 
@@ -63,12 +73,20 @@ __device__ __forceinline__ double from_prev(double x) {
 
 __device__ __forceinline__ bool finite(double x) { return __builtin_isfinite(x); }
 
+// Index of the wave inside its workgroup, as a scalar: branches on it are
+// uniform, so the strip code (and its DPP moves) runs with the whole wave
+// active.
+__device__ __forceinline__ int wave_index() {
+  return __builtin_amdgcn_readfirstlane(static_cast<int>(threadIdx.x) / kWave);
+}
+
 // ---- linear advection --------------------------------------------------------
 // u_t + a.grad u = 0; upwind flux a+ u_L + a- u_R (the Lax-Friedrichs flux of
 // a linear flux in exact arithmetic).
 struct Adv {
   static constexpr int NV = 1;
   static constexpr int kPrefetch = FVM_PREFETCH_ADV;
+  static constexpr int kPrefetch2 = FVM_PREFETCH2_ADV;
   struct Prim {};
   double ax, ay;
   __device__ explicit Adv(const ModelConsts& m) : ax(m.ax), ay(m.ay) {}
@@ -100,6 +118,7 @@ struct Adv {
 struct Euler {
   static constexpr int NV = 4;
   static constexpr int kPrefetch = FVM_PREFETCH_EULER;
+  static constexpr int kPrefetch2 = FVM_PREFETCH2_EULER;
   struct Prim { double u, v, p, c; };
   double gamma, gm1;
   __device__ explicit Euler(const ModelConsts& m) : gamma(m.gamma), gm1(m.gm1) {}
@@ -161,6 +180,7 @@ struct Euler {
 struct Spray {
   static constexpr int NV = 6;
   static constexpr int kPrefetch = FVM_PREFETCH_SPRAY;
+  static constexpr int kPrefetch2 = FVM_PREFETCH2_SPRAY;
   struct Prim { double ux, uy; };
   double K, inv_theta, s_eps, log_s_eps;
   __device__ explicit Spray(const ModelConsts& m)

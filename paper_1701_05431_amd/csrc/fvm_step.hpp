@@ -159,6 +159,148 @@ __device__ __forceinline__ void march_strip(const M& m, const double* __restrict
   }
 }
 
+// ---- one strip, two cells per lane ------------------------------------------------
+// The wide layout: lane l holds cells xs+2l and xs+2l+1, so a wave updates 128
+// consecutive cells and every load and store is an aligned 16-byte access
+// (row pitch even, buffers 16-byte aligned). The face between a lane's two
+// cells is computed in the lane, the face to the next lane's first cell with
+// DPP moves, and the two faces at the strip's ends (left of lane 0, right of
+// lane 63) from a halo cell that each lane loads (lane 0: column xs-1, lane
+// 63: column xs+128) and passes through the same flux code. EDGE strips
+// reach past the grid's last column: there every cell is addressed through
+// the boundary map (past-the-end cells hold the ghost values that their left
+// neighbour needs) and stores are masked per cell.
+typedef double dbl2 __attribute__((ext_vector_type(2)));
+
+template <int NV, int BC, bool EDGE>
+__device__ __forceinline__ void load_pair(double* a, double* b, const double* __restrict__ w,
+                                          const GridGeom& g, int ca, int cb, int r) {
+  const size_t off = static_cast<size_t>(row_index<BC>(r, g.ny)) * g.ld;
+#pragma unroll
+  for (int v = 0; v < NV; ++v) {
+    const double* p = w + v * g.plane + off;
+    if (EDGE) {
+      a[v] = p[ca];
+      b[v] = p[cb];
+    } else {
+      const dbl2 x = *reinterpret_cast<const dbl2*>(p + ca);
+      a[v] = x.x;
+      b[v] = x.y;
+    }
+  }
+}
+
+template <class M, int BC, bool EDGE>
+__device__ __forceinline__ void march_strip2(const M& m, const double* __restrict__ win,
+                                             double* __restrict__ wout,
+                                             const double* __restrict__ ug, const GridGeom& g,
+                                             int xs, int j0, int j1, double mux, double muy,
+                                             double dt, unsigned long long& bx,
+                                             unsigned long long& by) {
+  constexpr int NV = M::NV;
+  using Prim = typename M::Prim;
+  const int lane = threadIdx.x & (kWave - 1);
+  const bool first = lane == 0, last = lane == kWave - 1;
+  const int xa = xs + 2 * lane, xb = xa + 1;
+  const int ca = EDGE ? col_index<BC>(xa, g.nx) : xa;
+  const int cb = EDGE ? col_index<BC>(xb, g.nx) : xb;
+  const bool oka = !EDGE || xa < g.nx, okb = !EDGE || xb < g.nx;
+  const int ch = col_index<BC>(first ? xs - 1 : xs + 2 * kWave, g.nx);
+
+  constexpr int PF = M::kPrefetch2;
+  constexpr int R = PF + 2;
+  double A[R][NV], B[R][NV], H[R][NV], GA[R][NV], GB[R][NV];
+  Prim PA[R], PB[R];
+  load_pair<NV, BC, EDGE>(A[R - 1], B[R - 1], win, g, ca, cb, j0 - 1);
+  load_pair<NV, BC, EDGE>(A[0], B[0], win, g, ca, cb, j0);
+  load_row<NV, BC>(H[0], win + ch, g, j0);
+#pragma unroll
+  for (int p = 1; p <= PF; ++p) {
+    load_pair<NV, BC, EDGE>(A[p], B[p], win, g, ca, cb, min(j0 + p, j1));
+    load_row<NV, BC>(H[p], win + ch, g, min(j0 + p, j1 - 1));
+  }
+  m.prim(A[R - 1], PA[R - 1]);
+  m.prim(B[R - 1], PB[R - 1]);
+  m.prim(A[0], PA[0]);
+  m.prim(B[0], PB[0]);
+  m.template flux<1>(A[R - 1], PA[R - 1], A[0], PA[0], GA[0]);
+  m.template flux<1>(B[R - 1], PB[R - 1], B[0], PB[0], GB[0]);
+
+  for (int jb = j0; jb < j1; jb += R) {
+#pragma unroll
+    for (int u = 0; u < R; ++u) {
+      const int j = jb + u;
+      const int c = u, n = (u + 1) % R, l = (u + R - 1) % R;
+      load_pair<NV, BC, EDGE>(A[l], B[l], win, g, ca, cb, min(j + 1 + PF, j1));
+      load_row<NV, BC>(H[(u + PF + 1) % R], win + ch, g, min(j + 1 + PF, j1 - 1));
+      m.prim(A[n], PA[n]);
+      m.prim(B[n], PB[n]);
+      m.template flux<1>(A[c], PA[c], A[n], PA[n], GA[n]);
+      m.template flux<1>(B[c], PB[c], B[n], PB[n], GB[n]);
+      double Fab[NV], Fr[NV], Fh[NV], Wr[NV], L[NV], Rt[NV], Oa[NV], Ob[NV];
+      Prim Pr, Ph;
+      m.template flux<0>(A[c], PA[c], B[c], PB[c], Fab);
+      m.shift_next(A[c], PA[c], Wr, Pr);
+      m.template flux<0>(B[c], PB[c], Wr, Pr, Fr);
+      // the strip's end faces: lane 0 (halo | a), lane 63 (b | halo)
+      m.prim(H[c], Ph);
+#pragma unroll
+      for (int v = 0; v < NV; ++v) {
+        L[v] = first ? H[c][v] : B[c][v];
+        Rt[v] = first ? A[c][v] : H[c][v];
+      }
+      const Prim Pl = first ? Ph : PB[c];
+      const Prim Prt = first ? PA[c] : Ph;
+      m.template flux<0>(L, Pl, Rt, Prt, Fh);
+      // the cross-lane move runs with every lane active (a DPP read from a
+      // lane that is switched off yields 0), then each lane picks its face
+      double Fp[NV];
+#pragma unroll
+      for (int v = 0; v < NV; ++v) Fp[v] = from_prev(Fr[v]);
+#pragma unroll
+      for (int v = 0; v < NV; ++v) {
+        const double fw = first ? Fh[v] : Fp[v];
+        const double fe = last ? Fh[v] : Fr[v];
+        Oa[v] = A[c][v] - fma(mux, Fab[v] - fw, muy * (GA[n][v] - GA[c][v]));
+        Ob[v] = B[c][v] - fma(mux, fe - Fab[v], muy * (GB[n][v] - GB[c][v]));
+      }
+      const size_t row = static_cast<size_t>(j) * g.ld;
+      if constexpr (NV == 6) {
+        double ua[2], ub[2];
+        load_pair<2, BC, EDGE>(ua, ub, ug, g, ca, cb, j);
+        m.source(Oa, ua[0], ua[1], dt);
+        m.source(Ob, ub[0], ub[1], dt);
+      }
+      if (j < j1) {
+        if (EDGE) {
+#pragma unroll
+          for (int v = 0; v < NV; ++v) {
+            if (oka) __builtin_nontemporal_store(Oa[v], wout + v * g.plane + row + ca);
+            if (okb) __builtin_nontemporal_store(Ob[v], wout + v * g.plane + row + cb);
+          }
+        } else {
+#pragma unroll
+          for (int v = 0; v < NV; ++v) {
+            const dbl2 o = {Oa[v], Ob[v]};
+            __builtin_nontemporal_store(o, reinterpret_cast<dbl2*>(wout + v * g.plane + row + ca));
+          }
+        }
+        double sx, sy;
+        if (oka) {
+          m.speeds(Oa, sx, sy);
+          bx = umax64(bx, bits(sx));
+          by = umax64(by, bits(sy));
+        }
+        if (okb) {
+          m.speeds(Ob, sx, sy);
+          bx = umax64(bx, bits(sx));
+          by = umax64(by, bits(sy));
+        }
+      }
+    }
+  }
+}
+
 // ---- reductions and the device-side time step ------------------------------------
 
 // Adaptive dt from the maxima: dt = C / (Sx/dx + Sy/dy); dt_max if both are 0.

@@ -187,6 +187,11 @@ class Solver:
         check(lib().fvm_get_tiling(self.h, C.byref(r), C.byref(w)), "fvm_get_tiling")
         return r.value, w.value
 
+    def set_cells_per_lane(self, cpl: int = 0) -> int:
+        """Lane layout of the step kernel (0 = default); returns the one in use."""
+        check(lib().fvm_set_cells_per_lane(self.h, int(cpl)), "fvm_set_cells_per_lane")
+        return int(lib().fvm_get_cells_per_lane(self.h))
+
 
 class Batch:
     """Many independent grids packed in one buffer per ping-pong side, each

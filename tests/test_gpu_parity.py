@@ -141,16 +141,49 @@ def test_decomposition_invariance_bitwise():
     nx, ny = 250, 120
     W = inputs.riemann_state(nx, ny, 9)
     outs = []
-    for (npx, npy, rows, wpb) in [(1, 1, 64, 4), (5, 4, 1, 1), (10, 8, 7, 2), (2, 2, 120, 8),
-                                  (25, 3, 33, 4)]:
+    for (npx, npy, rows, wpb, cpl) in [(1, 1, 64, 4, 1), (5, 4, 1, 1, 1), (10, 8, 7, 2, 1),
+                                       (2, 2, 120, 8, 1), (25, 3, 33, 4, 1), (1, 1, 64, 4, 2),
+                                       (5, 4, 1, 1, 2), (10, 8, 7, 2, 2), (2, 2, 3, 8, 2)]:
         p = params_from(model=1, bc=1, nx=nx, ny=ny, npart_x=npx, npart_y=npy)
         s = Solver(p)
         s.set_tiling(rows, wpb)
+        assert s.set_cells_per_lane(cpl) == cpl
         s.set_state(W)
         s.run(7)
         outs.append(gpu_state(s))
     for o in outs[1:]:
         assert np.array_equal(o, outs[0])
+
+
+@pytest.mark.parametrize("model", [0, 1, 2])
+@pytest.mark.parametrize("bc", [0, 1])
+@pytest.mark.parametrize("nx", [1, 2, 127, 128, 129, 300, 389])
+def test_lane_layouts_agree_bitwise(model, bc, nx):
+    """One and two cells per lane, odd and even widths, strips that end
+    inside or at the end of the grid: bit-for-bit the same steps."""
+    ny = 37
+    ld = nx + (nx % 2)
+    ug = None
+    if model == 0:
+        W = inputs.advection_state(nx, ny, nx)
+        kw = dict(ax=0.6, ay=-0.8)
+    elif model == 1:
+        W = inputs.riemann_state(nx, ny, nx)
+        kw = {}
+    else:
+        W, ug = inputs.spray_state(nx, ny, nx)
+        kw = dict(cfl=0.9)
+    res = []
+    for cpl in (1, 2):
+        p = params_from(model=model, bc=bc, nx=nx, ny=ny, ld=ld, **kw)
+        s = Solver(p, ug=ug)
+        assert s.set_cells_per_lane(cpl) == cpl
+        s.set_state(W)
+        d = s.run(5, record_dt=True).cpu().numpy()
+        res.append((gpu_state(s), d))
+    assert np.array_equal(res[0][0], res[1][0]) and np.array_equal(res[0][1], res[1][1])
+    ref, odts = orc.run(oparams(params_from(model=model, bc=bc, nx=nx, ny=ny, **kw)), W, 5, ug=ug)
+    assert rel_linf(res[1][0], ref) <= TOL
 
 
 def test_pitch_padding_is_untouched():
