@@ -213,6 +213,16 @@ int fvm_get_tiling(const fvm_grid* g, int* rows_per_strip, int* waves_per_block)
 int fvm_set_cells_per_lane(fvm_grid* g, int cells_per_lane);
 int fvm_get_cells_per_lane(const fvm_grid* g);
 
+/* Autotuner: picks the tiling and lane layout of the fused step by timing
+ * dry-run steps of every candidate (dt = 0, which leaves the bound state bit
+ * for bit unchanged) on the bound buffers and stream, applies the fastest,
+ * and, if cache_path is non-NULL, appends it to that text file; a later call
+ * with the same device, model and grid shape reuses the stored choice without
+ * timing. This is the analogue of the paper's per-codelet performance models
+ * (Sec. 5.3.2): the task size that runs fastest is chosen by measurement.
+ * Synchronises the stream. */
+int fvm_autotune(fvm_grid* g, const char* cache_path);
+
 /* ---- batches of independent grids -------------------------------------- */
 
 /* Creates a plan for n independent grids solved together, one persistent
@@ -253,6 +263,11 @@ int fvm_batch_sync(fvm_batch* b);
 
 /* Tile shape of the persistent launch (rows per strip, waves per block). */
 int fvm_batch_set_tiling(fvm_batch* b, int rows_per_strip, int waves_per_block);
+
+/* Autotuner of the persistent launch's tile shape (dry runs with every dt
+ * scaled to 0, states unchanged); cache as for fvm_autotune, keyed by the
+ * device, model and the list of grid shapes. Synchronises the stream. */
+int fvm_batch_autotune(fvm_batch* b, const char* cache_path);
 
 #ifdef __cplusplus
 }

@@ -65,6 +65,7 @@ SIGNATURES = {
     "fvm_get_tiling": (C.c_int, [_V, C.POINTER(C.c_int), C.POINTER(C.c_int)]),
     "fvm_set_cells_per_lane": (C.c_int, [_V, C.c_int]),
     "fvm_get_cells_per_lane": (C.c_int, [_V]),
+    "fvm_autotune": (C.c_int, [_V, C.c_char_p]),
     "fvm_batch_create": (C.c_int, [C.c_int, _P, C.POINTER(C.c_size_t), C.POINTER(_V)]),
     "fvm_batch_destroy": (C.c_int, [_V]),
     "fvm_batch_scratch_bytes": (C.c_size_t, [_V]),
@@ -75,6 +76,7 @@ SIGNATURES = {
     "fvm_batch_current": (C.c_int, [_V, C.POINTER(_V)]),
     "fvm_batch_sync": (C.c_int, [_V]),
     "fvm_batch_set_tiling": (C.c_int, [_V, C.c_int, C.c_int]),
+    "fvm_batch_autotune": (C.c_int, [_V, C.c_char_p]),
 }
 
 _lib = None

@@ -8,8 +8,11 @@
 #include <cmath>
 #include <cstdint>
 #include <cstring>
+#include <cstdio>
+#include <fstream>
 #include <list>
 #include <new>
+#include <string>
 #include <vector>
 
 #include "../../include/fvm.h"
@@ -95,6 +98,26 @@ Tiling tiling(const GridGeom& g, int rows, int wpb, int cpl) {
   return t;
 }
 
+// Default tile shape for a grid: the widest workgroup (up to 8 strips) the
+// grid's width fills, and the tallest strips (up to 64 rows) that still give
+// about 2048 wave strips, i.e. two per SIMD on 256 CUs. On the 4096^2 Euler
+// grid this is the measured optimum (64 rows, 8 strips); smaller grids get
+// shorter strips instead of idle CUs. fvm_autotune refines it by measurement.
+void default_tiling(const fvm_params& p, int cpl, int* rows, int* wpb) {
+  // the spray step holds more registers per lane (fewer waves fit), the
+  // advection step far fewer
+  const long long target = p.model == FVM_SPRAY ? 1024 : (p.model == FVM_ADV ? 4096 : 2048);
+  const int wmax = p.model == FVM_SPRAY ? 4 : 8;
+  const int width = strip_width(cpl);
+  const long long strips_x = (p.nx + width - 1) / width;
+  int w = 1;
+  while (w < wmax && 2 * w <= strips_x) w *= 2;
+  long long r = strips_x * p.ny / target;
+  r = r < 4 ? 4 : (r > 64 ? 64 : r);
+  *rows = static_cast<int>(r);
+  *wpb = w;
+}
+
 bool valid_tiling(int rows, int wpb) {
   return rows >= 1 && rows <= 4096 && (wpb == 1 || wpb == 2 || wpb == 4 || wpb == 8);
 }
@@ -138,6 +161,7 @@ struct fvm_grid {
   GridGeom g{};
   ModelConsts m{};
   int rows = kDefaultRows, wpb = kDefaultWpb;
+  int adj_rows = kDefaultRows, adj_wpb = kDefaultWpb;  // adjoint kernel (one cell per lane)
   int cpl_req = 0;   // requested cells per lane (0: the widest the buffers allow)
   int cpl = 1;       // layout in use
   double* w_a = nullptr;
@@ -213,16 +237,8 @@ int fvm_create(const fvm_params* p, fvm_grid** out) {
   if (!g) return FVM_EINVAL;
   g->p = *p;
   g->nv = fvm_nvar(p->model);
-  // measured defaults on MI355X (two cells per lane): Euler 4096^2 is
-  // fastest with 64-row strips in 8-wave workgroups, the spray model (more
-  // registers per lane) with 32-row strips in 4-wave workgroups
-  if (p->model == FVM_EULER) {
-    g->rows = 64;
-    g->wpb = 8;
-  } else if (p->model == FVM_SPRAY) {
-    g->rows = 32;
-    g->wpb = 4;
-  }
+  default_tiling(*p, 2, &g->rows, &g->wpb);
+  default_tiling(*p, 1, &g->adj_rows, &g->adj_wpb);
   g->g = geometry(*p);
   g->m = model_consts(*p);
   *out = g;
@@ -397,7 +413,7 @@ static int graph_for(fvm_grid* g, int kind, int n, double* start, const double* 
     double* out = g->other(in);
     args[s] = g->step_args(in, out, kind == 0 ? kDtAdaptive : kDtArray);
     args[s].dts = dts;
-    args[s].k = k0 + s;
+    args[s].k = kind == 2 ? 0 : k0 + s;  // kind 2: dry run, dts = the scratch's zero
     args[s].dt_log = log;
     args[s].dt_log_cap = log_cap;
     void* kp[] = {&args[s]};
@@ -411,21 +427,21 @@ static int graph_for(fvm_grid* g, int kind, int n, double* start, const double* 
     hipGraphNode_t node;
     if (hipGraphAddKernelNode(&node, c.graph, prev ? &prev : nullptr, prev ? 1 : 0, &np) !=
         hipSuccess) {
-      hipGraphDestroy(c.graph);
+      (void)hipGraphDestroy(c.graph);
       return FVM_EDEVICE;
     }
     prev = node;
     in = out;
   }
   if (hipGraphInstantiate(&c.exec, c.graph, nullptr, nullptr, 0) != hipSuccess) {
-    hipGraphDestroy(c.graph);
+    (void)hipGraphDestroy(c.graph);
     return FVM_EDEVICE;
   }
   g->graphs.push_front(c);
   while (g->graphs.size() > kGraphCacheMax) {
     auto& b = g->graphs.back();
-    hipGraphExecDestroy(b.exec);
-    hipGraphDestroy(b.graph);
+    (void)hipGraphExecDestroy(b.exec);
+    (void)hipGraphDestroy(b.graph);
     g->graphs.pop_back();
   }
   *exec = c.exec;
@@ -514,6 +530,129 @@ int fvm_set_tiling(fvm_grid* g, int rows, int wpb) {
   return FVM_OK;
 }
 
+// ---- autotuning --------------------------------------------------------------------
+
+}  // extern "C"
+
+namespace {
+
+std::string device_arch() {
+  int dev = 0;
+  hipDeviceProp_t prop;
+  if (hipGetDevice(&dev) != hipSuccess || hipGetDeviceProperties(&prop, dev) != hipSuccess)
+    return "unknown";
+  std::string a = prop.gcnArchName;
+  const size_t colon = a.find(':');
+  return colon == std::string::npos ? a : a.substr(0, colon);
+}
+
+bool cache_lookup(const char* path, const std::string& key, int* rows, int* wpb, int* cpl) {
+  if (!path) return false;
+  std::ifstream in(path);
+  std::string line;
+  bool found = false;
+  while (std::getline(in, line)) {
+    const size_t bar = line.find(" | ");
+    if (bar == std::string::npos || line.substr(0, bar) != key) continue;
+    int r = 0, w = 0, c = 0;
+    if (std::sscanf(line.c_str() + bar + 3, "rows=%d wpb=%d cpl=%d", &r, &w, &c) == 3) {
+      *rows = r;
+      *wpb = w;
+      *cpl = c;
+      found = true;  // the last entry for a key wins
+    }
+  }
+  return found;
+}
+
+void cache_store(const char* path, const std::string& key, int rows, int wpb, int cpl,
+                 double us) {
+  if (!path) return;
+  std::ofstream out(path, std::ios::app);
+  out << key << " | rows=" << rows << " wpb=" << wpb << " cpl=" << cpl << " us=" << us << "\n";
+}
+
+}  // namespace
+
+// Times `reps` launches of an n-step dry-run graph (dt = 0) in the current
+// tiling; returns microseconds per step, or a negative value on error.
+static double time_dry(fvm_grid* g, int n, int reps) {
+  hipGraphExec_t exec;
+  if (graph_for(g, 2, n, g->cur, &g->scr->zero, 0, nullptr, 0, &exec) != FVM_OK) return -1.0;
+  hipEvent_t e0, e1;
+  if (hipEventCreate(&e0) != hipSuccess) return -1.0;
+  if (hipEventCreate(&e1) != hipSuccess) {
+    (void)hipEventDestroy(e0);
+    return -1.0;
+  }
+  double us = -1.0;
+  bool ok = hipGraphLaunch(exec, g->stream) == hipSuccess;  // warm-up
+  ok = ok && hipEventRecord(e0, g->stream) == hipSuccess;
+  for (int r = 0; r < reps && ok; ++r) ok = hipGraphLaunch(exec, g->stream) == hipSuccess;
+  ok = ok && hipEventRecord(e1, g->stream) == hipSuccess && hipEventSynchronize(e1) == hipSuccess;
+  float ms = 0.0f;
+  if (ok && hipEventElapsedTime(&ms, e0, e1) == hipSuccess) us = 1e3 * ms / (n * reps);
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  return us;
+}
+
+extern "C" {
+
+int fvm_autotune(fvm_grid* g, const char* cache_path) {
+  if (!g || !g->bound) return FVM_EINVAL;
+  char kbuf[256];
+  std::snprintf(kbuf, sizeof kbuf, "%s grid model=%d bc=%d nx=%d ny=%d ld=%d",
+                device_arch().c_str(), g->p.model, g->p.bc, g->p.nx, g->p.ny, g->p.ld);
+  const std::string key = kbuf;
+  int rows = 0, wpb = 0, cpl = 0;
+  if (cache_lookup(cache_path, key, &rows, &wpb, &cpl) && valid_tiling(rows, wpb) &&
+      (cpl == 1 || cpl == 2)) {
+    g->rows = rows;
+    g->wpb = wpb;
+    g->cpl_req = cpl;
+    g->clear_graphs();
+    choose_layout(g);
+    return FVM_OK;
+  }
+  const int cpls[2] = {2, 1};
+  const int wpbs[4] = {1, 2, 4, 8};
+  const int rowss[8] = {4, 8, 16, 32, 48, 64, 96, 128};
+  double best = 1e300;
+  int br = g->rows, bw = g->wpb, bc = g->cpl;
+  const int save_req = g->cpl_req;
+  for (int c : cpls) {
+    g->cpl_req = c;
+    choose_layout(g);
+    if (g->cpl != c) continue;  // the buffers do not allow this layout
+    for (int w : wpbs)
+      for (int r : rowss) {
+        if (r > g->p.ny && r != rowss[0]) continue;
+        g->rows = r;
+        g->wpb = w;
+        const double us = time_dry(g, 8, 2);
+        if (us < 0) {
+          g->clear_graphs();
+          return FVM_EDEVICE;
+        }
+        if (us < best) {
+          best = us;
+          br = r;
+          bw = w;
+          bc = c;
+        }
+      }
+  }
+  g->clear_graphs();
+  g->rows = br;
+  g->wpb = bw;
+  g->cpl_req = save_req ? save_req : bc;
+  choose_layout(g);
+  g->speeds_valid = true;  // the dry runs recomputed the maxima of the unchanged state
+  cache_store(cache_path, key, br, bw, bc, best);
+  return FVM_OK;
+}
+
 int fvm_set_cells_per_lane(fvm_grid* g, int cpl) {
   if (!g || cpl < 0 || cpl > 2) return FVM_EINVAL;
   g->cpl_req = cpl;
@@ -542,7 +681,7 @@ int fvm_adjoint_step(fvm_grid* g, const double* w, double dt, const double* lam_
   a.dts = nullptr;
   a.dt_arg = dt;
   a.g = g->g;
-  a.t = tiling(g->g, g->rows, g->wpb, 1);
+  a.t = tiling(g->g, g->adj_rows, g->adj_wpb, 1);
   a.m = g->m;
   return dev_err(launch_adjoint(a, g->p.model, g->stream));
 }
@@ -583,7 +722,7 @@ int fvm_adjoint_run(fvm_grid* g, double* const* ckpts, int ckpt_every, const dou
       a.dts = dts_dev;
       a.k = k;
       a.g = g->g;
-      a.t = tiling(g->g, g->rows, g->wpb, 1);
+      a.t = tiling(g->g, g->adj_rows, g->adj_wpb, 1);
       a.m = g->m;
       int rc = dev_err(launch_adjoint(a, g->p.model, g->stream));
       if (rc) return rc;

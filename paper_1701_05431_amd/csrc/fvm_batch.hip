@@ -19,6 +19,9 @@
 #include <list>
 #include <new>
 #include <numeric>
+#include <cstdio>
+#include <fstream>
+#include <string>
 #include <vector>
 
 #include "../../include/fvm.h"
@@ -66,7 +69,7 @@ __global__ FVM_STEP_BOUNDS(WPB) void batch_kernel(BatchArgs a) {
     }
     const BatchGrid G = a.grids[lo];
     GridScratch* s = a.gscr + lo;
-    const double dt = s->dt;
+    const double dt = s->dt * a.dt_scale;
     const double mux = dt / G.g.dx, muy = dt / G.g.dy;
     const int tile = item - G.item0;
     const int tx = tile % G.tiles_x, ty = tile / G.tiles_x;
@@ -387,7 +390,7 @@ static int batch_graph(fvm_batch* b, int kind, int nsteps, double* log, int log_
   bool ok = true;
   for (int s = 0; s < nsteps && ok; ++s) {
     double* out = b->other(in);
-    if (kind == 0) {
+    if (kind != 1) {  // 0: persistent launch; 2: its dry run (dt scaled to 0)
       BatchArgs a{};
       a.win = in;
       a.wout = out;
@@ -399,6 +402,7 @@ static int batch_graph(fvm_batch* b, int kind, int nsteps, double* log, int log_
       a.ngrids = b->n;
       a.nitems = b->nitems;
       a.rows = b->rows;
+      a.dt_scale = kind == 2 ? 0.0 : 1.0;
       a.m = b->m;
       ok = add(batch_kernel_ptr(b->model, b->bc, b->wpb, b->cpl),
                dim3(std::min(b->nblocks, b->nitems)),
@@ -430,14 +434,14 @@ static int batch_graph(fvm_batch* b, int kind, int nsteps, double* log, int log_
     in = out;
   }
   if (!ok || hipGraphInstantiate(&c.exec, c.graph, nullptr, nullptr, 0) != hipSuccess) {
-    hipGraphDestroy(c.graph);
+    (void)hipGraphDestroy(c.graph);
     return FVM_EDEVICE;
   }
   b->graphs.push_front(c);
   while (b->graphs.size() > 8) {
     auto& x = b->graphs.back();
-    hipGraphExecDestroy(x.exec);
-    hipGraphDestroy(x.graph);
+    (void)hipGraphExecDestroy(x.exec);
+    (void)hipGraphDestroy(x.graph);
     b->graphs.pop_back();
   }
   *exec = c.exec;
@@ -480,6 +484,88 @@ int fvm_batch_current(const fvm_batch* b, double** w) {
   if (!b || !w || !b->bound) return FVM_EINVAL;
   *w = b->cur;
   return FVM_OK;
+}
+
+// Chooses the batch tiling by timing dry persistent launches (dt scaled to 0,
+// states unchanged) of every candidate; see fvm_autotune.
+int fvm_batch_autotune(fvm_batch* b, const char* cache_path) {
+  if (!b || !b->bound) return FVM_EINVAL;
+  unsigned long long h = 1469598103934665603ull;  // FNV-1a over the grid shapes
+  for (const auto& p : b->p)
+    for (int x : {p.nx, p.ny, p.ld}) {
+      h ^= static_cast<unsigned long long>(x);
+      h *= 1099511628211ull;
+    }
+  int dev = 0;
+  hipDeviceProp_t prop;
+  std::string arch = "unknown";
+  if (hipGetDevice(&dev) == hipSuccess && hipGetDeviceProperties(&prop, dev) == hipSuccess) {
+    arch = prop.gcnArchName;
+    arch = arch.substr(0, arch.find(':'));
+  }
+  char kbuf[256];
+  std::snprintf(kbuf, sizeof kbuf, "%s batch model=%d bc=%d n=%d shapes=%016llx", arch.c_str(),
+                b->model, b->bc, b->n, h);
+  const std::string key = kbuf;
+  if (cache_path) {
+    std::ifstream in(cache_path);
+    std::string line;
+    int r = 0, w = 0, found = 0;
+    while (std::getline(in, line)) {
+      const size_t bar = line.find(" | ");
+      if (bar == std::string::npos || line.substr(0, bar) != key) continue;
+      if (std::sscanf(line.c_str() + bar + 3, "rows=%d wpb=%d", &r, &w) == 2) found = 1;
+    }
+    if (found) return fvm_batch_set_tiling(b, r, w);
+  }
+  if (!b->speeds_valid) {
+    const int rc = fvm_batch_cfl(b);
+    if (rc) return rc;
+  }
+  hipEvent_t e0, e1;
+  if (hipEventCreate(&e0) != hipSuccess) return FVM_EDEVICE;
+  if (hipEventCreate(&e1) != hipSuccess) {
+    (void)hipEventDestroy(e0);
+    return FVM_EDEVICE;
+  }
+  double best = 1e300;
+  int br = b->rows, bw = b->wpb;
+  int rc = FVM_OK;
+  for (int w : {1, 2, 4, 8}) {
+    for (int r : {8, 16, 32, 48, 64, 96}) {
+      rc = fvm_batch_set_tiling(b, r, w);
+      if (rc) break;
+      hipGraphExec_t exec;
+      const int n = 4;
+      rc = batch_graph(b, 2, n, nullptr, 0, &exec);
+      if (rc) break;
+      bool ok = hipGraphLaunch(exec, b->stream) == hipSuccess;
+      ok = ok && hipEventRecord(e0, b->stream) == hipSuccess;
+      for (int k = 0; k < 2 && ok; ++k) ok = hipGraphLaunch(exec, b->stream) == hipSuccess;
+      ok = ok && hipEventRecord(e1, b->stream) == hipSuccess && hipEventSynchronize(e1) == hipSuccess;
+      float ms = 0.0f;
+      if (!ok || hipEventElapsedTime(&ms, e0, e1) != hipSuccess) {
+        rc = FVM_EDEVICE;
+        break;
+      }
+      const double us = 1e3 * ms / (2 * n);
+      if (us < best) {
+        best = us;
+        br = r;
+        bw = w;
+      }
+    }
+    if (rc) break;
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (rc) return rc;
+  rc = fvm_batch_set_tiling(b, br, bw);
+  if (rc == FVM_OK && cache_path) {
+    std::ofstream out(cache_path, std::ios::app);
+    out << key << " | rows=" << br << " wpb=" << bw << " us=" << best << "\n";
+  }
+  return rc;
 }
 
 int fvm_batch_sync(fvm_batch* b) {

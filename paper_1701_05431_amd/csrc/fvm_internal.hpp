@@ -35,7 +35,8 @@ struct alignas(256) GridScratch {
   unsigned int pad0;
   double dt;                   // dt of the next adaptive step
   double cur_sx, cur_sy;       // finalized maxima of the current state
-  double pad1[2];
+  double zero;                 // always 0: the dt of the tuner's dry-run steps
+  double pad1;
 };
 static_assert(sizeof(GridScratch) == 256, "scratch layout");
 
@@ -138,6 +139,7 @@ struct BatchArgs {
   int ngrids;                 // records sorted by item0 (largest grids first)
   int nitems;
   int rows;
+  double dt_scale;            // 1; 0 for the tuner's dry runs (state unchanged)
   ModelConsts m;
 };
 

@@ -73,6 +73,43 @@ __device__ __forceinline__ double from_prev(double x) {
 
 __device__ __forceinline__ bool finite(double x) { return __builtin_isfinite(x); }
 
+// Reciprocal and square root of the per-cell primitives. By default the
+// compiler's correctly rounded sequences; with FVM_FAST_DIVSQRT the hardware
+// estimates refined by Newton steps (reciprocal) and one Goldschmidt step
+// pair plus a residual correction (square root), within an ulp of the exact
+// result for the normal-range arguments the models produce, in about half
+// the instructions. Zero, negative and non-finite arguments give the same
+// classification as the exact forms (0 -> 0 for the root, NaN propagates).
+#ifndef FVM_FAST_DIVSQRT
+#define FVM_FAST_DIVSQRT 1
+#endif
+__device__ __forceinline__ double recip(double x) {
+#if FVM_FAST_DIVSQRT
+  double r = __builtin_amdgcn_rcp(x);
+  double e = fma(-x, r, 1.0);
+  r = fma(r, e, r);
+  e = fma(-x, r, 1.0);
+  return fma(r, e, r);
+#else
+  return 1.0 / x;
+#endif
+}
+__device__ __forceinline__ double root(double x) {
+#if FVM_FAST_DIVSQRT
+  const double y = __builtin_amdgcn_rsq(x);
+  double g = x * y;
+  double h = 0.5 * y;
+  const double r = fma(-h, g, 0.5);
+  g = fma(g, r, g);
+  h = fma(h, r, h);
+  const double d = fma(-g, g, x);
+  g = fma(d, h, g);
+  return x == 0.0 ? x : g;
+#else
+  return sqrt(x);
+#endif
+}
+
 // Index of the wave inside its workgroup, as a scalar: branches on it are
 // uniform, so the strip code (and its DPP moves) runs with the whole wave
 // active.
@@ -123,11 +160,11 @@ struct Euler {
   double gamma, gm1;
   __device__ explicit Euler(const ModelConsts& m) : gamma(m.gamma), gm1(m.gm1) {}
   __device__ __forceinline__ void prim(const double* w, Prim& q) const {
-    const double r = 1.0 / w[0];
+    const double r = recip(w[0]);
     q.u = w[1] * r;
     q.v = w[2] * r;
     q.p = gm1 * fma(-0.5, fma(w[1], q.u, w[2] * q.v), w[3]);
-    q.c = sqrt(gamma * q.p * r);
+    q.c = root(gamma * q.p * r);
   }
   template <int D>
   __device__ __forceinline__ void flux(const double* wl, const Prim& pl, const double* wr,
@@ -160,14 +197,12 @@ struct Euler {
     qr.v = 0.0;  // the x-flux does not use v
   }
   __device__ __forceinline__ void speeds(const double* w, double& sx, double& sy) const {
-    const double r = 1.0 / w[0];
-    const double u = w[1] * r, v = w[2] * r;
-    const double p = gm1 * fma(-0.5, fma(w[1], u, w[2] * v), w[3]);
-    const double c = sqrt(gamma * p * r);
-    const bool ok = finite(w[0]) & finite(w[1]) & finite(w[2]) & finite(w[3]) &
-                    (w[0] > 0.0) & (p >= 0.0);
-    sx = ok ? fabs(u) + c : __builtin_nan("");
-    sy = ok ? fabs(v) + c : __builtin_nan("");
+    Prim q;
+    prim(w, q);
+    const bool ok = finite(w[0]) && finite(w[1]) && finite(w[2]) && finite(w[3]) &&
+                    (w[0] > 0.0) && (q.p >= 0.0);
+    sx = ok ? fabs(q.u) + q.c : __builtin_nan("");
+    sy = ok ? fabs(q.v) + q.c : __builtin_nan("");
   }
 };
 

@@ -192,6 +192,15 @@ class Solver:
         check(lib().fvm_set_cells_per_lane(self.h, int(cpl)), "fvm_set_cells_per_lane")
         return int(lib().fvm_get_cells_per_lane(self.h))
 
+    def autotune(self, cache_path: str | None = None):
+        """Times dry-run steps of every tiling and lane layout on this grid,
+        applies the fastest (optionally cached in a text file); returns
+        (rows, waves_per_block, cells_per_lane)."""
+        self._bind_stream()
+        path = cache_path.encode() if cache_path else None
+        check(lib().fvm_autotune(self.h, path), "fvm_autotune")
+        return self.tiling() + (int(lib().fvm_get_cells_per_lane(self.h)),)
+
 
 class Batch:
     """Many independent grids packed in one buffer per ping-pong side, each
@@ -268,6 +277,11 @@ class Batch:
     def set_tiling(self, rows: int = 0, waves_per_block: int = 0) -> None:
         check(lib().fvm_batch_set_tiling(self.h, int(rows), int(waves_per_block)),
               "fvm_batch_set_tiling")
+
+    def autotune(self, cache_path: str | None = None) -> None:
+        """Picks the persistent launch's tile shape by timing dry runs."""
+        path = cache_path.encode() if cache_path else None
+        check(lib().fvm_batch_autotune(self.h, path), "fvm_batch_autotune")
 
     def sync(self) -> int:
         return int(lib().fvm_batch_sync(self.h))
