@@ -79,9 +79,15 @@ __global__ FVM_STEP_BOUNDS(WPB) void batch_kernel(BatchArgs a) {
     const int j1 = min(j0 + a.rows, G.g.ny);
     unsigned long long bx = 0, by = 0;
     if (xs < G.g.nx) {
-      if (CPL == 1)
+      if (CPL == 1 && FVM_LEGACY_STRIP)
         march_strip<M, BC>(m, a.win + G.offset, a.wout + G.offset, nullptr, G.g, xs, j0, j1, mux,
                            muy, dt, bx, by);
+      else if (CPL == 1 && xs + kWave <= G.g.nx)
+        march_strip1<M, BC, false>(m, a.win + G.offset, a.wout + G.offset, nullptr, G.g, xs, j0,
+                                   j1, mux, muy, dt, bx, by);
+      else if (CPL == 1)
+        march_strip1<M, BC, true>(m, a.win + G.offset, a.wout + G.offset, nullptr, G.g, xs, j0,
+                                  j1, mux, muy, dt, bx, by);
       else if (xs + 2 * kWave <= G.g.nx)
         march_strip2<M, BC, false>(m, a.win + G.offset, a.wout + G.offset, nullptr, G.g, xs, j0,
                                    j1, mux, muy, dt, bx, by);

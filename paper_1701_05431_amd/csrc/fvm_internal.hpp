@@ -57,9 +57,15 @@ struct GridGeom {
   double hmin;                // min(dx, dy) for the fixed-dt check
 };
 
-// Cells a wave strip updates: 62 with one cell per lane (lanes 0 and 63 are
-// the halo), 128 with two cells per lane.
-__host__ __device__ constexpr int strip_width(int cpl) { return cpl == 2 ? 2 * kWave : kOutPerWave; }
+// Cells a wave strip updates: 64 with one cell per lane, 128 with two.
+// (FVM_LEGACY_STRIP selects the older one-cell strip whose lanes 0 and 63
+// are the halo: 62 cells.)
+#ifndef FVM_LEGACY_STRIP
+#define FVM_LEGACY_STRIP 0
+#endif
+__host__ __device__ constexpr int strip_width(int cpl) {
+  return cpl == 2 ? 2 * kWave : (FVM_LEGACY_STRIP ? kOutPerWave : kWave);
+}
 
 // Tile decomposition of one grid for a launch.
 struct Tiling {

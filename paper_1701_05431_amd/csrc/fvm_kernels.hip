@@ -45,7 +45,12 @@ __device__ __forceinline__ void strip(const M& m, const double* __restrict__ win
                                       unsigned long long& by) {
   if (xs >= g.nx) return;
   if (CPL == 1) {
-    march_strip<M, BC>(m, win, wout, ug, g, xs, j0, j1, mux, muy, dt, bx, by);
+    if (FVM_LEGACY_STRIP)
+      march_strip<M, BC>(m, win, wout, ug, g, xs, j0, j1, mux, muy, dt, bx, by);
+    else if (xs + kWave <= g.nx)
+      march_strip1<M, BC, false>(m, win, wout, ug, g, xs, j0, j1, mux, muy, dt, bx, by);
+    else
+      march_strip1<M, BC, true>(m, win, wout, ug, g, xs, j0, j1, mux, muy, dt, bx, by);
   } else if (xs + 2 * kWave <= g.nx) {
     march_strip2<M, BC, false>(m, win, wout, ug, g, xs, j0, j1, mux, muy, dt, bx, by);
   } else {

@@ -35,6 +35,16 @@
 #ifndef FVM_PREFETCH2_SPRAY
 #define FVM_PREFETCH2_SPRAY 1
 #endif
+// ... and for the aligned one-cell-per-lane layout
+#ifndef FVM_PREFETCH1_ADV
+#define FVM_PREFETCH1_ADV 2
+#endif
+#ifndef FVM_PREFETCH1_EULER
+#define FVM_PREFETCH1_EULER 1
+#endif
+#ifndef FVM_PREFETCH1_SPRAY
+#define FVM_PREFETCH1_SPRAY 1
+#endif
 
 namespace fvm {
 
@@ -124,6 +134,7 @@ struct Adv {
   static constexpr int NV = 1;
   static constexpr int kPrefetch = FVM_PREFETCH_ADV;
   static constexpr int kPrefetch2 = FVM_PREFETCH2_ADV;
+  static constexpr int kPrefetch1 = FVM_PREFETCH1_ADV;
   struct Prim {};
   double ax, ay;
   __device__ explicit Adv(const ModelConsts& m) : ax(m.ax), ay(m.ay) {}
@@ -156,6 +167,7 @@ struct Euler {
   static constexpr int NV = 4;
   static constexpr int kPrefetch = FVM_PREFETCH_EULER;
   static constexpr int kPrefetch2 = FVM_PREFETCH2_EULER;
+  static constexpr int kPrefetch1 = FVM_PREFETCH1_EULER;
   struct Prim { double u, v, p, c; };
   double gamma, gm1;
   __device__ explicit Euler(const ModelConsts& m) : gamma(m.gamma), gm1(m.gm1) {}
@@ -216,6 +228,7 @@ struct Spray {
   static constexpr int NV = 6;
   static constexpr int kPrefetch = FVM_PREFETCH_SPRAY;
   static constexpr int kPrefetch2 = FVM_PREFETCH2_SPRAY;
+  static constexpr int kPrefetch1 = FVM_PREFETCH1_SPRAY;
   struct Prim { double ux, uy; };
   double K, inv_theta, s_eps, log_s_eps;
   __device__ explicit Spray(const ModelConsts& m)

@@ -159,6 +159,95 @@ __device__ __forceinline__ void march_strip(const M& m, const double* __restrict
   }
 }
 
+// ---- one strip, one cell per lane, aligned -------------------------------------------
+// Lane l holds cell xs+l: a wave updates 64 consecutive cells (one aligned
+// 512-byte segment per plane and row). The left face of lane 0 and the right
+// face of lane 63 come from a halo cell (lane 0: column xs-1, lane 63: column
+// xs+64) passed through the same flux code, as in the two-cells layout; the
+// other x-faces use DPP moves. EDGE strips reach past the grid's last column
+// (addresses through the boundary map, stores masked).
+template <class M, int BC, bool EDGE>
+__device__ __forceinline__ void march_strip1(const M& m, const double* __restrict__ win,
+                                             double* __restrict__ wout,
+                                             const double* __restrict__ ug, const GridGeom& g,
+                                             int xs, int j0, int j1, double mux, double muy,
+                                             double dt, unsigned long long& bx,
+                                             unsigned long long& by) {
+  constexpr int NV = M::NV;
+  using Prim = typename M::Prim;
+  const int lane = threadIdx.x & (kWave - 1);
+  const bool first = lane == 0, last = lane == kWave - 1;
+  const int x = xs + lane;
+  const int cx = EDGE ? col_index<BC>(x, g.nx) : x;
+  const bool ok = !EDGE || x < g.nx;
+  const int ch = col_index<BC>(first ? xs - 1 : xs + kWave, g.nx);
+  const double* base = win + cx;
+
+  constexpr int PF = M::kPrefetch1;
+  constexpr int R = PF + 2;
+  double W[R][NV], H[R][NV], G[R][NV];
+  Prim P[R];
+  load_row<NV, BC>(W[R - 1], base, g, j0 - 1);
+  load_row<NV, BC>(W[0], base, g, j0);
+  load_row<NV, BC>(H[0], win + ch, g, j0);
+#pragma unroll
+  for (int p = 1; p <= PF; ++p) {
+    load_row<NV, BC>(W[p], base, g, min(j0 + p, j1));
+    load_row<NV, BC>(H[p], win + ch, g, min(j0 + p, j1 - 1));
+  }
+  m.prim(W[R - 1], P[R - 1]);
+  m.prim(W[0], P[0]);
+  m.template flux<1>(W[R - 1], P[R - 1], W[0], P[0], G[0]);
+
+  for (int jb = j0; jb < j1; jb += R) {
+#pragma unroll
+    for (int u = 0; u < R; ++u) {
+      const int j = jb + u;
+      const int c = u, n = (u + 1) % R, l = (u + R - 1) % R;
+      load_row<NV, BC>(W[l], base, g, min(j + 1 + PF, j1));
+      load_row<NV, BC>(H[l], win + ch, g, min(j + 1 + PF, j1 - 1));
+      m.prim(W[n], P[n]);
+      m.template flux<1>(W[c], P[c], W[n], P[n], G[n]);
+      double Fr[NV], Fh[NV], Wr[NV], L[NV], Rt[NV], Fp[NV], Wo[NV];
+      Prim Pr, Ph;
+      m.shift_next(W[c], P[c], Wr, Pr);
+      m.template flux<0>(W[c], P[c], Wr, Pr, Fr);
+      m.prim(H[c], Ph);
+#pragma unroll
+      for (int v = 0; v < NV; ++v) {
+        L[v] = first ? H[c][v] : W[c][v];
+        Rt[v] = first ? W[c][v] : H[c][v];
+      }
+      const Prim Pl = first ? Ph : P[c];
+      const Prim Prt = first ? P[c] : Ph;
+      m.template flux<0>(L, Pl, Rt, Prt, Fh);
+      // the cross-lane move runs with every lane active, then each lane
+      // picks its faces
+#pragma unroll
+      for (int v = 0; v < NV; ++v) Fp[v] = from_prev(Fr[v]);
+#pragma unroll
+      for (int v = 0; v < NV; ++v) {
+        const double fw = first ? Fh[v] : Fp[v];
+        const double fe = last ? Fh[v] : Fr[v];
+        Wo[v] = W[c][v] - fma(mux, fe - fw, muy * (G[n][v] - G[c][v]));
+      }
+      const size_t cell = static_cast<size_t>(j) * g.ld + cx;
+      if constexpr (NV == 6) {
+        m.source(Wo, ug[cell], ug[g.plane + cell], dt);
+      }
+      if (ok && j < j1) {
+#pragma unroll
+        for (int v = 0; v < NV; ++v)
+          __builtin_nontemporal_store(Wo[v], wout + v * g.plane + cell);
+        double sx, sy;
+        m.speeds(Wo, sx, sy);
+        bx = umax64(bx, bits(sx));
+        by = umax64(by, bits(sy));
+      }
+    }
+  }
+}
+
 // ---- one strip, two cells per lane ------------------------------------------------
 // The wide layout: lane l holds cells xs+2l and xs+2l+1, so a wave updates 128
 // consecutive cells and every load and store is an aligned 16-byte access
