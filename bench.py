@@ -30,6 +30,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+LAYOUTS = {"planes": 0, "rows": 1}  # FVM_LAYOUT_PLANES, FVM_LAYOUT_ROWS
 METRIC = ("Gcell-updates/s and % HBM roofline (FP64); batched vs per-grid; "
           "adjoint/forward cost")
 KERNEL_SOURCES = ["fvm_kernels.hip", "fvm_step.hpp", "fvm_models.hpp", "fvm_internal.hpp"]
@@ -68,7 +69,7 @@ def bench_euler(args):
     from paper_1701_05431_amd import inputs
     from paper_1701_05431_amd.solver import Solver, params_from
     pre = inputs.EULER_4096
-    p = params_from(pre)
+    p = params_from(pre, layout=LAYOUTS[args.layout])
     s = Solver(p)
     W = inputs.riemann_state(pre.nx, pre.ny, 0)
     s.set_state(torch.from_numpy(W))
@@ -86,18 +87,18 @@ def bench_euler(args):
     per_launch = sec / args.steps
     achieved = 64.0 * cells / per_launch / 1e9
     return dict(sec=sec, cells=cells, per_launch=per_launch, achieved=achieved,
-                tiling=s.tiling(), solver=s)
+                tiling=s.tiling(), cpl=s.cells_per_lane(), solver=s)
 
 
-def bench_spray(steps, warmup, autotune=True):
+def bench_spray(steps, warmup, autotune=True, layout="rows"):
     import torch
     from paper_1701_05431_amd import inputs
     from paper_1701_05431_amd.solver import Solver, params_from
     pre = inputs.SPRAY_2048
     W, ug = inputs.spray_state(pre.nx, pre.ny, 0)
-    s = Solver(params_from(pre), ug=ug)
+    s = Solver(params_from(pre, layout=LAYOUTS[layout]), ug=ug)
     s.set_state(torch.from_numpy(W))
-    tiling = s.autotune() if autotune else s.tiling() + (s.set_cells_per_lane(0),)
+    tiling = s.autotune() if autotune else s.tiling() + (s.cells_per_lane(),)
     s.run(warmup)
     sec = timed(lambda: s.run(steps))
     st = s.sync()
@@ -111,12 +112,12 @@ def bench_spray(steps, warmup, autotune=True):
                        "cells_per_lane": tiling[2]}}
 
 
-def bench_batch(steps, warmup):
+def bench_batch(steps, warmup, layout="rows"):
     import torch
     from paper_1701_05431_amd import inputs
     from paper_1701_05431_amd.solver import Batch, params_from
     sizes = inputs.batch_sizes(inputs.BATCH_COUNT, 0)
-    plist = [params_from(inputs.BATCH_256, nx=n, ny=n) for n in sizes]
+    plist = [params_from(inputs.BATCH_256, nx=n, ny=n, layout=LAYOUTS[layout]) for n in sizes]
     states = [inputs.riemann_state(n, n, k) for k, n in enumerate(sizes)]
     cells = sum(n * n for n in sizes)
     out = {"workload": inputs.BATCH_256.name, "grids": len(sizes), "cells": cells,
@@ -151,7 +152,7 @@ def bench_batch(steps, warmup):
     return out
 
 
-def bench_adjoint(reps):
+def bench_adjoint(reps, layout="rows"):
     import torch
     from paper_1701_05431_amd import inputs
     from paper_1701_05431_amd.solver import Solver, params_from
@@ -159,7 +160,7 @@ def bench_adjoint(reps):
     every = inputs.ADJOINT_CKPT_EVERY
     W = inputs.riemann_state(pre.nx, pre.ny, 0)
     tgt = torch.from_numpy(inputs.adjoint_target_density(pre.nx, pre.ny, 0)).cuda()
-    s = Solver(params_from(pre))
+    s = Solver(params_from(pre, layout=LAYOUTS[layout]))
     Wt = torch.from_numpy(W).cuda()
     s.set_state(Wt)
     s.autotune()
@@ -171,8 +172,8 @@ def bench_adjoint(reps):
 
     def bwd():
         cur = s.current()[:, :, :pre.nx]
-        lam = torch.zeros_like(s.current())
-        lam[0, :, :pre.nx] = cur[0] - tgt
+        lam = torch.zeros((s.nv, pre.ny, pre.nx), dtype=torch.float64, device="cuda")
+        lam[0] = cur[0] - tgt
         holder["g"] = s.adjoint(holder["ck"], every, holder["dts"], lam)
 
     fwd()
@@ -260,6 +261,9 @@ def main():
     ap.add_argument("--only", choices=["spray", "batch", "adjoint", "advection"],
                     help="run just this secondary workload (for profiling) and print its record")
     ap.add_argument("--no-autotune", action="store_true")
+    ap.add_argument("--layout", choices=sorted(LAYOUTS), default="rows",
+                    help="state storage: one plane per variable, or the variables' rows "
+                         "interleaved per grid row")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-probe", type=int, default=0, help="bytes of a plain D2D copy")
     args = ap.parse_args()
@@ -274,9 +278,10 @@ def main():
         copy_probe(args.copy_probe, 10)
         return
     if args.only:
-        run = {"spray": lambda: bench_spray(args.steps, args.warmup, not args.no_autotune),
-               "batch": lambda: bench_batch(args.steps, args.warmup),
-               "adjoint": lambda: bench_adjoint(1),
+        run = {"spray": lambda: bench_spray(args.steps, args.warmup, not args.no_autotune,
+                                            args.layout),
+               "batch": lambda: bench_batch(args.steps, args.warmup, args.layout),
+               "adjoint": lambda: bench_adjoint(1, args.layout),
                "advection": lambda: bench_advection(args.steps)}[args.only]
         print(json.dumps(run()), flush=True)
         return
@@ -293,11 +298,11 @@ def main():
     work = {}
     if not args.only_euler:
         log("spray")
-        work["spray"] = bench_spray(200, 10)
+        work["spray"] = bench_spray(200, 10, layout=args.layout)
         log("batch")
-        work["batch"] = bench_batch(100, 4)
+        work["batch"] = bench_batch(100, 4, args.layout)
         log("adjoint")
-        work["adjoint"] = bench_adjoint(3)
+        work["adjoint"] = bench_adjoint(3, args.layout)
         log("advection")
         work["advection"] = bench_advection(100)
     cpu = None
@@ -319,8 +324,9 @@ def main():
         "data": "synthetic",
         "config": {"workload": "euler_4096x4096", "nx": 4096, "ny": 4096, "nvar": 4,
                    "flux": "rusanov", "bc": "transmissive", "cfl": 0.45, "subdomains": "8x8",
-                   "init": "four-quadrant Riemann, seed 0",
-                   "tiling": {"rows_per_strip": e["tiling"][0], "waves_per_block": e["tiling"][1]}},
+                   "init": "four-quadrant Riemann, seed 0", "layout": args.layout,
+                   "tiling": {"rows_per_strip": e["tiling"][0], "waves_per_block": e["tiling"][1],
+                              "cells_per_lane": e["cpl"]}},
         "roofline": roof,
         "cpu_baseline": cpu,
         "workloads": work,

@@ -18,9 +18,16 @@
  *
  * Conventions common to every call
  * --------------------------------
- *  - States are FP64 structure-of-arrays in device memory: variable v of cell
- *    (i, j) is at w[(v * ny + j) * ld + i], 0 <= i < nx, 0 <= j < ny, with a
- *    row pitch ld >= nx (elements). Cell centres are ((i+1/2)dx, (j+1/2)dy),
+ *  - States are FP64 in device memory, one contiguous row of nx values (row
+ *    pitch ld >= nx elements) per variable and grid row, 0 <= i < nx,
+ *    0 <= j < ny, in one of two layouts (fvm_params.layout):
+ *      FVM_LAYOUT_PLANES: variable v of cell (i, j) at w[(v * ny + j) * ld + i]
+ *                         (one plane per variable);
+ *      FVM_LAYOUT_ROWS:   at w[(j * nVar + v) * ld + i] (the nVar rows of a
+ *                         grid row are adjacent in memory).
+ *    Both hold nVar * ny * ld doubles and give bitwise the same results; the
+ *    row layout streams faster on HBM3E (fewer far-apart streams per strip).
+ *    Cell centres are ((i+1/2)dx, (j+1/2)dy),
  *    dx = lx/nx, dy = ly/ny. nVar is 1 (advection), 4 (Euler: rho, rho u,
  *    rho v, rho E) or 6 (spray: m_0, m_{1/2}, m_{2/2}, m_{3/2}, q_x, q_y).
  *  - The caller owns all device memory (state buffers, the spray gas
@@ -62,6 +69,9 @@ extern "C" {
 #define FVM_PERIODIC 0     /* the domain wraps around (Sec. 5)                */
 #define FVM_TRANSMISSIVE 1 /* ghost cell = boundary cell (zero gradient)      */
 
+#define FVM_LAYOUT_PLANES 0 /* w[(v * ny + j) * ld + i]                       */
+#define FVM_LAYOUT_ROWS 1   /* w[(j * nVar + v) * ld + i]; nVar * ld <= 2^31-1 */
+
 typedef struct fvm_params {
   int model;     /* FVM_ADV, FVM_EULER or FVM_SPRAY                          */
   int bc;        /* FVM_PERIODIC or FVM_TRANSMISSIVE                         */
@@ -69,7 +79,7 @@ typedef struct fvm_params {
   int npart_x;   /* NPartX: balanced subdomains along x, nx % npart_x == 0   */
   int npart_y;   /* NPartY (Sec. 3.2); the result does not depend on them    */
   int ld;        /* row pitch in elements, >= nx                             */
-  int reserved;  /* must be 0                                                */
+  int layout;    /* FVM_LAYOUT_PLANES or FVM_LAYOUT_ROWS                     */
   double lx, ly; /* domain lengths (> 0); dx = lx/nx, dy = ly/ny             */
   double gamma;  /* Euler: ratio of specific heats (> 1)                     */
   double ax, ay; /* advection velocity                                       */
@@ -109,8 +119,9 @@ int fvm_destroy(fvm_grid* g);
 /* Binds caller-owned device memory and a stream to the plan:
  *   w_a, w_b : two state buffers of nVar * ny * ld doubles each (ping-pong);
  *              w_a holds the current state after binding;
- *   ug       : spray only, the gas velocity (u_gx, u_gy) as 2 planes with the
- *              same pitch, read-only; NULL for other models;
+ *   ug       : spray only, the gas velocity (u_gx, u_gy) as a 2-variable
+ *              field with the state's ld and layout (2 * ny * ld doubles),
+ *              read-only; NULL for other models;
  *   scratch  : fvm_scratch_bytes(p) bytes, 256-byte aligned;
  *   stream   : hipStream_t (void*), NULL = null stream.
  * Enqueues a kernel that clears the scratch (speeds unknown, status 0). */
@@ -123,13 +134,14 @@ int fvm_set_stream(fvm_grid* g, void* stream);
 /* Device pointer of the buffer that holds the current state. */
 int fvm_current(const fvm_grid* g, double** w);
 
-/* Copies a state (pitch ld) into the current buffer; src is a host pointer
- * if src_on_device == 0 (the call then waits for the copy), else a device
- * pointer (asynchronous). Marks the speed maxima as unknown. */
+/* Copies a state (the grid's ld and layout) into the current buffer; src
+ * is a host pointer if src_on_device == 0 (the call then waits for the
+ * copy), else a device pointer (asynchronous). Marks the speed maxima as
+ * unknown. */
 int fvm_set_state(fvm_grid* g, const double* src, int src_on_device);
 
-/* Copies the current state (pitch ld) to dst; a host destination makes the
- * call wait. */
+/* Copies the current state (ld and layout kept) to dst; a host destination
+ * makes the call wait. */
 int fvm_get_state(fvm_grid* g, double* dst, int dst_on_device);
 
 /* Speed maxima of the current state (checkTimeStep, Sec. 4.2) and the
@@ -160,8 +172,8 @@ int fvm_run(fvm_grid* g, int nsteps, double* dts_dev);
 int fvm_run_dts(fvm_grid* g, int nsteps, const double* dts_dev);
 
 /* As fvm_run, and stores checkpoints: ckpts[s] (host array of device
- * pointers, ceil(nsteps / ckpt_every) of them, each a full state with pitch
- * ld) receives W^{s * ckpt_every}. The step that produces a checkpointed
+ * pointers, ceil(nsteps / ckpt_every) of them, each a full state in the grid's
+ * ld and layout) receives W^{s * ckpt_every}. The step that produces a checkpointed
  * state writes it straight into the checkpoint buffer. */
 int fvm_run_ckpt(fvm_grid* g, int nsteps, int ckpt_every,
                  double* const* ckpts, double* dts_dev);
@@ -179,7 +191,7 @@ int fvm_get_status(fvm_grid* g, int clear);
  *                             + J_R(i-1/2)^T (lam_i - lam_{i-1})] + (same in y)
  * with J_L, J_R the Jacobians of the numerical flux with respect to its left
  * and right states (derived from Sec. 2.2.1; max() follows its left argument
- * on ties). Inputs (all device memory, pitch ld):
+ * on ties). Inputs (all device memory, the grid's ld and layout):
  *   ckpts[s]   : host array of device pointers, W^{s * ckpt_every}, as
  *                written by fvm_run_ckpt;
  *   dts_dev    : the nsteps forward time steps;
@@ -195,7 +207,7 @@ int fvm_adjoint_run(fvm_grid* g, double* const* ckpts, int ckpt_every,
                     double* lam_tmp, double* seg_buf);
 
 /* One adjoint step at state w with time step dt: lam_out = (dW^{n+1}/dW^n)^T
- * lam_in (device pointers, pitch ld). Asynchronous. */
+ * lam_in (device pointers, the grid's ld and layout). Asynchronous. */
 int fvm_adjoint_step(fvm_grid* g, const double* w, double dt,
                      const double* lam_in, double* lam_out);
 
@@ -205,11 +217,11 @@ int fvm_adjoint_step(fvm_grid* g, const double* w, double dt,
 int fvm_set_tiling(fvm_grid* g, int rows_per_strip, int waves_per_block);
 int fvm_get_tiling(const fvm_grid* g, int* rows_per_strip, int* waves_per_block);
 
-/* Lane layout of the fused step: 1 = one cell per lane (any pitch), 2 = two
+/* Lanes of the fused step: 1 = one cell per lane (any pitch), 2 = two
  * adjacent cells per lane with 16-byte accesses (needs an even ld and 16-byte
  * aligned buffers; otherwise the call falls back to 1), 0 = the model's
- * default. Results are bitwise identical for every layout. fvm_get returns
- * the layout in use. */
+ * default. Results are bitwise identical either way.
+ * fvm_get_cells_per_lane returns the value in use. */
 int fvm_set_cells_per_lane(fvm_grid* g, int cells_per_lane);
 int fvm_get_cells_per_lane(const fvm_grid* g);
 

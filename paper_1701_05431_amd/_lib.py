@@ -14,6 +14,7 @@ LIB_PATH = os.path.join(HERE, "libfvm.so")
 FVM_OK, FVM_EINVAL, FVM_EDEVICE, FVM_ECFL, FVM_ENONFINITE, FVM_EUNSUPPORTED = 0, -1, -2, -3, -4, -5
 FVM_ADV, FVM_EULER, FVM_SPRAY = 0, 1, 2
 FVM_PERIODIC, FVM_TRANSMISSIVE = 0, 1
+FVM_LAYOUT_PLANES, FVM_LAYOUT_ROWS = 0, 1
 
 
 class FvmError(RuntimeError):
@@ -26,7 +27,7 @@ class FvmError(RuntimeError):
 class Params(C.Structure):
     _fields_ = [
         ("model", C.c_int), ("bc", C.c_int), ("nx", C.c_int), ("ny", C.c_int),
-        ("npart_x", C.c_int), ("npart_y", C.c_int), ("ld", C.c_int), ("reserved", C.c_int),
+        ("npart_x", C.c_int), ("npart_y", C.c_int), ("ld", C.c_int), ("layout", C.c_int),
         ("lx", C.c_double), ("ly", C.c_double), ("gamma", C.c_double),
         ("ax", C.c_double), ("ay", C.c_double), ("K", C.c_double),
         ("theta", C.c_double), ("s_eps", C.c_double), ("cfl", C.c_double),

@@ -25,6 +25,31 @@ hipError_t launch_cfl(const CflArgs& a, int model, hipStream_t st);
 hipError_t launch_clear_scratch(GridScratch* s, int n, hipStream_t st);
 hipError_t launch_clear_log_cursor(GridScratch* s, hipStream_t st);
 hipError_t launch_adjoint(const AdjointArgs& a, int model, hipStream_t st);
+
+GridGeom grid_geometry(const fvm_params& p) {
+  GridGeom g{};
+  g.nx = p.nx;
+  g.ny = p.ny;
+  g.bc = p.bc;
+  if (p.layout == FVM_LAYOUT_ROWS) {
+    g.ld = fvm_nvar(p.model) * p.ld;
+    g.plane = static_cast<size_t>(p.ld);
+    g.uld = 2 * p.ld;
+    g.uplane = static_cast<size_t>(p.ld);
+  } else {
+    g.ld = p.ld;
+    g.plane = static_cast<size_t>(p.ld) * p.ny;
+    g.uld = p.ld;
+    g.uplane = g.plane;
+  }
+  g.dx = p.lx / p.nx;
+  g.dy = p.ly / p.ny;
+  g.cfl = p.cfl;
+  g.dt_max = p.dt_max;
+  g.hmin = g.dx < g.dy ? g.dx : g.dy;
+  return g;
+}
+
 }  // namespace fvm
 
 using namespace fvm;
@@ -42,7 +67,9 @@ bool valid_params(const fvm_params* p) {
   if (p->bc != FVM_PERIODIC && p->bc != FVM_TRANSMISSIVE) return false;
   if (p->nx < 1 || p->ny < 1 || p->npart_x < 1 || p->npart_y < 1) return false;
   if (p->nx % p->npart_x != 0 || p->ny % p->npart_y != 0) return false;
-  if (p->ld < p->nx || p->reserved != 0) return false;
+  if (p->ld < p->nx) return false;
+  if (p->layout != FVM_LAYOUT_PLANES && p->layout != FVM_LAYOUT_ROWS) return false;
+  if (static_cast<long long>(p->ld) * fvm_nvar(p->model) > 2147483647ll) return false;
   if (!(p->lx > 0) || !(p->ly > 0) || !std::isfinite(p->lx) || !std::isfinite(p->ly)) return false;
   if (!(p->cfl > 0) || !std::isfinite(p->cfl)) return false;
   if (!(p->dt_max >= 0) || !std::isfinite(p->dt_max)) return false;
@@ -71,20 +98,6 @@ ModelConsts model_consts(const fvm_params& p) {
   return m;
 }
 
-GridGeom geometry(const fvm_params& p) {
-  GridGeom g{};
-  g.nx = p.nx;
-  g.ny = p.ny;
-  g.ld = p.ld;
-  g.bc = p.bc;
-  g.plane = static_cast<size_t>(p.ld) * p.ny;
-  g.dx = p.lx / p.nx;
-  g.dy = p.ly / p.ny;
-  g.cfl = p.cfl;
-  g.dt_max = p.dt_max;
-  g.hmin = g.dx < g.dy ? g.dx : g.dy;
-  return g;
-}
 
 Tiling tiling(const GridGeom& g, int rows, int wpb, int cpl) {
   Tiling t{};
@@ -184,6 +197,9 @@ struct fvm_grid {
   }
   double* other(const double* w) const { return w == w_a ? w_b : w_a; }
 
+  // doubles in one state (either layout)
+  size_t elems() const { return static_cast<size_t>(nv) * p.ny * p.ld; }
+
   StepArgs step_args(const double* win, double* wout, int mode) const {
     StepArgs a{};
     a.win = win;
@@ -239,7 +255,7 @@ int fvm_create(const fvm_params* p, fvm_grid** out) {
   g->nv = fvm_nvar(p->model);
   default_tiling(*p, 2, &g->rows, &g->wpb);
   default_tiling(*p, 1, &g->adj_rows, &g->adj_wpb);
-  g->g = geometry(*p);
+  g->g = grid_geometry(*p);
   g->m = model_consts(*p);
   *out = g;
   return FVM_OK;
@@ -298,7 +314,7 @@ int fvm_current(const fvm_grid* g, double** w) {
 
 int fvm_set_state(fvm_grid* g, const double* src, int src_on_device) {
   if (!g || !src || !g->bound) return FVM_EINVAL;
-  const size_t bytes = sizeof(double) * g->nv * g->g.plane;
+  const size_t bytes = sizeof(double) * g->elems();
   hipError_t e = hipMemcpyAsync(g->cur, src, bytes,
                                 src_on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice,
                                 g->stream);
@@ -309,7 +325,7 @@ int fvm_set_state(fvm_grid* g, const double* src, int src_on_device) {
 
 int fvm_get_state(fvm_grid* g, double* dst, int dst_on_device) {
   if (!g || !dst || !g->bound) return FVM_EINVAL;
-  const size_t bytes = sizeof(double) * g->nv * g->g.plane;
+  const size_t bytes = sizeof(double) * g->elems();
   hipError_t e = hipMemcpyAsync(dst, g->cur, bytes,
                                 dst_on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost,
                                 g->stream);
@@ -490,7 +506,7 @@ int fvm_run_ckpt(fvm_grid* g, int nsteps, int ckpt_every, double* const* ckpts,
   if (rc) return rc;
   if (dts_dev) rc = dev_err(launch_clear_log_cursor(g->scr, g->stream));
   if (rc) return rc;
-  const size_t bytes = sizeof(double) * g->nv * g->g.plane;
+  const size_t bytes = sizeof(double) * g->elems();
   if (nck > 0) {
     rc = dev_err(hipMemcpyAsync(ckpts[0], g->cur, bytes, hipMemcpyDeviceToDevice, g->stream));
     if (rc) return rc;
@@ -602,8 +618,9 @@ extern "C" {
 int fvm_autotune(fvm_grid* g, const char* cache_path) {
   if (!g || !g->bound) return FVM_EINVAL;
   char kbuf[256];
-  std::snprintf(kbuf, sizeof kbuf, "%s grid model=%d bc=%d nx=%d ny=%d ld=%d",
-                device_arch().c_str(), g->p.model, g->p.bc, g->p.nx, g->p.ny, g->p.ld);
+  std::snprintf(kbuf, sizeof kbuf, "%s grid model=%d bc=%d nx=%d ny=%d ld=%d layout=%d",
+                device_arch().c_str(), g->p.model, g->p.bc, g->p.nx, g->p.ny, g->p.ld,
+                g->p.layout);
   const std::string key = kbuf;
   int rows = 0, wpb = 0, cpl = 0;
   if (cache_lookup(cache_path, key, &rows, &wpb, &cpl) && valid_tiling(rows, wpb) &&
@@ -696,7 +713,7 @@ int fvm_adjoint_run(fvm_grid* g, double* const* ckpts, int ckpt_every, const dou
   const int nck = (nsteps + ckpt_every - 1) / ckpt_every;
   for (int s = 0; s < nck; ++s)
     if (!ckpts[s]) return FVM_EINVAL;
-  const size_t state = g->nv * g->g.plane;
+  const size_t state = g->elems();
   double* lin = lam;
   double* lout = lam_tmp;
   for (int s = nck - 1; s >= 0; --s) {

@@ -52,7 +52,7 @@ __global__ void batch_log_rewind_kernel(GridScratch* g, int n) {
   if (k < n) g[k].nstep = 0;
 }
 
-template <class M, int BC, int WPB, int CPL>
+template <class M, int BC, int WPB>
 __global__ FVM_STEP_BOUNDS(WPB) void batch_kernel(BatchArgs a) {
   const M m(a.m);
   __shared__ int s_item;
@@ -74,18 +74,19 @@ __global__ FVM_STEP_BOUNDS(WPB) void batch_kernel(BatchArgs a) {
     const int tile = item - G.item0;
     const int tx = tile % G.tiles_x, ty = tile / G.tiles_x;
     const int wave = wave_index();
-    const int xs = (tx * WPB + wave) * strip_width(CPL);
+    const bool wide = G.cpl == 2;  // uniform across the workgroup
+    const int xs = (tx * WPB + wave) * (wide ? strip_width(2) : strip_width(1));
     const int j0 = ty * a.rows;
     const int j1 = min(j0 + a.rows, G.g.ny);
     unsigned long long bx = 0, by = 0;
     if (xs < G.g.nx) {
-      if (CPL == 1 && FVM_LEGACY_STRIP)
+      if (!wide && FVM_LEGACY_STRIP)
         march_strip<M, BC>(m, a.win + G.offset, a.wout + G.offset, nullptr, G.g, xs, j0, j1, mux,
                            muy, dt, bx, by);
-      else if (CPL == 1 && xs + kWave <= G.g.nx)
+      else if (!wide && xs + kWave <= G.g.nx)
         march_strip1<M, BC, false>(m, a.win + G.offset, a.wout + G.offset, nullptr, G.g, xs, j0,
                                    j1, mux, muy, dt, bx, by);
-      else if (CPL == 1)
+      else if (!wide)
         march_strip1<M, BC, true>(m, a.win + G.offset, a.wout + G.offset, nullptr, G.g, xs, j0,
                                   j1, mux, muy, dt, bx, by);
       else if (xs + 2 * kWave <= G.g.nx)
@@ -109,26 +110,25 @@ __global__ FVM_STEP_BOUNDS(WPB) void batch_kernel(BatchArgs a) {
   }
 }
 
-template <class M, int BC, int CPL>
+template <class M, int BC>
 static void* batch_fn_wpb(int wpb) {
   switch (wpb) {
-    case 1: return reinterpret_cast<void*>(&batch_kernel<M, BC, 1, CPL>);
-    case 2: return reinterpret_cast<void*>(&batch_kernel<M, BC, 2, CPL>);
-    case 4: return reinterpret_cast<void*>(&batch_kernel<M, BC, 4, CPL>);
-    case 8: return reinterpret_cast<void*>(&batch_kernel<M, BC, 8, CPL>);
+    case 1: return reinterpret_cast<void*>(&batch_kernel<M, BC, 1>);
+    case 2: return reinterpret_cast<void*>(&batch_kernel<M, BC, 2>);
+    case 4: return reinterpret_cast<void*>(&batch_kernel<M, BC, 4>);
+    case 8: return reinterpret_cast<void*>(&batch_kernel<M, BC, 8>);
     default: return nullptr;
   }
 }
 
 template <class M>
-static void* batch_fn_bc(int bc, int wpb, int cpl) {
-  if (cpl == 2) return bc == 0 ? batch_fn_wpb<M, 0, 2>(wpb) : batch_fn_wpb<M, 1, 2>(wpb);
-  return bc == 0 ? batch_fn_wpb<M, 0, 1>(wpb) : batch_fn_wpb<M, 1, 1>(wpb);
+static void* batch_fn_bc(int bc, int wpb) {
+  return bc == 0 ? batch_fn_wpb<M, 0>(wpb) : batch_fn_wpb<M, 1>(wpb);
 }
 
-static void* batch_kernel_ptr(int model, int bc, int wpb, int cpl) {
-  if (model == 0) return batch_fn_bc<Adv>(bc, wpb, cpl);
-  if (model == 1) return batch_fn_bc<Euler>(bc, wpb, cpl);
+static void* batch_kernel_ptr(int model, int bc, int wpb) {
+  if (model == 0) return batch_fn_bc<Adv>(bc, wpb);
+  if (model == 1) return batch_fn_bc<Euler>(bc, wpb);
   return nullptr;
 }
 
@@ -145,7 +145,7 @@ struct BatchGraph {
   int nsteps;
   const double* start;
   const double* log;
-  int rows, wpb, cpl;
+  int rows, wpb;
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
 };
@@ -160,7 +160,6 @@ struct fvm_batch {
   std::vector<int> order;        // processing order (largest first)
   ModelConsts m{};
   int rows = 32, wpb = 2;
-  int cpl = 1;                   // 2 when every grid has an even pitch
   double* w_a = nullptr;
   double* w_b = nullptr;
   double* cur = nullptr;
@@ -198,19 +197,14 @@ struct fvm_batch {
       BatchGrid r{};
       r.offset = offsets[k];
       r.user = k;
-      GridGeom g{};
-      g.nx = p[k].nx;
-      g.ny = p[k].ny;
-      g.ld = p[k].ld;
-      g.bc = p[k].bc;
-      g.plane = static_cast<size_t>(p[k].ld) * p[k].ny;
-      g.dx = p[k].lx / p[k].nx;
-      g.dy = p[k].ly / p[k].ny;
-      g.cfl = p[k].cfl;
-      g.dt_max = p[k].dt_max;
-      g.hmin = g.dx < g.dy ? g.dx : g.dy;
+      const GridGeom g = grid_geometry(p[k]);
       r.g = g;
-      r.tiles_x = (g.nx + strip_width(cpl) * wpb - 1) / (strip_width(cpl) * wpb);
+      // two cells per lane needs 16-byte aligned rows: an even pitch (the
+      // grid offsets are multiples of 32 elements, the buffers 256-byte
+      // aligned)
+      r.cpl = p[k].ld % 2 == 0 ? 2 : 1;
+      const int w = strip_width(r.cpl) * wpb;
+      r.tiles_x = (g.nx + w - 1) / w;
       r.tiles_y = (g.ny + rows - 1) / rows;
       r.ntiles = r.tiles_x * r.tiles_y;
       r.item0 = item;
@@ -264,9 +258,6 @@ int fvm_batch_create(int n, const fvm_params* p, const size_t* offsets, fvm_batc
   m.ax = q.ax;
   m.ay = q.ay;
   b->m = m;
-  bool even = true;
-  for (int k = 0; k < n; ++k) even = even && (p[k].ld % 2 == 0);
-  b->cpl = even ? 2 : 1;
   b->plan();
   *out = b;
   return FVM_OK;
@@ -308,7 +299,7 @@ int fvm_batch_bind(fvm_batch* b, double* w_a, double* w_b, void* scratch, void* 
   if (hipGetDevice(&dev) != hipSuccess) return FVM_EDEVICE;
   if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
     return FVM_EDEVICE;
-  void* f = batch_kernel_ptr(b->model, b->bc, b->wpb, b->cpl);
+  void* f = batch_kernel_ptr(b->model, b->bc, b->wpb);
   if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, f, b->wpb * kWave, 0) != hipSuccess)
     return FVM_EDEVICE;
   b->nblocks = std::max(1, cus * std::max(1, per_cu));
@@ -332,7 +323,7 @@ int fvm_batch_set_tiling(fvm_batch* b, int rows, int wpb) {
   if (hipGetDevice(&dev) != hipSuccess) return FVM_EDEVICE;
   if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
     return FVM_EDEVICE;
-  void* f = batch_kernel_ptr(b->model, b->bc, b->wpb, b->cpl);
+  void* f = batch_kernel_ptr(b->model, b->bc, b->wpb);
   if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, f, b->wpb * kWave, 0) != hipSuccess)
     return FVM_EDEVICE;
   b->nblocks = std::max(1, cus * std::max(1, per_cu));
@@ -360,7 +351,7 @@ static int batch_graph(fvm_batch* b, int kind, int nsteps, double* log, int log_
                        hipGraphExec_t* exec) {
   for (auto it = b->graphs.begin(); it != b->graphs.end(); ++it) {
     if (it->kind == kind && it->nsteps == nsteps && it->start == b->cur && it->log == log &&
-        it->rows == b->rows && it->wpb == b->wpb && it->cpl == b->cpl) {
+        it->rows == b->rows && it->wpb == b->wpb) {
       b->graphs.splice(b->graphs.begin(), b->graphs, it);
       *exec = b->graphs.front().exec;
       return FVM_OK;
@@ -373,7 +364,6 @@ static int batch_graph(fvm_batch* b, int kind, int nsteps, double* log, int log_
   c.log = log;
   c.rows = b->rows;
   c.wpb = b->wpb;
-  c.cpl = b->cpl;
   if (hipGraphCreate(&c.graph, 0) != hipSuccess) return FVM_EDEVICE;
   hipGraphNode_t prev = nullptr;
   const double* in = b->cur;
@@ -410,7 +400,7 @@ static int batch_graph(fvm_batch* b, int kind, int nsteps, double* log, int log_
       a.rows = b->rows;
       a.dt_scale = kind == 2 ? 0.0 : 1.0;
       a.m = b->m;
-      ok = add(batch_kernel_ptr(b->model, b->bc, b->wpb, b->cpl),
+      ok = add(batch_kernel_ptr(b->model, b->bc, b->wpb),
                dim3(std::min(b->nblocks, b->nitems)),
                dim3(b->wpb * kWave), &a);
     } else {
@@ -427,12 +417,12 @@ static int batch_graph(fvm_batch* b, int kind, int nsteps, double* log, int log_
         a.g = r.g;
         a.t.rows = b->rows;
         a.t.wpb = b->wpb;
-        a.t.cpl = b->cpl;
+        a.t.cpl = r.cpl;
         a.t.tiles_x = r.tiles_x;
         a.t.tiles_y = r.tiles_y;
         a.t.ntiles = r.ntiles;
         a.m = b->m;
-        ok = add(step_kernel_ptr(b->model, b->bc, b->wpb, b->cpl), dim3(r.ntiles),
+        ok = add(step_kernel_ptr(b->model, b->bc, b->wpb, r.cpl), dim3(r.ntiles),
                  dim3(b->wpb * kWave),
                  &a);
       }
@@ -498,7 +488,7 @@ int fvm_batch_autotune(fvm_batch* b, const char* cache_path) {
   if (!b || !b->bound) return FVM_EINVAL;
   unsigned long long h = 1469598103934665603ull;  // FNV-1a over the grid shapes
   for (const auto& p : b->p)
-    for (int x : {p.nx, p.ny, p.ld}) {
+    for (int x : {p.nx, p.ny, p.ld, p.layout}) {
       h ^= static_cast<unsigned long long>(x);
       h *= 1099511628211ull;
     }

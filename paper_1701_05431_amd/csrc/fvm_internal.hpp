@@ -7,6 +7,8 @@
 #include <cstddef>
 #include <cstdint>
 
+struct fvm_params;
+
 namespace fvm {
 
 constexpr int kWave = 64;       // CDNA wavefront width
@@ -48,14 +50,22 @@ struct ModelConsts {
   double s_eps, log_s_eps;    // spray closure
 };
 
-// Geometry and policy of one grid.
+// Geometry and policy of one grid. Variable v of cell (i, j) sits at
+// v * plane + j * ld + i: the planar layout has ld = row pitch and
+// plane = pitch * ny, the row-interleaved layout ld = nVar * pitch and
+// plane = pitch. The spray gas velocity (2 variables) uses uld / uplane.
 struct GridGeom {
   int nx, ny, ld, bc;
-  size_t plane;               // ld * ny
+  size_t plane;
   double dx, dy;              // lx/nx, ly/ny
   double cfl, dt_max;
   double hmin;                // min(dx, dy) for the fixed-dt check
+  size_t uplane;
+  int uld, pad;
 };
+
+// Geometry of a validated parameter set (fvm_api.hip).
+GridGeom grid_geometry(const fvm_params& p);
 
 // Cells a wave strip updates: 64 with one cell per lane, 128 with two.
 // (FVM_LEGACY_STRIP selects the older one-cell strip whose lanes 0 and 63
@@ -122,7 +132,8 @@ struct BatchGrid {            // per-grid record in device memory
   size_t offset;              // element offset of the grid inside the packed buffers
   GridGeom g;
   int tiles_x, tiles_y, ntiles, item0;  // item0: first work item of the grid
-  int user, pad;                       // the caller's index of the grid
+  int user;                            // the caller's index of the grid
+  int cpl;                             // cells per lane of the grid's strips
 };
 
 struct BatchScratch {         // header of the batch scratch

@@ -83,13 +83,16 @@ __device__ __forceinline__ double from_prev(double x) {
 
 __device__ __forceinline__ bool finite(double x) { return __builtin_isfinite(x); }
 
-// Reciprocal and square root of the per-cell primitives. By default the
-// compiler's correctly rounded sequences; with FVM_FAST_DIVSQRT the hardware
-// estimates refined by Newton steps (reciprocal) and one Goldschmidt step
-// pair plus a residual correction (square root), within an ulp of the exact
-// result for the normal-range arguments the models produce, in about half
-// the instructions. Zero, negative and non-finite arguments give the same
-// classification as the exact forms (0 -> 0 for the root, NaN propagates).
+// Reciprocal and square root of the per-cell primitives. With
+// FVM_FAST_DIVSQRT (the default) the hardware estimates are refined in FP64:
+// two Newton-Raphson steps for 1/x, and for sqrt(x) one step of Goldschmidt's
+// coupled iteration on (x*y, y/2), y ~ 1/sqrt(x), followed by one
+// Newton-style residual correction (the textbook scheme, e.g. P. Markstein,
+// IA-64 and Elementary Functions, 2000). For the normal-range arguments the
+// models produce this is within an ulp of the correctly rounded result, in
+// about half the instructions. Zero, negative and non-finite arguments are
+// classified as by the exact forms (0 -> 0 for the root, NaN propagates).
+// FVM_FAST_DIVSQRT=0 selects the compiler's correctly rounded sequences.
 #ifndef FVM_FAST_DIVSQRT
 #define FVM_FAST_DIVSQRT 1
 #endif
@@ -259,7 +262,7 @@ struct Spray {
   __device__ __forceinline__ void speeds(const double* w, double& sx, double& sy) const {
     Prim q;
     prim(w, q);
-    bool ok = finite(w[4]) & finite(w[5]);
+    bool ok = finite(w[4]) && finite(w[5]);
 #pragma unroll
     for (int k = 0; k < 4; ++k) ok = ok & finite(w[k]) & (w[k] >= 0.0);
     sx = ok ? fabs(q.ux) : __builtin_nan("");

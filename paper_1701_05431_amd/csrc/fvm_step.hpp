@@ -49,6 +49,11 @@ __device__ __forceinline__ int row_index(int r, int ny) {
   return r < 0 ? 0 : (r >= ny ? ny - 1 : r);
 }
 
+// offset of cell (i, j) in the first variable of the spray gas velocity
+__device__ __forceinline__ size_t ucell(const GridGeom& g, int j, int i) {
+  return static_cast<size_t>(j) * g.uld + i;
+}
+
 template <int NV, int BC>
 __device__ __forceinline__ void load_row(double* w, const double* __restrict__ base,
                                          const GridGeom& g, int r) {
@@ -138,7 +143,7 @@ __device__ __forceinline__ void march_strip(const M& m, const double* __restrict
         }
         const size_t cell = static_cast<size_t>(j) * g.ld + ic;
         if constexpr (NV == 6) {
-          m.source(Wo, ug[cell], ug[g.plane + cell], dt);
+          m.source(Wo, ug[ucell(g, j, ic)], ug[g.uplane + ucell(g, j, ic)], dt);
         }
         if (out && j < j1) {
 #pragma unroll
@@ -233,7 +238,7 @@ __device__ __forceinline__ void march_strip1(const M& m, const double* __restric
       }
       const size_t cell = static_cast<size_t>(j) * g.ld + cx;
       if constexpr (NV == 6) {
-        m.source(Wo, ug[cell], ug[g.plane + cell], dt);
+        m.source(Wo, ug[ucell(g, j, cx)], ug[g.uplane + ucell(g, j, cx)], dt);
       }
       if (ok && j < j1) {
 #pragma unroll
@@ -356,7 +361,10 @@ __device__ __forceinline__ void march_strip2(const M& m, const double* __restric
       const size_t row = static_cast<size_t>(j) * g.ld;
       if constexpr (NV == 6) {
         double ua[2], ub[2];
-        load_pair<2, BC, EDGE>(ua, ub, ug, g, ca, cb, j);
+        GridGeom gu = g;
+        gu.ld = g.uld;
+        gu.plane = g.uplane;
+        load_pair<2, BC, EDGE>(ua, ub, ug, gu, ca, cb, j);
         m.source(Oa, ua[0], ua[1], dt);
         m.source(Ob, ub[0], ub[1], dt);
       }

@@ -19,8 +19,8 @@ from ._lib import check, lib
 def params_from(preset=None, **kw) -> _lib.Params:
     """fvm_params from a workload preset (or keyword arguments)."""
     d = dict(model=None, bc=_lib.FVM_PERIODIC, nx=None, ny=None, npart_x=1, npart_y=1,
-             ld=None, lx=1.0, ly=1.0, gamma=1.4, ax=0.0, ay=0.0, K=1.0, theta=0.1,
-             s_eps=0.01, cfl=0.45, dt_max=0.0)
+             ld=None, layout=_lib.FVM_LAYOUT_PLANES, lx=1.0, ly=1.0, gamma=1.4, ax=0.0,
+             ay=0.0, K=1.0, theta=0.1, s_eps=0.01, cfl=0.45, dt_max=0.0)
     if preset is not None:
         for k in ("model", "bc", "nx", "ny", "npart_x", "npart_y", "lx", "ly", "gamma", "ax",
                   "ay", "K", "theta", "s_eps", "cfl", "dt_max"):
@@ -31,7 +31,6 @@ def params_from(preset=None, **kw) -> _lib.Params:
     p = _lib.Params()
     for k, v in d.items():
         setattr(p, k, v)
-    p.reserved = 0
     return p
 
 
@@ -43,9 +42,24 @@ def _stream_handle(device) -> C.c_void_p:
     return C.c_void_p(torch.cuda.current_stream(device).cuda_stream)
 
 
+def storage_shape(p: _lib.Params, nv: int):
+    """Shape of the contiguous tensor that holds one field of nv variables in
+    the grid's layout: (nv, Ny, ld) for planes, (Ny, nv, ld) for rows."""
+    if p.layout == _lib.FVM_LAYOUT_ROWS:
+        return (p.ny, nv, p.ld)
+    return (nv, p.ny, p.ld)
+
+
+def logical(p: _lib.Params, t: torch.Tensor) -> torch.Tensor:
+    """The (nVar, Ny, ld) view of a storage tensor (strided for rows)."""
+    return t.permute(1, 0, 2) if p.layout == _lib.FVM_LAYOUT_ROWS else t
+
+
 class Solver:
-    """One grid: two ping-pong state buffers [nVar, Ny, ld] (float64), the
-    spray gas velocity if any, and the scratch, all allocated by torch."""
+    """One grid: two ping-pong state buffers (float64, nVar * Ny * ld each,
+    in the layout of p.layout), the spray gas velocity if any, and the
+    scratch, all allocated by torch. States go in and come out as
+    (nVar, Ny, Nx) or (nVar, Ny, ld) tensors whatever the layout."""
 
     def __init__(self, p: _lib.Params, device="cuda", ug=None):
         L = lib()
@@ -53,7 +67,7 @@ class Solver:
         self.p = p
         self.device = torch.device(device)
         self.nv = L.fvm_nvar(p.model)
-        shape = (self.nv, p.ny, p.ld)
+        shape = storage_shape(p, self.nv)
         self.wa = torch.zeros(shape, dtype=torch.float64, device=self.device)
         self.wb = torch.zeros(shape, dtype=torch.float64, device=self.device)
         self.ug = None
@@ -82,18 +96,20 @@ class Solver:
 
     # ---- state -------------------------------------------------------------
     def _as_state(self, W, nv=None) -> torch.Tensor:
+        """A storage tensor (grid layout, contiguous) holding W, given as
+        (nv, Ny, Nx) or (nv, Ny, ld)."""
         nv = self.nv if nv is None else nv
         p = self.p
         if isinstance(W, np.ndarray):
             W = torch.from_numpy(np.ascontiguousarray(W, dtype=np.float64))
         W = W.to(device=self.device, dtype=torch.float64)
-        if W.shape == (nv, p.ny, p.nx) and p.ld != p.nx:
-            out = torch.zeros((nv, p.ny, p.ld), dtype=torch.float64, device=self.device)
-            out[:, :, :p.nx] = W
-            W = out
-        if W.shape != (nv, p.ny, p.ld):
+        if W.shape not in ((nv, p.ny, p.nx), (nv, p.ny, p.ld)):
             raise ValueError(f"state shape {tuple(W.shape)} does not match ({nv}, {p.ny}, {p.ld})")
-        return W.contiguous()
+        if W.shape[2] == p.ld and p.layout == _lib.FVM_LAYOUT_PLANES:
+            return W.contiguous()
+        out = torch.zeros(storage_shape(p, nv), dtype=torch.float64, device=self.device)
+        logical(p, out)[:, :, :W.shape[2]].copy_(W)
+        return out
 
     def _bind_stream(self):
         lib().fvm_set_stream(self.h, _stream_handle(self.device))
@@ -104,16 +120,20 @@ class Solver:
         check(lib().fvm_set_state(self.h, _ptr(src), 1), "fvm_set_state")
         self._keep = src  # keep the source alive until the copy has run
 
-    def current(self) -> torch.Tensor:
-        """The buffer holding the current state (a view; the next step
-        overwrites the other buffer, not this one)."""
+    def current_storage(self) -> torch.Tensor:
+        """The buffer holding the current state, in the grid's layout."""
         ptr = C.c_void_p()
         check(lib().fvm_current(self.h, C.byref(ptr)), "fvm_current")
         return self.wa if ptr.value == self.wa.data_ptr() else self.wb
 
+    def current(self) -> torch.Tensor:
+        """The current state as an (nVar, Ny, ld) view of its buffer (the
+        next step overwrites the other buffer, not this one)."""
+        return logical(self.p, self.current_storage())
+
     def state(self) -> torch.Tensor:
-        """A copy of the current state, shape (nVar, Ny, Nx)."""
-        return self.current()[:, :, :self.p.nx].clone()
+        """A contiguous copy of the current state, shape (nVar, Ny, Nx)."""
+        return self.current()[:, :, :self.p.nx].clone(memory_format=torch.contiguous_format)
 
     # ---- stepping ------------------------------------------------------------
     def cfl_dt(self):
@@ -140,7 +160,8 @@ class Solver:
         self._keep = dts
 
     def run_ckpt(self, nsteps: int, every: int):
-        """Adaptive run that stores W^0, W^every, ...; returns (ckpts, dts)."""
+        """Adaptive run that stores W^0, W^every, ...; returns (ckpts, dts),
+        the checkpoints as storage tensors in the grid's layout."""
         nck = (nsteps + every - 1) // every
         ck = [torch.empty_like(self.wa) for _ in range(nck)]
         dts = torch.zeros(max(nsteps, 1), dtype=torch.float64, device=self.device)
@@ -150,8 +171,8 @@ class Solver:
         return ck, dts[:nsteps]
 
     def adjoint(self, ckpts, every: int, dts: torch.Tensor, lam: torch.Tensor) -> torch.Tensor:
-        """dL/dW^0 from dL/dW^N (lam, shape (nVar, Ny, ld)) through len(dts)
-        steps with the given checkpoints."""
+        """dL/dW^0 from dL/dW^N (lam, shape (nVar, Ny, Nx or ld)) through
+        len(dts) steps with the given checkpoints; an (nVar, Ny, ld) view."""
         lam = self._as_state(lam).clone()
         tmp = torch.empty_like(lam)
         seg = torch.empty((max(every - 1, 1),) + tuple(lam.shape), dtype=torch.float64,
@@ -161,7 +182,7 @@ class Solver:
         check(lib().fvm_adjoint_run(self.h, arr, int(every), _ptr(dts), int(dts.numel()),
                                     _ptr(lam), _ptr(tmp), _ptr(seg)), "fvm_adjoint_run")
         self._keep = (tmp, seg)
-        return lam
+        return logical(self.p, lam)
 
     def adjoint_step(self, W, dt: float, lam) -> torch.Tensor:
         W = self._as_state(W)
@@ -171,7 +192,7 @@ class Solver:
         check(lib().fvm_adjoint_step(self.h, _ptr(W), float(dt), _ptr(lam), _ptr(out)),
               "fvm_adjoint_step")
         self._keep = (W, lam)
-        return out
+        return logical(self.p, out)
 
     def sync(self) -> int:
         return int(lib().fvm_sync(self.h))
@@ -188,8 +209,12 @@ class Solver:
         return r.value, w.value
 
     def set_cells_per_lane(self, cpl: int = 0) -> int:
-        """Lane layout of the step kernel (0 = default); returns the one in use."""
+        """Cells per lane of the step kernel (0 = default); returns the value
+        in use."""
         check(lib().fvm_set_cells_per_lane(self.h, int(cpl)), "fvm_set_cells_per_lane")
+        return self.cells_per_lane()
+
+    def cells_per_lane(self) -> int:
         return int(lib().fvm_get_cells_per_lane(self.h))
 
     def autotune(self, cache_path: str | None = None):
@@ -199,7 +224,7 @@ class Solver:
         self._bind_stream()
         path = cache_path.encode() if cache_path else None
         check(lib().fvm_autotune(self.h, path), "fvm_autotune")
-        return self.tiling() + (int(lib().fvm_get_cells_per_lane(self.h)),)
+        return self.tiling() + (self.cells_per_lane(),)
 
 
 class Batch:
@@ -249,9 +274,10 @@ class Batch:
         return self.wa if ptr.value == self.wa.data_ptr() else self.wb
 
     def view(self, buf: torch.Tensor, k: int) -> torch.Tensor:
+        """Grid k of a packed buffer as an (nVar, Ny, ld) view."""
         p = self.plist[k]
         n = self.nv * p.ny * p.ld
-        return buf[self.offsets[k]:self.offsets[k] + n].view(self.nv, p.ny, p.ld)
+        return logical(p, buf[self.offsets[k]:self.offsets[k] + n].view(storage_shape(p, self.nv)))
 
     def set_states(self, states) -> None:
         cur = self.current()
@@ -265,7 +291,8 @@ class Batch:
 
     def states(self):
         cur = self.current()
-        return [self.view(cur, k)[:, :, :self.plist[k].nx].clone() for k in range(self.n)]
+        return [self.view(cur, k)[:, :, :self.plist[k].nx].clone(memory_format=torch.contiguous_format)
+                for k in range(self.n)]
 
     def run(self, nsteps: int, record_dt: bool = False, per_grid: bool = False):
         dts = (torch.zeros(max(nsteps, 1) * self.n, dtype=torch.float64, device=self.device)
@@ -309,7 +336,7 @@ class FVRun(torch.autograd.Function):
     def backward(ctx, gN):
         s = ctx.solver
         lam = s.adjoint(ctx.ckpts, ctx.every, ctx.dts, gN.detach().contiguous())
-        return lam[:, :, :s.p.nx].clone(), None, None, None
+        return lam[:, :, :s.p.nx].clone(memory_format=torch.contiguous_format), None, None, None
 
 
 def fvrun(W0: torch.Tensor, solver: Solver, nsteps: int, every: int | None = None):

@@ -37,6 +37,15 @@ def test_binding_covers_the_header():
     assert set(declared_functions()) == set(_lib.SIGNATURES)
 
 
+def test_binding_constants_match_the_header():
+    from paper_1701_05431_amd import _lib
+    text = open(HEADER).read()
+    defines = dict(re.findall(r"#define (FVM_[A-Z_]+) \(?(-?\d+)\)?", text))
+    assert len(defines) == 13
+    for name, value in defines.items():
+        assert getattr(_lib, name) == int(value), name
+
+
 def test_params_struct_layout():
     from paper_1701_05431_amd import _lib
     # 8 ints followed by 10 doubles, no padding
@@ -60,6 +69,8 @@ def test_validation_on_host(L):
         dict(cfl=float("nan")),
         dict(lx=-1.0),
         dict(dt_max=-1.0),
+        dict(layout=2),             # unknown layout
+        dict(layout=1, ld=600_000_000, ny=1, npart_y=1),  # nVar * ld overflows int
     ]
     for c in cases:
         kw = dict(model=1, nx=64, ny=32, npart_x=8, npart_y=4)
@@ -70,6 +81,8 @@ def test_validation_on_host(L):
         h = C.c_void_p()
         assert L.fvm_create(p, C.byref(h)) == _lib.FVM_EINVAL, c
         assert not h.value
+    rows = params_from(model=1, nx=64, ny=32, ld=70, layout=_lib.FVM_LAYOUT_ROWS)
+    assert L.fvm_validate(rows) == _lib.FVM_OK
     sp = params_from(model=2, nx=8, ny=8, theta=0.0)
     assert L.fvm_validate(sp) == _lib.FVM_EINVAL
     sp = params_from(model=2, nx=8, ny=8, s_eps=1.5)

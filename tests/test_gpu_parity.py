@@ -174,14 +174,16 @@ def test_lane_layouts_agree_bitwise(model, bc, nx):
         W, ug = inputs.spray_state(nx, ny, nx)
         kw = dict(cfl=0.9)
     res = []
-    for cpl in (1, 2):
-        p = params_from(model=model, bc=bc, nx=nx, ny=ny, ld=ld, **kw)
-        s = Solver(p, ug=ug)
-        assert s.set_cells_per_lane(cpl) == cpl
-        s.set_state(W)
-        d = s.run(5, record_dt=True).cpu().numpy()
-        res.append((gpu_state(s), d))
-    assert np.array_equal(res[0][0], res[1][0]) and np.array_equal(res[0][1], res[1][1])
+    for layout in (_lib.FVM_LAYOUT_PLANES, _lib.FVM_LAYOUT_ROWS):
+        for cpl in (1, 2):
+            p = params_from(model=model, bc=bc, nx=nx, ny=ny, ld=ld, layout=layout, **kw)
+            s = Solver(p, ug=ug)
+            assert s.set_cells_per_lane(cpl) == cpl
+            s.set_state(W)
+            d = s.run(5, record_dt=True).cpu().numpy()
+            res.append((gpu_state(s), d))
+    for r in res[1:]:
+        assert np.array_equal(res[0][0], r[0]) and np.array_equal(res[0][1], r[1])
     ref, odts = orc.run(oparams(params_from(model=model, bc=bc, nx=nx, ny=ny, **kw)), W, 5, ug=ug)
     assert rel_linf(res[1][0], ref) <= TOL
 
@@ -200,6 +202,26 @@ def test_pitch_padding_is_untouched():
     assert np.all(cur[:, :, nx:] == -777.0)
     ref, _ = orc.run(oparams(p), W, 3)
     assert rel_linf(cur[:, :, :nx], ref) <= TOL
+
+
+def test_row_layout_addresses():
+    """Row-interleaved storage: each variable's row j sits at (j * nVar + v)
+    * ld, the padding columns stay untouched, and the result is the
+    oracle's."""
+    nx, ny, ld = 70, 33, 96
+    W = inputs.riemann_state(nx, ny, 2)
+    p = params_from(model=1, bc=0, nx=nx, ny=ny, ld=ld, layout=_lib.FVM_LAYOUT_ROWS)
+    s = Solver(p)
+    assert tuple(s.wa.shape) == (ny, 4, ld)
+    s.wa.fill_(12345.0)
+    s.wb.fill_(-777.0)
+    s.set_state(W)
+    s.run(3)
+    torch.cuda.synchronize()
+    raw = s.current_storage().cpu().numpy()
+    assert np.all(raw[:, :, nx:] == -777.0)
+    ref, _ = orc.run(oparams(p), W, 3)
+    assert rel_linf(np.transpose(raw[:, :, :nx], (1, 0, 2)), ref) <= TOL
 
 
 # ---------------------------------------------------------------------------
@@ -289,6 +311,23 @@ def test_batch_equals_single_grid_runs():
     assert rel_linf(got[3], ref) <= TOL
 
 
+def test_batch_row_layout_equals_planar():
+    sizes = [64, 97, 130, 71, 257]
+    plist, states = _batch_case(sizes, 3)
+    rows = [params_from(model=p.model, bc=p.bc, nx=p.nx, ny=p.ny, ld=p.ld, cfl=p.cfl,
+                        layout=_lib.FVM_LAYOUT_ROWS if k % 2 == 0 else _lib.FVM_LAYOUT_PLANES)
+            for k, p in enumerate(plist)]
+    out = []
+    for pl in (plist, rows):
+        b = Batch(pl)
+        b.set_states(states)
+        d = b.run(7, record_dt=True).cpu().numpy()
+        out.append(([x.cpu().numpy() for x in b.states()], d))
+    assert np.array_equal(out[0][1], out[1][1])
+    for k in range(len(sizes)):
+        assert np.array_equal(out[0][0][k], out[1][0][k]), k
+
+
 def test_batch_workload_sample_parity():
     """Sizes drawn as in the 256-grid workload; a few grids checked against
     the oracle after 5 steps."""
@@ -326,6 +365,11 @@ def test_adjoint_step(model, bc):
     torch.cuda.synchronize()
     ref = orc.adjoint_step(P, W, dt, lam)
     assert rel_linf(got[:, :, :nx].cpu().numpy(), ref) <= TOL
+    p.layout = _lib.FVM_LAYOUT_ROWS
+    p.ld = nx + 3
+    got_rows = Solver(p).adjoint_step(W, dt, lam)
+    torch.cuda.synchronize()
+    assert np.array_equal(got_rows[:, :, :nx].cpu().numpy(), got[:, :, :nx].cpu().numpy())
 
 
 def test_fvrun_gradient_matches_oracle_and_fd():
@@ -339,6 +383,12 @@ def test_fvrun_gradient_matches_oracle_and_fd():
     loss = 0.5 * ((Y[0] - tgt) ** 2).sum()
     loss.backward()
     g = X.grad.cpu().numpy()
+    # the same gradient from row-interleaved storage
+    pr = params_from(model=1, bc=1, nx=n, ny=n, ld=n + 2, layout=_lib.FVM_LAYOUT_ROWS)
+    Xr = torch.tensor(W0, device="cuda", requires_grad=True)
+    Yr = fvrun(Xr, Solver(pr), 30, 5)
+    (0.5 * ((Yr[0] - tgt) ** 2).sum()).backward()
+    assert torch.equal(Yr, Y) and np.array_equal(Xr.grad.cpu().numpy(), g)
     P = oparams(p)
     WN, odts = orc.run(P, W0, 30)
     lamN = np.zeros_like(W0)
