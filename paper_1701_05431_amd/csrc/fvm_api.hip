@@ -111,6 +111,16 @@ Tiling tiling(const GridGeom& g, int rows, int wpb, int cpl) {
   return t;
 }
 
+// The adjoint kernel's strips update 62 columns each (lanes 0 and 63 only
+// supply the halo), whatever the forward kernel's lane layout.
+Tiling adjoint_tiling(const GridGeom& g, int rows, int wpb) {
+  Tiling t = tiling(g, rows, wpb, 1);
+  const int w = kOutPerWave * wpb;
+  t.tiles_x = (g.nx + w - 1) / w;
+  t.ntiles = t.tiles_x * t.tiles_y;
+  return t;
+}
+
 // Default tile shape for a grid: the widest workgroup (up to 8 strips) the
 // grid's width fills, and the tallest strips (up to 64 rows) that still give
 // about 2048 wave strips, i.e. two per SIMD on 256 CUs. On the 4096^2 Euler
@@ -698,7 +708,7 @@ int fvm_adjoint_step(fvm_grid* g, const double* w, double dt, const double* lam_
   a.dts = nullptr;
   a.dt_arg = dt;
   a.g = g->g;
-  a.t = tiling(g->g, g->adj_rows, g->adj_wpb, 1);
+  a.t = adjoint_tiling(g->g, g->adj_rows, g->adj_wpb);
   a.m = g->m;
   return dev_err(launch_adjoint(a, g->p.model, g->stream));
 }
@@ -739,7 +749,7 @@ int fvm_adjoint_run(fvm_grid* g, double* const* ckpts, int ckpt_every, const dou
       a.dts = dts_dev;
       a.k = k;
       a.g = g->g;
-      a.t = tiling(g->g, g->adj_rows, g->adj_wpb, 1);
+      a.t = adjoint_tiling(g->g, g->adj_rows, g->adj_wpb);
       a.m = g->m;
       int rc = dev_err(launch_adjoint(a, g->p.model, g->stream));
       if (rc) return rc;

@@ -30,7 +30,7 @@
 #define FVM_PREFETCH2_ADV 2
 #endif
 #ifndef FVM_PREFETCH2_EULER
-#define FVM_PREFETCH2_EULER 1
+#define FVM_PREFETCH2_EULER 2
 #endif
 #ifndef FVM_PREFETCH2_SPRAY
 #define FVM_PREFETCH2_SPRAY 1

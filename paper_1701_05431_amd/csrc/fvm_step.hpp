@@ -143,7 +143,10 @@ __device__ __forceinline__ void march_strip(const M& m, const double* __restrict
         }
         const size_t cell = static_cast<size_t>(j) * g.ld + ic;
         if constexpr (NV == 6) {
-          m.source(Wo, ug[ucell(g, j, ic)], ug[g.uplane + ucell(g, j, ic)], dt);
+          // rows past the strip are computed but not stored; keep their
+          // gas-velocity reads inside the field
+          const size_t uc = ucell(g, min(j, j1 - 1), ic);
+          m.source(Wo, ug[uc], ug[g.uplane + uc], dt);
         }
         if (out && j < j1) {
 #pragma unroll
@@ -238,7 +241,10 @@ __device__ __forceinline__ void march_strip1(const M& m, const double* __restric
       }
       const size_t cell = static_cast<size_t>(j) * g.ld + cx;
       if constexpr (NV == 6) {
-        m.source(Wo, ug[ucell(g, j, cx)], ug[g.uplane + ucell(g, j, cx)], dt);
+        // rows past the strip are computed but not stored; keep their
+        // gas-velocity reads inside the field
+        const size_t uc = ucell(g, min(j, j1 - 1), cx);
+        m.source(Wo, ug[uc], ug[g.uplane + uc], dt);
       }
       if (ok && j < j1) {
 #pragma unroll

@@ -372,6 +372,24 @@ def test_adjoint_step(model, bc):
     assert np.array_equal(got_rows[:, :, :nx].cpu().numpy(), got[:, :, :nx].cpu().numpy())
 
 
+@pytest.mark.parametrize("nx", [1, 62, 63, 64, 124, 130, 500, 1024])
+def test_adjoint_step_covers_every_column(nx):
+    """The adjoint strips (62 columns each) tile the whole width at every
+    default workgroup size."""
+    ny = 9
+    print(f"adjoint widths nx={nx}", flush=True)
+    W = inputs.riemann_state(nx, ny, 8) + 0.01 * np.stack(
+        [inputs.gaussian_bumps(nx, ny, 50 + v) for v in range(4)])
+    p = params_from(model=1, bc=1, nx=nx, ny=ny)
+    lam = np.random.default_rng(nx).standard_normal(W.shape)
+    P = oparams(p)
+    _, _, dt = orc.cfl(P, W)
+    got = Solver(p).adjoint_step(W, dt, lam)
+    torch.cuda.synchronize()
+    ref = orc.adjoint_step(P, W, dt, lam)
+    assert rel_linf(got[:, :, :nx].cpu().numpy(), ref) <= TOL
+
+
 def test_fvrun_gradient_matches_oracle_and_fd():
     n = 32
     W0 = inputs.riemann_state(n, n, 0)
