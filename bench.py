@@ -117,10 +117,13 @@ def bench_batch(steps, warmup, layout="rows"):
     from paper_1701_05431_amd import inputs
     from paper_1701_05431_amd.solver import Batch, params_from
     sizes = inputs.batch_sizes(inputs.BATCH_COUNT, 0)
-    plist = [params_from(inputs.BATCH_256, nx=n, ny=n, layout=LAYOUTS[layout]) for n in sizes]
+    # pitches rounded up to even so that every grid takes two cells per lane
+    plist = [params_from(inputs.BATCH_256, nx=n, ny=n, ld=n + n % 2, layout=LAYOUTS[layout])
+             for n in sizes]
     states = [inputs.riemann_state(n, n, k) for k, n in enumerate(sizes)]
     cells = sum(n * n for n in sizes)
     out = {"workload": inputs.BATCH_256.name, "grids": len(sizes), "cells": cells,
+           "pitch": "nx rounded up to even",
            "steps": steps}
     for name, per_grid in (("persistent", False), ("per_grid", True)):
         b = Batch(plist)

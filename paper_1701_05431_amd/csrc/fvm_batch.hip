@@ -1,13 +1,17 @@
 // fvm_batch.hip -- many independent grids of uneven sizes advanced together.
 //
-// One persistent launch per time step walks a work list of (grid, tile)
-// items, largest grids first, handed out by an atomic queue, so that the
-// small grids fill the gaps the large ones leave and no launch is smaller
-// than the chip. Each item is the single-grid kernel's tile (same device
-// code, so a grid's result is bit-for-bit the one of a single-grid launch).
-// Each grid keeps its own adaptive dt: the item's workgroup folds its
-// speeds into the grid's maxima and the last item of a grid computes that
-// grid's next dt. The last workgroup of the launch rewinds the queue.
+// One persistent launch per time step walks a work list of (grid, group of
+// strips) items, largest grids first, handed out by an atomic queue, so that
+// the small grids fill the gaps the large ones leave and no launch is smaller
+// than the chip. A grid's wave strips (the single-grid kernel's strips, `rows`
+// rows each) are numbered row-major and an item is WPB consecutive strips of
+// one grid, one per wave: a grid narrower than a workgroup stacks its waves
+// over several row blocks instead of leaving them idle. The device code per
+// strip is the single-grid kernel's, so a grid's result is bit-for-bit the
+// one of a single-grid launch. Each grid keeps its own adaptive dt: the item's
+// workgroup folds its speeds into the grid's maxima and the last item of a
+// grid computes that grid's next dt. The last workgroup of the launch rewinds
+// the queue.
 //
 // The reference schedule -- one launch of the single-grid kernel per grid per
 // time step -- is available as fvm_batch_run_per_grid.
@@ -54,9 +58,15 @@ __global__ void batch_log_rewind_kernel(GridScratch* g, int n) {
 
 template <class M, int BC, int WPB>
 __global__ FVM_STEP_BOUNDS(WPB) void batch_kernel(BatchArgs a) {
+  // both lane layouts live in this kernel, so the Euler strips keep one row
+  // of loads in flight (not two) to stay within 256 registers per lane
+  constexpr int kPF = M::NV >= 4 ? 1 : M::kPrefetch2;
   const M m(a.m);
+  const int wave = wave_index();
   __shared__ int s_item;
   for (;;) {
+    // the workgroup's next item, through LDS: every thread reads it after
+    // the barrier
     if (threadIdx.x == 0) s_item = static_cast<int>(atomicAdd(&a.bscr->queue, 1u));
     __syncthreads();
     const int item = s_item;
@@ -71,32 +81,30 @@ __global__ FVM_STEP_BOUNDS(WPB) void batch_kernel(BatchArgs a) {
     GridScratch* s = a.gscr + lo;
     const double dt = s->dt * a.dt_scale;
     const double mux = dt / G.g.dx, muy = dt / G.g.dy;
-    const int tile = item - G.item0;
-    const int tx = tile % G.tiles_x, ty = tile / G.tiles_x;
-    const int wave = wave_index();
-    const bool wide = G.cpl == 2;  // uniform across the workgroup
-    const int xs = (tx * WPB + wave) * (wide ? strip_width(2) : strip_width(1));
-    const int j0 = ty * a.rows;
-    const int j1 = min(j0 + a.rows, G.g.ny);
+    const int k = (item - G.item0) * WPB + wave;  // this wave's strip
     unsigned long long bx = 0, by = 0;
-    if (xs < G.g.nx) {
+    if (k < G.nstrips) {
+      const int sx = k % G.strips_x, ty = k / G.strips_x;
+      const bool wide = G.cpl == 2;  // uniform across the workgroup
+      const int xs = sx * (wide ? strip_width(2) : strip_width(1));
+      const int j0 = ty * a.rows;
+      const int j1 = min(j0 + a.rows, G.g.ny);
+      const double* win = a.win + G.offset;
+      double* wout = a.wout + G.offset;
       if (!wide && FVM_LEGACY_STRIP)
-        march_strip<M, BC>(m, a.win + G.offset, a.wout + G.offset, nullptr, G.g, xs, j0, j1, mux,
-                           muy, dt, bx, by);
+        march_strip<M, BC>(m, win, wout, nullptr, G.g, xs, j0, j1, mux, muy, dt, bx, by);
       else if (!wide && xs + kWave <= G.g.nx)
-        march_strip1<M, BC, false>(m, a.win + G.offset, a.wout + G.offset, nullptr, G.g, xs, j0,
-                                   j1, mux, muy, dt, bx, by);
+        march_strip1<M, BC, false>(m, win, wout, nullptr, G.g, xs, j0, j1, mux, muy, dt, bx, by);
       else if (!wide)
-        march_strip1<M, BC, true>(m, a.win + G.offset, a.wout + G.offset, nullptr, G.g, xs, j0,
-                                  j1, mux, muy, dt, bx, by);
+        march_strip1<M, BC, true>(m, win, wout, nullptr, G.g, xs, j0, j1, mux, muy, dt, bx, by);
       else if (xs + 2 * kWave <= G.g.nx)
-        march_strip2<M, BC, false>(m, a.win + G.offset, a.wout + G.offset, nullptr, G.g, xs, j0,
-                                   j1, mux, muy, dt, bx, by);
+        march_strip2<M, BC, false, kPF>(m, win, wout, nullptr, G.g, xs, j0, j1, mux, muy, dt, bx,
+                                        by);
       else
-        march_strip2<M, BC, true>(m, a.win + G.offset, a.wout + G.offset, nullptr, G.g, xs, j0,
-                                  j1, mux, muy, dt, bx, by);
+        march_strip2<M, BC, true, kPF>(m, win, wout, nullptr, G.g, xs, j0, j1, mux, muy, dt, bx,
+                                       by);
     }
-    if (block_commit<WPB>(bx, by, s, static_cast<unsigned int>(G.ntiles)) && threadIdx.x == 0)
+    if (block_commit<WPB>(bx, by, s, static_cast<unsigned int>(G.nitems)) && threadIdx.x == 0)
       finalize_grid(s, G.g, dt, a.dt_log ? a.dt_log + G.user : nullptr, a.dt_log_cap, a.ngrids,
                     nullptr);
   }
@@ -203,12 +211,13 @@ struct fvm_batch {
       // grid offsets are multiples of 32 elements, the buffers 256-byte
       // aligned)
       r.cpl = p[k].ld % 2 == 0 ? 2 : 1;
-      const int w = strip_width(r.cpl) * wpb;
-      r.tiles_x = (g.nx + w - 1) / w;
+      const int w = strip_width(r.cpl);
+      r.strips_x = (g.nx + w - 1) / w;
       r.tiles_y = (g.ny + rows - 1) / rows;
-      r.ntiles = r.tiles_x * r.tiles_y;
+      r.nstrips = r.strips_x * r.tiles_y;
+      r.nitems = (r.nstrips + wpb - 1) / wpb;
       r.item0 = item;
-      item += r.ntiles;
+      item += r.nitems;
       recs.push_back(r);
     }
     nitems = item;
@@ -415,14 +424,15 @@ static int batch_graph(fvm_batch* b, int kind, int nsteps, double* log, int log_
         a.dt_log_stride = b->n;
         a.mode = kDtAdaptive;
         a.g = r.g;
+        // the single-grid kernel's workgroup tiles
         a.t.rows = b->rows;
         a.t.wpb = b->wpb;
         a.t.cpl = r.cpl;
-        a.t.tiles_x = r.tiles_x;
+        a.t.tiles_x = (r.strips_x + b->wpb - 1) / b->wpb;
         a.t.tiles_y = r.tiles_y;
-        a.t.ntiles = r.ntiles;
+        a.t.ntiles = a.t.tiles_x * a.t.tiles_y;
         a.m = b->m;
-        ok = add(step_kernel_ptr(b->model, b->bc, b->wpb, r.cpl), dim3(r.ntiles),
+        ok = add(step_kernel_ptr(b->model, b->bc, b->wpb, r.cpl), dim3(a.t.ntiles),
                  dim3(b->wpb * kWave),
                  &a);
       }
@@ -528,7 +538,7 @@ int fvm_batch_autotune(fvm_batch* b, const char* cache_path) {
   int br = b->rows, bw = b->wpb;
   int rc = FVM_OK;
   for (int w : {1, 2, 4, 8}) {
-    for (int r : {8, 16, 32, 48, 64, 96}) {
+    for (int r : {8, 16, 32, 48, 64, 96, 128}) {
       rc = fvm_batch_set_tiling(b, r, w);
       if (rc) break;
       hipGraphExec_t exec;

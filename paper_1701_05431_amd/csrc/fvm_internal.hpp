@@ -131,9 +131,13 @@ struct AdjointArgs {
 struct BatchGrid {            // per-grid record in device memory
   size_t offset;              // element offset of the grid inside the packed buffers
   GridGeom g;
-  int tiles_x, tiles_y, ntiles, item0;  // item0: first work item of the grid
-  int user;                            // the caller's index of the grid
-  int cpl;                             // cells per lane of the grid's strips
+  int strips_x;               // wave strips across the grid
+  int tiles_y;                // row blocks
+  int nstrips;                // strips_x * tiles_y wave strips, numbered row-major
+  int nitems;                 // work items: groups of WPB consecutive strips
+  int item0;                  // first work item of the grid
+  int user;                   // the caller's index of the grid
+  int cpl;                    // cells per lane of the grid's strips
 };
 
 struct BatchScratch {         // header of the batch scratch
@@ -154,7 +158,7 @@ struct BatchArgs {
   double* dt_log;             // nullable, dt_log[step * ngrids + grid]
   int dt_log_cap;             // steps the log can hold
   int ngrids;                 // records sorted by item0 (largest grids first)
-  int nitems;
+  int nitems;                 // work items of all grids
   int rows;
   double dt_scale;            // 1; 0 for the tuner's dry runs (state unchanged)
   ModelConsts m;

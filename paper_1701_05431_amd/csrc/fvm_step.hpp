@@ -290,7 +290,7 @@ __device__ __forceinline__ void load_pair(double* a, double* b, const double* __
   }
 }
 
-template <class M, int BC, bool EDGE>
+template <class M, int BC, bool EDGE, int PF = M::kPrefetch2>
 __device__ __forceinline__ void march_strip2(const M& m, const double* __restrict__ win,
                                              double* __restrict__ wout,
                                              const double* __restrict__ ug, const GridGeom& g,
@@ -307,8 +307,7 @@ __device__ __forceinline__ void march_strip2(const M& m, const double* __restric
   const bool oka = !EDGE || xa < g.nx, okb = !EDGE || xb < g.nx;
   const int ch = col_index<BC>(first ? xs - 1 : xs + 2 * kWave, g.nx);
 
-  constexpr int PF = M::kPrefetch2;
-  constexpr int R = PF + 2;
+  constexpr int R = PF + 2;  // PF rows of loads in flight
   double A[R][NV], B[R][NV], H[R][NV], GA[R][NV], GB[R][NV];
   Prim PA[R], PB[R];
   load_pair<NV, BC, EDGE>(A[R - 1], B[R - 1], win, g, ca, cb, j0 - 1);
