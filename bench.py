@@ -35,6 +35,9 @@ METRIC = ("Gcell-updates/s and % HBM roofline (FP64); batched vs per-grid; "
           "adjoint/forward cost")
 KERNEL_SOURCES = ["fvm_kernels.hip", "fvm_step.hpp", "fvm_models.hpp", "fvm_internal.hpp"]
 COUNTERS = os.path.join(ROOT, "profiles", "euler_4096_step_counters.json")
+# tile shapes the autotuner measured on MI355X for these workloads (looked up
+# by device, model, sizes and layout; a miss is tuned and appended)
+TUNING = os.path.join(ROOT, "paper_1701_05431_amd", "tuning_mi355x.txt")
 
 
 def kernel_hash() -> str:
@@ -76,7 +79,7 @@ def bench_euler(args):
     if args.rows or args.wpb:
         s.set_tiling(args.rows, args.wpb)
     elif not args.no_autotune:
-        log(f"euler: autotuned tiling (rows, waves/block, cells/lane) = {s.autotune()}")
+        log(f"euler: autotuned tiling (rows, waves/block, cells/lane) = {s.autotune(args.tuning)}")
     log(f"euler {pre.nx}x{pre.ny}: warmup {args.warmup}")
     s.run(args.warmup)
     torch.cuda.synchronize()
@@ -90,7 +93,7 @@ def bench_euler(args):
                 tiling=s.tiling(), cpl=s.cells_per_lane(), solver=s)
 
 
-def bench_spray(steps, warmup, autotune=True, layout="rows"):
+def bench_spray(steps, warmup, autotune=True, layout="rows", tuning=TUNING):
     import torch
     from paper_1701_05431_amd import inputs
     from paper_1701_05431_amd.solver import Solver, params_from
@@ -98,7 +101,7 @@ def bench_spray(steps, warmup, autotune=True, layout="rows"):
     W, ug = inputs.spray_state(pre.nx, pre.ny, 0)
     s = Solver(params_from(pre, layout=LAYOUTS[layout]), ug=ug)
     s.set_state(torch.from_numpy(W))
-    tiling = s.autotune() if autotune else s.tiling() + (s.cells_per_lane(),)
+    tiling = s.autotune(tuning) if autotune else s.tiling() + (s.cells_per_lane(),)
     s.run(warmup)
     sec = timed(lambda: s.run(steps))
     st = s.sync()
@@ -112,7 +115,7 @@ def bench_spray(steps, warmup, autotune=True, layout="rows"):
                        "cells_per_lane": tiling[2]}}
 
 
-def bench_batch(steps, warmup, layout="rows"):
+def bench_batch(steps, warmup, layout="rows", tuning=TUNING):
     import torch
     from paper_1701_05431_amd import inputs
     from paper_1701_05431_amd.solver import Batch, params_from
@@ -132,7 +135,7 @@ def bench_batch(steps, warmup, layout="rows"):
             # the reference schedule gets its best tile shape too
             cands = [(8, 1), (16, 2), (32, 4), (64, 8)]
         else:
-            b.autotune()
+            b.autotune(tuning)
             cands = [None]
         best = None
         for c in cands:
@@ -155,7 +158,7 @@ def bench_batch(steps, warmup, layout="rows"):
     return out
 
 
-def bench_adjoint(reps, layout="rows"):
+def bench_adjoint(reps, layout="rows", tuning=TUNING):
     import torch
     from paper_1701_05431_amd import inputs
     from paper_1701_05431_amd.solver import Solver, params_from
@@ -166,7 +169,7 @@ def bench_adjoint(reps, layout="rows"):
     s = Solver(params_from(pre, layout=LAYOUTS[layout]))
     Wt = torch.from_numpy(W).cuda()
     s.set_state(Wt)
-    s.autotune()
+    s.autotune(tuning)
     holder = {}
 
     def fwd():
@@ -231,14 +234,17 @@ def cpu_baseline(target_s: float = 12.0):
             "sample": f"{pre.name}: {k} adaptive steps after 1 warm-up step, {t:.1f} s"}
 
 
-def traffic_from_counters(per_launch_bytes: float):
+def traffic_from_counters(tiling: dict, layout: str):
     """HBM bytes per launch from the committed rocprofv3 counter summary,
-    only if it was taken on the current kernel source."""
+    only if it was taken on the current kernel source in the same launch
+    configuration."""
     if not os.path.exists(COUNTERS):
         return None
     with open(COUNTERS) as fh:
         c = json.load(fh)
-    if c.get("kernel_hash") != kernel_hash():
+    if c.get("kernel_hash") != kernel_hash() or c.get("tiling") != tiling:
+        return None
+    if c.get("layout") != layout:
         return None
     return c.get("bytes_per_launch")
 
@@ -264,6 +270,8 @@ def main():
     ap.add_argument("--only", choices=["spray", "batch", "adjoint", "advection"],
                     help="run just this secondary workload (for profiling) and print its record")
     ap.add_argument("--no-autotune", action="store_true")
+    ap.add_argument("--tuning", default=TUNING,
+                    help="autotuner cache file (tile shapes measured on this device)")
     ap.add_argument("--layout", choices=sorted(LAYOUTS), default="rows",
                     help="state storage: one plane per variable, or the variables' rows "
                          "interleaved per grid row")
@@ -282,16 +290,18 @@ def main():
         return
     if args.only:
         run = {"spray": lambda: bench_spray(args.steps, args.warmup, not args.no_autotune,
-                                            args.layout),
-               "batch": lambda: bench_batch(args.steps, args.warmup, args.layout),
-               "adjoint": lambda: bench_adjoint(1, args.layout),
+                                            args.layout, args.tuning),
+               "batch": lambda: bench_batch(args.steps, args.warmup, args.layout, args.tuning),
+               "adjoint": lambda: bench_adjoint(1, args.layout, args.tuning),
                "advection": lambda: bench_advection(args.steps)}[args.only]
         print(json.dumps(run()), flush=True)
         return
 
     e = bench_euler(args)
     value = e["cells"] * args.steps / e["sec"] / 1e9
-    traffic = traffic_from_counters(64.0 * e["cells"])
+    tiling = {"rows_per_strip": e["tiling"][0], "waves_per_block": e["tiling"][1],
+              "cells_per_lane": e["cpl"]}
+    traffic = traffic_from_counters(tiling, args.layout)
     roof = {"bound": "hbm", "achieved": e["achieved"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": e["achieved"] / HBM_PEAK_GBS, "traffic": traffic,
             "kernel": "fvm::step_kernel<Euler, transmissive>",
@@ -301,11 +311,11 @@ def main():
     work = {}
     if not args.only_euler:
         log("spray")
-        work["spray"] = bench_spray(200, 10, layout=args.layout)
+        work["spray"] = bench_spray(200, 10, layout=args.layout, tuning=args.tuning)
         log("batch")
-        work["batch"] = bench_batch(100, 4, args.layout)
+        work["batch"] = bench_batch(100, 4, args.layout, args.tuning)
         log("adjoint")
-        work["adjoint"] = bench_adjoint(3, args.layout)
+        work["adjoint"] = bench_adjoint(3, args.layout, args.tuning)
         log("advection")
         work["advection"] = bench_advection(100)
     cpu = None
@@ -328,8 +338,7 @@ def main():
         "config": {"workload": "euler_4096x4096", "nx": 4096, "ny": 4096, "nvar": 4,
                    "flux": "rusanov", "bc": "transmissive", "cfl": 0.45, "subdomains": "8x8",
                    "init": "four-quadrant Riemann, seed 0", "layout": args.layout,
-                   "tiling": {"rows_per_strip": e["tiling"][0], "waves_per_block": e["tiling"][1],
-                              "cells_per_lane": e["cpl"]}},
+                   "tiling": tiling},
         "roofline": roof,
         "cpu_baseline": cpu,
         "workloads": work,

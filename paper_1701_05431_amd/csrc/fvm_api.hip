@@ -644,7 +644,7 @@ int fvm_autotune(fvm_grid* g, const char* cache_path) {
   }
   const int cpls[2] = {2, 1};
   const int wpbs[4] = {1, 2, 4, 8};
-  const int rowss[8] = {4, 8, 16, 32, 48, 64, 96, 128};
+  const int rowss[10] = {4, 8, 16, 32, 48, 64, 96, 128, 192, 256};
   double best = 1e300;
   int br = g->rows, bw = g->wpb, bc = g->cpl;
   const int save_req = g->cpl_req;
