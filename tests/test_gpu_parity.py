@@ -10,6 +10,7 @@ the work decomposition (subdomain counts, tile shapes, batched vs single
 launches) are compared bit for bit.
 """
 import math
+import os
 
 import numpy as np
 import pytest
@@ -21,6 +22,8 @@ from paper_1701_05431_amd import _lib
 from paper_1701_05431_amd.solver import Batch, Solver, params_from, fvrun
 
 pytestmark = pytest.mark.gpu
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
 TOL = 1e-12
 DT_ULP = 4
@@ -429,12 +432,21 @@ def test_fvrun_gradient_matches_oracle_and_fd():
 # the full-size Euler workload in the benchmark's launch configuration
 # ---------------------------------------------------------------------------
 
-def test_euler_4096_full_size_one_step_parity():
+TUNING = os.path.join(ROOT, "paper_1701_05431_amd", "tuning_mi355x.txt")
+
+
+@pytest.mark.parametrize("bench_config", [False, True])
+def test_euler_4096_full_size_one_step_parity(bench_config):
+    """One step of the 4096^2 workload after 20 steps, against the oracle:
+    planar storage with the default tiling, and the benchmark's launch
+    configuration (row-interleaved storage, the tuned tile shape)."""
     pre = inputs.EULER_4096
-    p = params_from(pre)
+    p = params_from(pre, layout=_lib.FVM_LAYOUT_ROWS if bench_config else _lib.FVM_LAYOUT_PLANES)
     W = inputs.riemann_state(pre.nx, pre.ny, 0)
     s = Solver(p)
     s.set_state(W)
+    if bench_config:
+        print(f"euler 4096 bench tiling {s.autotune(TUNING)}", flush=True)
     s.run(20)
     Wk = gpu_state(s)
     dts = s.run(1, record_dt=True).cpu().numpy()
@@ -445,3 +457,63 @@ def test_euler_4096_full_size_one_step_parity():
     assert ulps(dts[0], odt) <= DT_ULP
     ref = orc.run_dts(P, Wk, dts)
     assert rel_linf(got, ref) <= TOL
+
+
+def test_spray_2048_full_size_bench_config():
+    """Two steps of the 2048^2 spray workload in the benchmark's launch
+    configuration against the oracle with the same dts."""
+    pre = inputs.SPRAY_2048
+    W, ug = inputs.spray_state(pre.nx, pre.ny, 0)
+    p = params_from(pre, layout=_lib.FVM_LAYOUT_ROWS)
+    s = Solver(p, ug=ug)
+    s.set_state(W)
+    print(f"spray 2048 bench tiling {s.autotune(TUNING)}", flush=True)
+    dts = s.run(2, record_dt=True).cpu().numpy()
+    got = gpu_state(s)
+    P = oparams(p)
+    orc.set_threads(16)
+    ref = orc.run_dts(P, W, dts, ug=ug)
+    assert rel_linf(got, ref) <= TOL
+    _, _, odt = orc.cfl(P, W)
+    assert ulps(dts[0], odt) <= DT_ULP
+
+
+def test_batch_256_full_workload_bench_config():
+    """The 256-grid workload as the benchmark runs it (even pitches, row
+    storage, tuned persistent tiling): 3 steps, the largest, a middle and the
+    smallest grid against the oracle, every grid's dts against its own
+    single-grid run's."""
+    sizes = inputs.batch_sizes(inputs.BATCH_COUNT, 0)
+    plist = [params_from(inputs.BATCH_256, nx=n, ny=n, ld=n + n % 2, layout=_lib.FVM_LAYOUT_ROWS)
+             for n in sizes]
+    states = [inputs.riemann_state(n, n, k) for k, n in enumerate(sizes)]
+    b = Batch(plist)
+    b.set_states(states)
+    b.autotune(TUNING)
+    b.set_states(states)
+    dts = b.run(3, record_dt=True).cpu().numpy()
+    got = b.states()
+    order = sorted(range(len(sizes)), key=lambda k: sizes[k])
+    orc.set_threads(16)
+    for k in (order[-1], order[len(order) // 2], order[0]):
+        print(f"batch grid {k} n={sizes[k]}", flush=True)
+        ref = orc.run_dts(oparams(plist[k]), states[k], dts[:, k])
+        assert rel_linf(got[k].cpu().numpy(), ref) <= TOL, k
+        _, _, odt = orc.cfl(oparams(plist[k]), states[k])
+        assert ulps(dts[0, k], odt) <= DT_ULP, k
+
+
+def test_adjoint_1024_full_size_step():
+    """One adjoint step of the 1024^2 workload's state in the benchmark's
+    storage layout against the oracle."""
+    pre = inputs.ADJOINT_1024
+    W = inputs.riemann_state(pre.nx, pre.ny, 0)
+    p = params_from(pre, layout=_lib.FVM_LAYOUT_ROWS)
+    lam = np.random.default_rng(3).standard_normal(W.shape)
+    P = oparams(p)
+    orc.set_threads(16)
+    _, _, dt = orc.cfl(P, W)
+    got = Solver(p).adjoint_step(W, dt, lam)
+    torch.cuda.synchronize()
+    ref = orc.adjoint_step(P, W, dt, lam)
+    assert rel_linf(got[:, :, :pre.nx].cpu().numpy(), ref) <= TOL
