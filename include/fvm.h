@@ -171,6 +171,14 @@ int fvm_run(fvm_grid* g, int nsteps, double* dts_dev);
  * frozen-dt replay used by the adjoint and by finite-difference checks. */
 int fvm_run_dts(fvm_grid* g, int nsteps, const double* dts_dev);
 
+/* nsteps steps with one fixed time step dt (> 0, finite), the policy of
+ * Sec. 2.2.1: before each step the state's largest speed is checked against
+ * eq. CFL_cond, dt * max(Sx, Sy) <= min(dx, dy), as the checkTimeStep task
+ * does (Sec. 4.2). A step that fails the check leaves the state unchanged and
+ * sets the sticky FVM_ECFL status (so does every later step of the run); the
+ * next synchronising call reports it. Replays a cached HIP graph. */
+int fvm_run_fixed(fvm_grid* g, int nsteps, double dt);
+
 /* As fvm_run, and stores checkpoints: ckpts[s] (host array of device
  * pointers, ceil(nsteps / ckpt_every) of them, each a full state in the grid's
  * ld and layout) receives W^{s * ckpt_every}. The step that produces a checkpointed

@@ -57,6 +57,7 @@ SIGNATURES = {
     "fvm_step": (C.c_int, [_V, C.c_double]),
     "fvm_run": (C.c_int, [_V, C.c_int, _V]),
     "fvm_run_dts": (C.c_int, [_V, C.c_int, _V]),
+    "fvm_run_fixed": (C.c_int, [_V, C.c_int, C.c_double]),
     "fvm_run_ckpt": (C.c_int, [_V, C.c_int, C.c_int, C.POINTER(_V), _V]),
     "fvm_sync": (C.c_int, [_V]),
     "fvm_get_status": (C.c_int, [_V, C.c_int]),

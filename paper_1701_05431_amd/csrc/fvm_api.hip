@@ -155,7 +155,7 @@ int status_from_bits(unsigned int st) {
 }
 
 struct GraphKey {
-  int kind;              // 0 adaptive run, 1 dts run
+  int kind;              // 0 adaptive run, 1 dts run, 2 tuner's dry run, 3 fixed-dt run
   int nsteps;
   const double* start;   // input buffer of the first step
   const double* other;
@@ -163,10 +163,11 @@ struct GraphKey {
   const double* log;
   int k0;
   int rows, wpb, cpl;
+  double dt;             // kind 3
   bool operator==(const GraphKey& o) const {
     return kind == o.kind && nsteps == o.nsteps && start == o.start && other == o.other &&
            dts == o.dts && log == o.log && k0 == o.k0 && rows == o.rows && wpb == o.wpb &&
-           cpl == o.cpl;
+           cpl == o.cpl && dt == o.dt;
   }
 };
 
@@ -419,8 +420,8 @@ int fvm_step(fvm_grid* g, double dt) {
 // Builds (or finds) the graph of `n` consecutive steps starting from buffer
 // `start`, with step k reading its dt according to `mode`.
 static int graph_for(fvm_grid* g, int kind, int n, double* start, const double* dts, int k0,
-                     double* log, int log_cap, hipGraphExec_t* exec) {
-  GraphKey key{kind, n, start, g->other(start), dts, log, k0, g->rows, g->wpb, g->cpl};
+                     double* log, int log_cap, hipGraphExec_t* exec, double dt = 0.0) {
+  GraphKey key{kind, n, start, g->other(start), dts, log, k0, g->rows, g->wpb, g->cpl, dt};
   for (auto it = g->graphs.begin(); it != g->graphs.end(); ++it) {
     if (it->key == key) {
       g->graphs.splice(g->graphs.begin(), g->graphs, it);
@@ -437,8 +438,10 @@ static int graph_for(fvm_grid* g, int kind, int n, double* start, const double* 
   std::vector<StepArgs> args(n);
   for (int s = 0; s < n; ++s) {
     double* out = g->other(in);
-    args[s] = g->step_args(in, out, kind == 0 ? kDtAdaptive : kDtArray);
+    args[s] = g->step_args(in, out,
+                           kind == 0 ? kDtAdaptive : (kind == 3 ? kDtFixedCheck : kDtArray));
     args[s].dts = dts;
+    args[s].dt_arg = dt;
     args[s].k = kind == 2 ? 0 : k0 + s;  // kind 2: dry run, dts = the scratch's zero
     args[s].dt_log = log;
     args[s].dt_log_cap = log_cap;
@@ -474,9 +477,11 @@ static int graph_for(fvm_grid* g, int kind, int n, double* start, const double* 
   return FVM_OK;
 }
 
-static int run_steps(fvm_grid* g, int kind, int nsteps, const double* dts, double* log) {
+static int run_steps(fvm_grid* g, int kind, int nsteps, const double* dts, double* log,
+                     double dt = 0.0) {
   int rc = FVM_OK;
-  if (kind == 0 && !g->speeds_valid) rc = enqueue_cfl(g, nullptr);
+  // adaptive steps and checked fixed steps read the current state's maxima
+  if ((kind == 0 || kind == 3) && !g->speeds_valid) rc = enqueue_cfl(g, nullptr);
   if (rc) return rc;
   if (log) rc = dev_err(launch_clear_log_cursor(g->scr, g->stream));
   if (rc) return rc;
@@ -484,7 +489,8 @@ static int run_steps(fvm_grid* g, int kind, int nsteps, const double* dts, doubl
   while (done < nsteps) {
     const int n = std::min(kGraphChunk, nsteps - done);
     hipGraphExec_t exec;
-    rc = graph_for(g, kind, n, g->cur, dts, kind == 1 ? done : 0, log, log ? nsteps : 0, &exec);
+    rc = graph_for(g, kind, n, g->cur, dts, kind == 1 ? done : 0, log, log ? nsteps : 0, &exec,
+                   dt);
     if (rc) return rc;
     rc = dev_err(hipGraphLaunch(exec, g->stream));
     if (rc) return rc;
@@ -498,6 +504,12 @@ static int run_steps(fvm_grid* g, int kind, int nsteps, const double* dts, doubl
 int fvm_run(fvm_grid* g, int nsteps, double* dts_dev) {
   if (!g || !g->bound || nsteps < 0) return FVM_EINVAL;
   return run_steps(g, 0, nsteps, nullptr, dts_dev);
+}
+
+int fvm_run_fixed(fvm_grid* g, int nsteps, double dt) {
+  if (!g || !g->bound || nsteps < 0) return FVM_EINVAL;
+  if (!(dt > 0.0) || !std::isfinite(dt)) return FVM_EINVAL;
+  return run_steps(g, 3, nsteps, nullptr, nullptr, dt);
 }
 
 int fvm_run_dts(fvm_grid* g, int nsteps, const double* dts_dev) {

@@ -153,6 +153,13 @@ class Solver:
         check(lib().fvm_run(self.h, int(nsteps), _ptr(dts)), "fvm_run")
         return dts[:nsteps] if record_dt else None
 
+    def run_fixed(self, nsteps: int, dt: float) -> None:
+        """nsteps steps of one fixed dt, each checked against the CFL
+        condition first (a failed check leaves the state unchanged and is
+        reported by sync() as FVM_ECFL)."""
+        self._bind_stream()
+        check(lib().fvm_run_fixed(self.h, int(nsteps), float(dt)), "fvm_run_fixed")
+
     def run_dts(self, dts) -> None:
         dts = torch.as_tensor(dts, dtype=torch.float64).to(self.device).contiguous()
         self._bind_stream()

@@ -253,6 +253,68 @@ def test_fixed_dt_step_and_cfl_check():
     assert s.status() == 0
 
 
+def test_fixed_dt_run_checks_every_step():
+    """fvm_run_fixed: every step checked against the CFL condition, each
+    step the oracle's fixed-dt step; a run whose dt fails the check leaves
+    the state unchanged and reports FVM_ECFL."""
+    nx, ny = 96, 80
+    W = inputs.riemann_state(nx, ny, 4)
+    p = params_from(model=1, bc=1, nx=nx, ny=ny, npart_x=4, npart_y=2)
+    P = oparams(p)
+    s = Solver(p)
+    s.set_state(W)
+    dt, sx, sy = s.cfl_dt()
+    lim = min(1.0 / nx, 1.0 / ny) / max(sx, sy)
+    s.run_fixed(12, 0.5 * lim)
+    assert s.sync() == 0
+    ref = W.copy()
+    for _ in range(12):
+        rc, ref = orc.step_fixed(P, ref, 0.5 * lim)
+        assert rc == 0
+    assert rel_linf(gpu_state(s), ref) <= TOL
+    before = gpu_state(s)
+    s.run_fixed(3, 4.0 * lim)
+    assert s.sync() == _lib.FVM_ECFL
+    assert np.array_equal(gpu_state(s), before)
+    rc, _ = orc.step_fixed(P, ref, 4.0 * lim)
+    assert rc == orc.ECFL
+
+
+@pytest.mark.parametrize("case", ["cosine", "vortex"])
+def test_paper_test_cases_converge_on_gpu(case):
+    """The paper's two analytic Euler cases (Sec. 5.1) run on the GPU with the
+    paper's fixed-dt policy to T = 0.2: the state at 128^2 is the oracle's,
+    and the L1 and L2 errors against the exact solution fall with the order
+    the paper prints (about 0.95, Sec. 5.1.3)."""
+    import json
+    paper = json.load(open(os.path.join(ROOT, "tests", "golden", "paper_numbers.json")))
+    slope_paper = paper["convergence_slope"]["value"]
+    fn = {"cosine": inputs.localized_cosine_primitives,
+          "vortex": inputs.isentropic_vortex_primitives}[case]
+    T = 0.2
+    errs = []
+    for n in (64, 128, 256, 512):
+        W0 = inputs.conservative_from_primitive(*fn(n, n, 0.0))
+        p = params_from(model=1, bc=0, nx=n, ny=n, npart_x=2, npart_y=2, cfl=0.4)
+        s = Solver(p)
+        s.set_state(W0)
+        dt, _, _ = s.cfl_dt()
+        steps = int(math.ceil(T / dt))
+        s.run_fixed(steps, T / steps)
+        assert s.sync() == 0
+        W = gpu_state(s)
+        if n == 128:
+            ref = orc.run_dts(oparams(p), W0, [T / steps] * steps)
+            assert rel_linf(W, ref) <= 1e-11, rel_linf(W, ref)
+        e = W[0] - fn(n, n, T)[0]
+        errs.append((np.mean(np.abs(e)), math.sqrt(np.mean(e * e))))
+    print(f"{case} errors {errs}", flush=True)
+    for k in range(2):
+        for a, b in ((1, 2), (2, 3)):
+            slope = math.log2(errs[a][k] / errs[b][k])
+            assert abs(slope - slope_paper) < 0.15, (case, k, a, slope, errs)
+
+
 @pytest.mark.parametrize("what", ["nan", "rho", "p"])
 def test_nonfinite_state_is_reported(what):
     n = 32
