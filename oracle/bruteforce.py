@@ -17,14 +17,27 @@ import math
 import numpy as np
 
 ADV, EULER, SPRAY = 0, 1, 2
-PERIODIC, TRANSMISSIVE = 0, 1
+PERIODIC, TRANSMISSIVE, DIRICHLET = 0, 1, 2
 TINY = 1e-300
 
 
-def _neighbours(W, axis, bc):
-    """(left, right) neighbour arrays along a spatial axis (2 = x, 1 = y)."""
+def _neighbours(W, axis, bc, ghost=None):
+    """(left, right) neighbour arrays along a spatial axis (2 = x, 1 = y).
+    Dirichlet: ghost is (nVar, 4) states west, east, south, north; the
+    neighbour beyond each side is that side's state."""
     if bc == PERIODIC:
         return np.roll(W, 1, axis=axis), np.roll(W, -1, axis=axis)
+    if bc == DIRICHLET:
+        g = np.asarray(ghost, dtype=np.float64)
+        lo, hi = (0, 1) if axis == 2 else (2, 3)
+        shape = list(W.shape)
+        shape[axis] = 1
+        gl = np.broadcast_to(g[:, lo].reshape(-1, 1, 1), shape)
+        gr = np.broadcast_to(g[:, hi].reshape(-1, 1, 1), shape)
+        n = W.shape[axis]
+        left = np.concatenate([gl, np.take(W, np.arange(n - 1), axis=axis)], axis=axis)
+        right = np.concatenate([np.take(W, np.arange(1, n), axis=axis), gr], axis=axis)
+        return left, right
     n = W.shape[axis]
     idx_l = np.clip(np.arange(n) - 1, 0, n - 1)
     idx_r = np.clip(np.arange(n) + 1, 0, n - 1)
@@ -95,14 +108,16 @@ def spray_source(W, ug, K, theta, s_eps):
 
 
 def step(model, W, dt, *, bc=PERIODIC, lx=1.0, ly=1.0, gamma=1.4,
-         a=(0.0, 0.0), ug=None, K=1.0, theta=0.1, s_eps=0.01):
-    """One step W^n -> W^{n+1} with the given dt on the whole grid."""
+         a=(0.0, 0.0), ug=None, K=1.0, theta=0.1, s_eps=0.01, ghost=None):
+    """One step W^n -> W^{n+1} with the given dt on the whole grid
+    (ghost: Dirichlet states, 4 x nVar, west, east, south, north)."""
     W = np.asarray(W, dtype=np.float64)
     nx, ny = W.shape[2], W.shape[1]
     mux = dt / (lx / nx)
     muy = dt / (ly / ny)
-    Wl, Wr = _neighbours(W, 2, bc)
-    Ws, Wn = _neighbours(W, 1, bc)
+    gT = None if ghost is None else np.asarray(ghost, dtype=np.float64).T
+    Wl, Wr = _neighbours(W, 2, bc, gT)
+    Ws, Wn = _neighbours(W, 1, bc, gT)
     FE = num_flux(model, W, Wr, 0, gamma, a)
     FW = num_flux(model, Wl, W, 0, gamma, a)
     GN = num_flux(model, W, Wn, 1, gamma, a)

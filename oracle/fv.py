@@ -14,7 +14,7 @@ import numpy as np
 from . import build as _build
 
 ADV, EULER, SPRAY = 0, 1, 2
-PERIODIC, TRANSMISSIVE = 0, 1
+PERIODIC, TRANSMISSIVE, DIRICHLET = 0, 1, 2
 OK, EINVAL, ECFL, ENONFINITE, EUNSUPPORTED = 0, -1, -3, -4, -5
 NVAR = {ADV: 1, EULER: 4, SPRAY: 6}
 
@@ -33,15 +33,24 @@ class Params(C.Structure):
         ("gamma", C.c_double), ("ax", C.c_double), ("ay", C.c_double),
         ("K", C.c_double), ("theta", C.c_double), ("s_eps", C.c_double),
         ("cfl", C.c_double), ("dt_max", C.c_double),
+        ("ghost", (C.c_double * 6) * 4),  # Dirichlet: west, east, south, north
     ]
 
 
 def params(model: int, nx: int, ny: int, *, bc: int = PERIODIC, npx: int = 1,
            npy: int = 1, lx: float = 1.0, ly: float = 1.0, gamma: float = 1.4,
            ax: float = 0.0, ay: float = 0.0, K: float = 1.0, theta: float = 0.1,
-           s_eps: float = 0.01, cfl: float = 0.45, dt_max: float = 0.0) -> Params:
-    return Params(model, bc, nx, ny, npx, npy, lx, ly, gamma, ax, ay, K, theta,
-                  s_eps, cfl, dt_max)
+           s_eps: float = 0.01, cfl: float = 0.45, dt_max: float = 0.0,
+           ghost=None) -> Params:
+    """ghost: Dirichlet states, 4 x nVar (west, east, south, north)."""
+    P = Params(model, bc, nx, ny, npx, npy, lx, ly, gamma, ax, ay, K, theta,
+               s_eps, cfl, dt_max)
+    if ghost is not None:
+        g = np.asarray(ghost, dtype=np.float64)
+        for side in range(4):
+            for v in range(g.shape[1]):
+                P.ghost[side][v] = g[side, v]
+    return P
 
 
 def from_preset(p, **over) -> Params:

@@ -46,6 +46,9 @@
  *      in a reference it cites) is replaced by a lognormal fit to
  *      (m_0, m_{1/2}, m_{2/2}); n(S=0) is read as the fitted density at S_eps.
  *   R7 transmissive boundaries: a ghost cell equal to the boundary cell.
+ *      Dirichlet boundaries (mentioned in Sec. 4.2 for the overlap of a
+ *      subdomain at the domain's edge): the ghost cell holds a prescribed
+ *      state, one constant state per side of the domain.
  *   R8 the adjoint (not in the paper) is the exact transpose of the
  *      implemented transport step with dt held fixed; max() follows the left
  *      argument on ties and d|x|/dx = +1 at x = 0.
@@ -58,7 +61,8 @@
 #endif
 
 enum { ORC_ADV = 0, ORC_EULER = 1, ORC_SPRAY = 2 };
-enum { ORC_PERIODIC = 0, ORC_TRANSMISSIVE = 1 };
+enum { ORC_PERIODIC = 0, ORC_TRANSMISSIVE = 1, ORC_DIRICHLET = 2 };
+enum { ORC_WEST = 0, ORC_EAST = 1, ORC_SOUTH = 2, ORC_NORTH = 3 };
 enum {
   ORC_OK = 0,
   ORC_EINVAL = -1,
@@ -76,6 +80,7 @@ typedef struct {
   double gamma, ax, ay;
   double K, theta, s_eps;
   double cfl, dt_max;
+  double ghost[4][ORC_MAXV];  /* Dirichlet ghost states: west, east, south, north */
 } orc_params;
 
 int orc_nvar(int model)
@@ -92,7 +97,8 @@ int orc_validate(const orc_params* P)
 {
   if (!P) return ORC_EINVAL;
   if (orc_nvar(P->model) == 0) return ORC_EINVAL;
-  if (P->bc != ORC_PERIODIC && P->bc != ORC_TRANSMISSIVE) return ORC_EINVAL;
+  if (P->bc != ORC_PERIODIC && P->bc != ORC_TRANSMISSIVE && P->bc != ORC_DIRICHLET)
+    return ORC_EINVAL;
   if (P->nx < 1 || P->ny < 1 || P->npx < 1 || P->npy < 1) return ORC_EINVAL;
   /* balanced parts NxLoc = Nx/NPartX, NyLoc = Ny/NPartY (Sec. 3.2) */
   if (P->nx % P->npx != 0 || P->ny % P->npy != 0) return ORC_EINVAL;
@@ -404,8 +410,9 @@ static void task_check_time_step(const orc_solver* S, orc_part* p)
  * of the south neighbour, its east column to ovlpW of the east neighbour and
  * its west column to ovlpE of the west neighbour (Sec. 4.2). On a physical
  * transmissive boundary the subdomain fills its own strip with its own
- * border (ghost = boundary cell, reading R7); on a periodic boundary the
- * neighbour wraps around (it may be the subdomain itself). */
+ * border (ghost = boundary cell, reading R7), on a Dirichlet boundary with
+ * the side's prescribed state; on a periodic boundary the neighbour wraps
+ * around (it may be the subdomain itself). */
 static void task_copy_overlaps(orc_solver* S, int q)
 {
   const orc_params* P = &S->P;
@@ -413,6 +420,7 @@ static void task_copy_overlaps(orc_solver* S, int q)
   int px = q % P->npx, py = q / P->npx;
   int nv = S->nv, nxl = p->nxl, nyl = p->nyl;
   int per = (P->bc == ORC_PERIODIC);
+  int dir = (P->bc == ORC_DIRICHLET);
 
   /* north row -> ovlpS of the north neighbour */
   if (py + 1 < P->npy || per) {
@@ -421,7 +429,8 @@ static void task_copy_overlaps(orc_solver* S, int q)
       for (int i = 0; i < nxl; ++i) nb->ovS[v * nxl + i] = U_(p, v, nyl - 1, i);
   } else {
     for (int v = 0; v < nv; ++v)
-      for (int i = 0; i < nxl; ++i) p->ovN[v * nxl + i] = U_(p, v, nyl - 1, i);
+      for (int i = 0; i < nxl; ++i)
+        p->ovN[v * nxl + i] = dir ? P->ghost[ORC_NORTH][v] : U_(p, v, nyl - 1, i);
   }
   /* south row -> ovlpN of the south neighbour */
   if (py > 0 || per) {
@@ -430,7 +439,8 @@ static void task_copy_overlaps(orc_solver* S, int q)
       for (int i = 0; i < nxl; ++i) nb->ovN[v * nxl + i] = U_(p, v, 0, i);
   } else {
     for (int v = 0; v < nv; ++v)
-      for (int i = 0; i < nxl; ++i) p->ovS[v * nxl + i] = U_(p, v, 0, i);
+      for (int i = 0; i < nxl; ++i)
+        p->ovS[v * nxl + i] = dir ? P->ghost[ORC_SOUTH][v] : U_(p, v, 0, i);
   }
   /* east column -> ovlpW of the east neighbour */
   if (px + 1 < P->npx || per) {
@@ -439,7 +449,8 @@ static void task_copy_overlaps(orc_solver* S, int q)
       for (int j = 0; j < nyl; ++j) nb->ovW[v * nyl + j] = U_(p, v, j, nxl - 1);
   } else {
     for (int v = 0; v < nv; ++v)
-      for (int j = 0; j < nyl; ++j) p->ovE[v * nyl + j] = U_(p, v, j, nxl - 1);
+      for (int j = 0; j < nyl; ++j)
+        p->ovE[v * nyl + j] = dir ? P->ghost[ORC_EAST][v] : U_(p, v, j, nxl - 1);
   }
   /* west column -> ovlpE of the west neighbour */
   if (px > 0 || per) {
@@ -448,7 +459,8 @@ static void task_copy_overlaps(orc_solver* S, int q)
       for (int j = 0; j < nyl; ++j) nb->ovE[v * nyl + j] = U_(p, v, j, 0);
   } else {
     for (int v = 0; v < nv; ++v)
-      for (int j = 0; j < nyl; ++j) p->ovW[v * nyl + j] = U_(p, v, j, 0);
+      for (int j = 0; j < nyl; ++j)
+        p->ovW[v * nyl + j] = dir ? P->ghost[ORC_WEST][v] : U_(p, v, j, 0);
   }
 }
 
@@ -824,7 +836,7 @@ int orc_adjoint_step(const orc_params* P, const double* W, double dt,
 {
   int rc = orc_validate(P);
   if (rc) return rc;
-  if (P->model == ORC_SPRAY) return ORC_EUNSUPPORTED;
+  if (P->model == ORC_SPRAY || P->bc == ORC_DIRICHLET) return ORC_EUNSUPPORTED;
   int nv = orc_nvar(P->model), nx = P->nx, ny = P->ny;
   size_t plane = (size_t)nx * ny;
   double mu[2] = {dt / (P->lx / nx), dt / (P->ly / ny)};
@@ -880,7 +892,7 @@ int orc_adjoint_run(const orc_params* P, const double* W0, int nsteps,
 {
   int rc = orc_validate(P);
   if (rc) return rc;
-  if (P->model == ORC_SPRAY) return ORC_EUNSUPPORTED;
+  if (P->model == ORC_SPRAY || P->bc == ORC_DIRICHLET) return ORC_EUNSUPPORTED;
   int nv = orc_nvar(P->model);
   size_t n = (size_t)nv * P->nx * P->ny;
   double* states = (double*)malloc(sizeof(double) * n * (nsteps > 0 ? nsteps : 1));

@@ -173,6 +173,101 @@ def test_spray_partitions_bitwise_and_whole_grid(orc):
 
 
 # --------------------------------------------------------------------------
+# Dirichlet boundaries (a prescribed ghost state per side)
+# --------------------------------------------------------------------------
+
+def _euler_ghosts():
+    prims = [(0.6, 0.2, -0.1, 0.5), (1.1, -0.3, 0.05, 0.9), (0.8, 0.1, 0.25, 0.4),
+             (0.4, -0.05, -0.2, 0.7)]  # west, east, south, north
+    return np.stack([inputs.conservative_from_primitive(*q) for q in prims])
+
+
+@pytest.mark.parametrize("model", [0, 1])
+def test_dirichlet_partitions_equal_whole_grid_bitwise(orc, model):
+    """The subdomain tasks with prescribed ghost states are the whole-grid
+    formula with the domain padded by those states, at every partition."""
+    n = 8
+    if model == 0:
+        W = inputs.advection_state(n, n, 6)
+        kw = dict(ax=0.8, ay=-0.3)
+        ghost = np.array([[0.3], [-0.2], [1.1], [0.7]])
+    else:
+        W = inputs.riemann_state(n, n, 6)
+        kw = {}
+        ghost = _euler_ghosts()
+    for npx, npy in PARTS:
+        P = orc.params(model, n, n, bc=orc.DIRICHLET, npx=npx, npy=npy, cfl=0.45, ghost=ghost,
+                       **kw)
+        got, dts = orc.run(P, W, 6)
+        ref = W.copy()
+        for dt in dts:
+            ref = bf.step(model, ref, dt, bc=bf.DIRICHLET, ghost=ghost,
+                          a=(kw.get("ax", 0.0), kw.get("ay", 0.0)))
+        assert np.array_equal(got, ref), (npx, npy)
+
+
+def test_dirichlet_uniform_state_matching_its_ghosts_is_fixed(orc):
+    n = 12
+    w = inputs.conservative_from_primitive(0.7, 0.3, -0.2, 0.6)
+    W = np.broadcast_to(w[:, None, None], (4, n, n)).copy()
+    P = orc.params(orc.EULER, n, n, bc=orc.DIRICHLET, npx=3, npy=2, ghost=np.stack([w] * 4))
+    got, _ = orc.run(P, W, 5)
+    assert np.array_equal(got, W)
+
+
+def test_dirichlet_equals_transmissive_until_waves_reach_the_boundary(orc):
+    """Ghosts equal to the boundary cells' initial states: the step is the
+    transmissive one as long as the boundary cells keep those states."""
+    n = 32
+    W = inputs.riemann_state(n, n, 9)
+    ghost = np.stack([W[:, n // 2, 0], W[:, n // 2, -1], W[:, 0, n // 2], W[:, -1, n // 2]])
+    # make each boundary side uniform (the quadrant states differ along a side)
+    W[:, :, 0] = ghost[0][:, None]
+    W[:, :, -1] = ghost[1][:, None]
+    W[:, 0, :] = ghost[2][:, None]
+    W[:, -1, :] = ghost[3][:, None]
+    Pd = orc.params(orc.EULER, n, n, bc=orc.DIRICHLET, npx=2, npy=2, ghost=ghost)
+    Pt = orc.params(orc.EULER, n, n, bc=orc.TRANSMISSIVE, npx=2, npy=2)
+    _, _, dt = orc.cfl(Pt, W)
+    # corners hold two different side states; compare away from them, and
+    # only one step (the first step only reads the initial boundary cells)
+    a = orc.run_dts(Pd, W, [dt])
+    b = orc.run_dts(Pt, W, [dt])
+    assert np.array_equal(a[:, 2:-2, 2:-2], b[:, 2:-2, 2:-2])
+    assert np.array_equal(a[:, 1:-1, 1:-1], b[:, 1:-1, 1:-1])
+
+
+def test_dirichlet_boundary_flux_balance(orc):
+    """Sum of the change over the grid = the fluxes through the four sides,
+    each a two-point flux between a boundary cell and its side's ghost."""
+    n = 16
+    W0 = inputs.riemann_state(n, n, 12)
+    ghost = _euler_ghosts()
+    P = orc.params(orc.EULER, n, n, bc=orc.DIRICHLET, npx=2, npy=2, ghost=ghost)
+    _, _, dt = orc.cfl(P, W0)
+    W1 = orc.run_dts(P, W0, [dt])
+    mu = dt * n
+    flux_in = np.zeros(4)
+    for j in range(n):
+        flux_in += mu * orc.num_flux(P, ghost[0], W0[:, j, 0], 0)
+        flux_in -= mu * orc.num_flux(P, W0[:, j, -1], ghost[1], 0)
+    for i in range(n):
+        flux_in += mu * orc.num_flux(P, ghost[2], W0[:, 0, i], 1)
+        flux_in -= mu * orc.num_flux(P, W0[:, -1, i], ghost[3], 1)
+    change = _fsum_planes(W1) - _fsum_planes(W0)
+    scale = np.max(np.abs(W0), axis=(1, 2)) * n * n
+    assert np.all(np.abs(change - flux_in) <= 1e-13 * scale)
+
+
+def test_dirichlet_adjoint_is_unsupported(orc):
+    n = 8
+    P = orc.params(orc.EULER, n, n, bc=orc.DIRICHLET, ghost=_euler_ghosts())
+    W = inputs.riemann_state(n, n, 1)
+    with pytest.raises(Exception):
+        orc.adjoint_step(P, W, 1e-3, np.ones_like(W))
+
+
+# --------------------------------------------------------------------------
 # conservation, invariants, symmetry
 # --------------------------------------------------------------------------
 
