@@ -68,13 +68,14 @@ extern "C" {
 
 #define FVM_PERIODIC 0     /* the domain wraps around (Sec. 5)                */
 #define FVM_TRANSMISSIVE 1 /* ghost cell = boundary cell (zero gradient)      */
+#define FVM_DIRICHLET 2    /* ghost cell = a prescribed state per side         */
 
 #define FVM_LAYOUT_PLANES 0 /* w[(v * ny + j) * ld + i]                       */
 #define FVM_LAYOUT_ROWS 1   /* w[(j * nVar + v) * ld + i]; nVar * ld <= 2^31-1 */
 
 typedef struct fvm_params {
   int model;     /* FVM_ADV, FVM_EULER or FVM_SPRAY                          */
-  int bc;        /* FVM_PERIODIC or FVM_TRANSMISSIVE                         */
+  int bc;        /* FVM_PERIODIC, FVM_TRANSMISSIVE or FVM_DIRICHLET          */
   int nx, ny;    /* cells, >= 1 each                                         */
   int npart_x;   /* NPartX: balanced subdomains along x, nx % npart_x == 0   */
   int npart_y;   /* NPartY (Sec. 3.2); the result does not depend on them    */
@@ -127,6 +128,15 @@ int fvm_destroy(fvm_grid* g);
  * Enqueues a kernel that clears the scratch (speeds unknown, status 0). */
 int fvm_bind(fvm_grid* g, double* w_a, double* w_b, const double* ug,
              void* scratch, void* stream);
+
+/* Dirichlet boundaries (bc == FVM_DIRICHLET): the state of the ghost cells
+ * beyond each side of the domain, the overlap a subdomain at the domain's
+ * edge receives (Sec. 4.2). ghost is a host array of 4 * nVar doubles, the
+ * conservative states of the west (i = -1), east (i = nx), south (j = -1)
+ * and north (j = ny) sides in that order; the plan keeps a copy, used by the
+ * steps enqueued after the call. FVM_EINVAL for another boundary condition
+ * or a non-finite value. Until the first call the ghost states are zero. */
+int fvm_set_boundary_states(fvm_grid* g, const double* ghost);
 
 /* Changes the stream later calls enqueue on. */
 int fvm_set_stream(fvm_grid* g, void* stream);
@@ -194,7 +204,8 @@ int fvm_get_status(fvm_grid* g, int clear);
 
 /* Gradient of a loss of the final state with respect to the initial state,
  * through nsteps transport steps with frozen time steps (advection and Euler;
- * FVM_EUNSUPPORTED for the spray model). The adjoint of one step is
+ * FVM_EUNSUPPORTED for the spray model and for Dirichlet boundaries). The
+ * adjoint of one step is
  *   lam^n = lam^{n+1} + dt/dx [J_L(i+1/2)^T (lam_{i+1} - lam_i)
  *                             + J_R(i-1/2)^T (lam_i - lam_{i-1})] + (same in y)
  * with J_L, J_R the Jacobians of the numerical flux with respect to its left
@@ -247,7 +258,8 @@ int fvm_autotune(fvm_grid* g, const char* cache_path);
 
 /* Creates a plan for n independent grids solved together, one persistent
  * launch per time step for all of them (each grid keeps its own adaptive
- * dt). p[k] are the grids' parameters (all the same model, not spray);
+ * dt). p[k] are the grids' parameters (all the same model and boundary
+ * condition, not spray, not Dirichlet);
  * offsets[k] is the element offset of grid k's state inside the packed
  * buffers, a multiple of 32 elements (256 bytes). */
 int fvm_batch_create(int n, const fvm_params* p, const size_t* offsets,

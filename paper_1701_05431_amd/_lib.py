@@ -13,7 +13,7 @@ LIB_PATH = os.path.join(HERE, "libfvm.so")
 
 FVM_OK, FVM_EINVAL, FVM_EDEVICE, FVM_ECFL, FVM_ENONFINITE, FVM_EUNSUPPORTED = 0, -1, -2, -3, -4, -5
 FVM_ADV, FVM_EULER, FVM_SPRAY = 0, 1, 2
-FVM_PERIODIC, FVM_TRANSMISSIVE = 0, 1
+FVM_PERIODIC, FVM_TRANSMISSIVE, FVM_DIRICHLET = 0, 1, 2
 FVM_LAYOUT_PLANES, FVM_LAYOUT_ROWS = 0, 1
 
 
@@ -58,6 +58,7 @@ SIGNATURES = {
     "fvm_run": (C.c_int, [_V, C.c_int, _V]),
     "fvm_run_dts": (C.c_int, [_V, C.c_int, _V]),
     "fvm_run_fixed": (C.c_int, [_V, C.c_int, C.c_double]),
+    "fvm_set_boundary_states": (C.c_int, [_V, _V]),
     "fvm_run_ckpt": (C.c_int, [_V, C.c_int, C.c_int, C.POINTER(_V), _V]),
     "fvm_sync": (C.c_int, [_V]),
     "fvm_get_status": (C.c_int, [_V, C.c_int]),

@@ -64,7 +64,8 @@ constexpr size_t kGraphCacheMax = 16;
 bool valid_params(const fvm_params* p) {
   if (!p) return false;
   if (fvm_nvar(p->model) == 0) return false;
-  if (p->bc != FVM_PERIODIC && p->bc != FVM_TRANSMISSIVE) return false;
+  if (p->bc != FVM_PERIODIC && p->bc != FVM_TRANSMISSIVE && p->bc != FVM_DIRICHLET)
+    return false;
   if (p->nx < 1 || p->ny < 1 || p->npart_x < 1 || p->npart_y < 1) return false;
   if (p->nx % p->npart_x != 0 || p->ny % p->npart_y != 0) return false;
   if (p->ld < p->nx) return false;
@@ -192,6 +193,7 @@ struct fvm_grid {
   double* w_b = nullptr;
   double* cur = nullptr;
   const double* ug = nullptr;
+  double ghost[4 * kMaxVar] = {};  // Dirichlet states, ghost[side * kMaxVar + v]
   GridScratch* scr = nullptr;
   hipStream_t stream = nullptr;
   bool bound = false;
@@ -222,6 +224,7 @@ struct fvm_grid {
     a.g = g;
     a.t = tiling(g, rows, wpb, cpl);
     a.m = m;
+    for (int k = 0; k < 4 * kMaxVar; ++k) a.ghost[k] = ghost[k];
     return a;
   }
 };
@@ -309,6 +312,16 @@ int fvm_bind(fvm_grid* g, double* w_a, double* w_b, const double* ug, void* scra
   choose_layout(g);
   g->speeds_valid = false;
   return dev_err(launch_clear_scratch(g->scr, 1, g->stream));
+}
+
+int fvm_set_boundary_states(fvm_grid* g, const double* ghost) {
+  if (!g || !ghost || g->p.bc != FVM_DIRICHLET) return FVM_EINVAL;
+  for (int k = 0; k < 4 * g->nv; ++k)
+    if (!std::isfinite(ghost[k])) return FVM_EINVAL;
+  for (int side = 0; side < 4; ++side)
+    for (int v = 0; v < g->nv; ++v) g->ghost[side * kMaxVar + v] = ghost[side * g->nv + v];
+  g->clear_graphs();  // the cached graphs hold the previous states
+  return FVM_OK;
 }
 
 int fvm_set_stream(fvm_grid* g, void* stream) {
@@ -711,7 +724,7 @@ int fvm_get_tiling(const fvm_grid* g, int* rows, int* wpb) {
 int fvm_adjoint_step(fvm_grid* g, const double* w, double dt, const double* lam_in,
                      double* lam_out) {
   if (!g || !g->bound || !w || !lam_in || !lam_out || lam_in == lam_out) return FVM_EINVAL;
-  if (g->p.model == FVM_SPRAY) return FVM_EUNSUPPORTED;
+  if (g->p.model == FVM_SPRAY || g->p.bc == FVM_DIRICHLET) return FVM_EUNSUPPORTED;
   if (!(dt >= 0.0) || !std::isfinite(dt)) return FVM_EINVAL;
   AdjointArgs a{};
   a.w = w;
@@ -731,7 +744,7 @@ int fvm_adjoint_run(fvm_grid* g, double* const* ckpts, int ckpt_every, const dou
       !lam_tmp || lam == lam_tmp)
     return FVM_EINVAL;
   if (ckpt_every > 1 && !seg_buf) return FVM_EINVAL;
-  if (g->p.model == FVM_SPRAY) return FVM_EUNSUPPORTED;
+  if (g->p.model == FVM_SPRAY || g->p.bc == FVM_DIRICHLET) return FVM_EUNSUPPORTED;
   const int nck = (nsteps + ckpt_every - 1) / ckpt_every;
   for (int s = 0; s < nck; ++s)
     if (!ckpts[s]) return FVM_EINVAL;

@@ -232,7 +232,7 @@ int fvm_batch_create(int n, const fvm_params* p, const size_t* offsets, fvm_batc
   if (n < 1 || !p || !offsets) return FVM_EINVAL;
   for (int k = 0; k < n; ++k) {
     if (fvm_validate(&p[k]) != FVM_OK) return FVM_EINVAL;
-    if (p[k].model == FVM_SPRAY) return FVM_EUNSUPPORTED;
+    if (p[k].model == FVM_SPRAY || p[k].bc == FVM_DIRICHLET) return FVM_EUNSUPPORTED;
     if (p[k].model != p[0].model || p[k].bc != p[0].bc) return FVM_EINVAL;
     if (p[k].gamma != p[0].gamma || p[k].ax != p[0].ax || p[k].ay != p[0].ay) return FVM_EINVAL;
     if (offsets[k] % 32 != 0) return FVM_EINVAL;

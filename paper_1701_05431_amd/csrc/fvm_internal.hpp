@@ -13,6 +13,12 @@ namespace fvm {
 
 constexpr int kWave = 64;       // CDNA wavefront width
 constexpr int kOutPerWave = 62; // cells a 64-lane wave strip updates (2 halo lanes)
+constexpr int kMaxVar = 6;      // largest nVar (spray)
+
+// Boundary conditions (template argument BC of the kernels).
+enum : int { kPeriodic = 0, kTransmissive = 1, kDirichlet = 2 };
+// Sides of the domain, in the order of the Dirichlet ghost states.
+enum : int { kWest = 0, kEast = 1, kSouth = 2, kNorth = 3 };
 
 // Sticky device status bits.
 enum : unsigned int {
@@ -102,6 +108,7 @@ struct StepArgs {
   GridGeom g;
   Tiling t;
   ModelConsts m;
+  double ghost[4 * kMaxVar];  // Dirichlet states: ghost[side * kMaxVar + v]
 };
 
 struct CflArgs {

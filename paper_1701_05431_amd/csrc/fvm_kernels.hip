@@ -37,24 +37,25 @@ namespace fvm {
 
 // One wave strip of the CPL layout (1: 62 cells per wave, any pitch; 2: 128
 // cells per wave, 16-byte aligned accesses).
+// (gh: the Dirichlet ghost states, BC == kDirichlet only)
 template <class M, int BC, int CPL>
 __device__ __forceinline__ void strip(const M& m, const double* __restrict__ win,
                                       double* __restrict__ wout, const double* __restrict__ ug,
                                       const GridGeom& g, int xs, int j0, int j1, double mux,
                                       double muy, double dt, unsigned long long& bx,
-                                      unsigned long long& by) {
+                                      unsigned long long& by, const double* gh) {
   if (xs >= g.nx) return;
   if (CPL == 1) {
-    if (FVM_LEGACY_STRIP)
+    if constexpr (FVM_LEGACY_STRIP && BC != kDirichlet)
       march_strip<M, BC>(m, win, wout, ug, g, xs, j0, j1, mux, muy, dt, bx, by);
     else if (xs + kWave <= g.nx)
-      march_strip1<M, BC, false>(m, win, wout, ug, g, xs, j0, j1, mux, muy, dt, bx, by);
+      march_strip1<M, BC, false>(m, win, wout, ug, g, xs, j0, j1, mux, muy, dt, bx, by, gh);
     else
-      march_strip1<M, BC, true>(m, win, wout, ug, g, xs, j0, j1, mux, muy, dt, bx, by);
+      march_strip1<M, BC, true>(m, win, wout, ug, g, xs, j0, j1, mux, muy, dt, bx, by, gh);
   } else if (xs + 2 * kWave <= g.nx) {
-    march_strip2<M, BC, false>(m, win, wout, ug, g, xs, j0, j1, mux, muy, dt, bx, by);
+    march_strip2<M, BC, false>(m, win, wout, ug, g, xs, j0, j1, mux, muy, dt, bx, by, gh);
   } else {
-    march_strip2<M, BC, true>(m, win, wout, ug, g, xs, j0, j1, mux, muy, dt, bx, by);
+    march_strip2<M, BC, true>(m, win, wout, ug, g, xs, j0, j1, mux, muy, dt, bx, by, gh);
   }
 }
 
@@ -72,7 +73,7 @@ __global__ FVM_STEP_BOUNDS(WPB) void step_kernel(StepArgs a) {
   const int j0 = ty * a.t.rows;
   const int j1 = min(j0 + a.t.rows, a.g.ny);
   unsigned long long bx = 0, by = 0;
-  strip<M, BC, CPL>(m, a.win, a.wout, a.ug, a.g, xs, j0, j1, mux, muy, dt_eff, bx, by);
+  strip<M, BC, CPL>(m, a.win, a.wout, a.ug, a.g, xs, j0, j1, mux, muy, dt_eff, bx, by, a.ghost);
   if (block_commit<WPB>(bx, by, a.scr, gridDim.x) && threadIdx.x == 0) {
     if (cfl_fail) atomicOr(&a.scr->status, kStatusCfl);
     finalize_grid(a.scr, a.g, dt_eff, a.dt_log, a.dt_log_cap, a.dt_log_stride, nullptr);
@@ -127,10 +128,19 @@ static StepFn step_fn_wpb(int wpb) {
   }
 }
 
+template <class M, int CPL>
+static StepFn step_fn_cpl(int bc, int wpb) {
+  switch (bc) {
+    case kPeriodic: return step_fn_wpb<M, kPeriodic, CPL>(wpb);
+    case kTransmissive: return step_fn_wpb<M, kTransmissive, CPL>(wpb);
+    case kDirichlet: return step_fn_wpb<M, kDirichlet, CPL>(wpb);
+    default: return nullptr;
+  }
+}
+
 template <class M>
 static StepFn step_fn_bc(int bc, int wpb, int cpl) {
-  if (cpl == 2) return bc == 0 ? step_fn_wpb<M, 0, 2>(wpb) : step_fn_wpb<M, 1, 2>(wpb);
-  return bc == 0 ? step_fn_wpb<M, 0, 1>(wpb) : step_fn_wpb<M, 1, 1>(wpb);
+  return cpl == 2 ? step_fn_cpl<M, 2>(bc, wpb) : step_fn_cpl<M, 1>(bc, wpb);
 }
 
 void* step_kernel_ptr(int model, int bc, int wpb, int cpl) {

@@ -54,9 +54,32 @@ __device__ __forceinline__ size_t ucell(const GridGeom& g, int j, int i) {
   return static_cast<size_t>(j) * g.uld + i;
 }
 
+// Dirichlet boundaries: the prescribed state of one side, for every lane or
+// for the lanes where `use` holds.
+template <int NV>
+__device__ __forceinline__ void ghost_state(double* w, const double* gh, int side) {
+#pragma unroll
+  for (int v = 0; v < NV; ++v) w[v] = gh[side * kMaxVar + v];
+}
+template <int NV>
+__device__ __forceinline__ void ghost_if(double* w, const double* gh, int side, bool use) {
+#pragma unroll
+  for (int v = 0; v < NV; ++v) w[v] = use ? gh[side * kMaxVar + v] : w[v];
+}
+
+// Row r of a strip's column(s); r may be -1 or ny (the ghost rows). With
+// Dirichlet boundaries those rows are the south / north states (r is uniform
+// across the wave, so is the branch).
 template <int NV, int BC>
 __device__ __forceinline__ void load_row(double* w, const double* __restrict__ base,
-                                         const GridGeom& g, int r) {
+                                         const GridGeom& g, int r,
+                                         const double* gh = nullptr) {
+  if constexpr (BC == kDirichlet) {
+    if (r < 0 || r >= g.ny) {
+      ghost_state<NV>(w, gh, r < 0 ? kSouth : kNorth);
+      return;
+    }
+  }
   const size_t off = static_cast<size_t>(row_index<BC>(r, g.ny)) * g.ld;
 #pragma unroll
   for (int v = 0; v < NV; ++v) {
@@ -94,6 +117,7 @@ __device__ __forceinline__ void march_strip(const M& m, const double* __restrict
                                             int xs, int j0, int j1, double mux, double muy,
                                             double dt, unsigned long long& bx,
                                             unsigned long long& by) {
+  static_assert(BC != kDirichlet, "the one-cell strips handle Dirichlet boundaries");
   constexpr int NV = M::NV;
   using Prim = typename M::Prim;
   const int lane = threadIdx.x & (kWave - 1);
@@ -180,7 +204,8 @@ __device__ __forceinline__ void march_strip1(const M& m, const double* __restric
                                              const double* __restrict__ ug, const GridGeom& g,
                                              int xs, int j0, int j1, double mux, double muy,
                                              double dt, unsigned long long& bx,
-                                             unsigned long long& by) {
+                                             unsigned long long& by,
+                                             const double* gh = nullptr) {
   constexpr int NV = M::NV;
   using Prim = typename M::Prim;
   const int lane = threadIdx.x & (kWave - 1);
@@ -188,20 +213,32 @@ __device__ __forceinline__ void march_strip1(const M& m, const double* __restric
   const int x = xs + lane;
   const int cx = EDGE ? col_index<BC>(x, g.nx) : x;
   const bool ok = !EDGE || x < g.nx;
-  const int ch = col_index<BC>(first ? xs - 1 : xs + kWave, g.nx);
+  const int hx = first ? xs - 1 : xs + kWave;  // halo column of lanes 0 and 63
+  const int ch = col_index<BC>(hx, g.nx);
   const double* base = win + cx;
+  // Dirichlet: the halo column or this lane's column is outside the grid
+  const bool h_out = hx < 0 || hx >= g.nx;
+  const int h_side = first ? kWest : kEast;
+  auto wrow = [&](double* w, int r) {
+    load_row<NV, BC>(w, base, g, r, gh);
+    if constexpr (BC == kDirichlet && EDGE) ghost_if<NV>(w, gh, kEast, x >= g.nx);
+  };
+  auto hrow = [&](double* w, int r) {
+    load_row<NV, BC>(w, win + ch, g, r, gh);
+    if constexpr (BC == kDirichlet) ghost_if<NV>(w, gh, h_side, h_out);
+  };
 
   constexpr int PF = M::kPrefetch1;
   constexpr int R = PF + 2;
   double W[R][NV], H[R][NV], G[R][NV];
   Prim P[R];
-  load_row<NV, BC>(W[R - 1], base, g, j0 - 1);
-  load_row<NV, BC>(W[0], base, g, j0);
-  load_row<NV, BC>(H[0], win + ch, g, j0);
+  wrow(W[R - 1], j0 - 1);
+  wrow(W[0], j0);
+  hrow(H[0], j0);
 #pragma unroll
   for (int p = 1; p <= PF; ++p) {
-    load_row<NV, BC>(W[p], base, g, min(j0 + p, j1));
-    load_row<NV, BC>(H[p], win + ch, g, min(j0 + p, j1 - 1));
+    wrow(W[p], min(j0 + p, j1));
+    hrow(H[p], min(j0 + p, j1 - 1));
   }
   m.prim(W[R - 1], P[R - 1]);
   m.prim(W[0], P[0]);
@@ -212,8 +249,8 @@ __device__ __forceinline__ void march_strip1(const M& m, const double* __restric
     for (int u = 0; u < R; ++u) {
       const int j = jb + u;
       const int c = u, n = (u + 1) % R, l = (u + R - 1) % R;
-      load_row<NV, BC>(W[l], base, g, min(j + 1 + PF, j1));
-      load_row<NV, BC>(H[l], win + ch, g, min(j + 1 + PF, j1 - 1));
+      wrow(W[l], min(j + 1 + PF, j1));
+      hrow(H[l], min(j + 1 + PF, j1 - 1));
       m.prim(W[n], P[n]);
       m.template flux<1>(W[c], P[c], W[n], P[n], G[n]);
       double Fr[NV], Fh[NV], Wr[NV], L[NV], Rt[NV], Fp[NV], Wo[NV];
@@ -274,7 +311,16 @@ typedef double dbl2 __attribute__((ext_vector_type(2)));
 
 template <int NV, int BC, bool EDGE>
 __device__ __forceinline__ void load_pair(double* a, double* b, const double* __restrict__ w,
-                                          const GridGeom& g, int ca, int cb, int r) {
+                                          const GridGeom& g, int ca, int cb, int r,
+                                          const double* gh = nullptr, bool a_out = false,
+                                          bool b_out = false) {
+  if constexpr (BC == kDirichlet) {
+    if (r < 0 || r >= g.ny) {  // uniform
+      ghost_state<NV>(a, gh, r < 0 ? kSouth : kNorth);
+      ghost_state<NV>(b, gh, r < 0 ? kSouth : kNorth);
+      return;
+    }
+  }
   const size_t off = static_cast<size_t>(row_index<BC>(r, g.ny)) * g.ld;
 #pragma unroll
   for (int v = 0; v < NV; ++v) {
@@ -288,6 +334,10 @@ __device__ __forceinline__ void load_pair(double* a, double* b, const double* __
       b[v] = x.y;
     }
   }
+  if constexpr (BC == kDirichlet && EDGE) {  // columns past the east edge
+    ghost_if<NV>(a, gh, kEast, a_out);
+    ghost_if<NV>(b, gh, kEast, b_out);
+  }
 }
 
 template <class M, int BC, bool EDGE, int PF = M::kPrefetch2>
@@ -296,7 +346,8 @@ __device__ __forceinline__ void march_strip2(const M& m, const double* __restric
                                              const double* __restrict__ ug, const GridGeom& g,
                                              int xs, int j0, int j1, double mux, double muy,
                                              double dt, unsigned long long& bx,
-                                             unsigned long long& by) {
+                                             unsigned long long& by,
+                                             const double* gh = nullptr) {
   constexpr int NV = M::NV;
   using Prim = typename M::Prim;
   const int lane = threadIdx.x & (kWave - 1);
@@ -305,18 +356,29 @@ __device__ __forceinline__ void march_strip2(const M& m, const double* __restric
   const int ca = EDGE ? col_index<BC>(xa, g.nx) : xa;
   const int cb = EDGE ? col_index<BC>(xb, g.nx) : xb;
   const bool oka = !EDGE || xa < g.nx, okb = !EDGE || xb < g.nx;
-  const int ch = col_index<BC>(first ? xs - 1 : xs + 2 * kWave, g.nx);
+  const int hx = first ? xs - 1 : xs + 2 * kWave;  // halo column of lanes 0 and 63
+  const int ch = col_index<BC>(hx, g.nx);
+  // Dirichlet: the halo column is outside the grid
+  const bool h_out = hx < 0 || hx >= g.nx;
+  const int h_side = first ? kWest : kEast;
+  auto prow = [&](double* a, double* b, int r) {
+    load_pair<NV, BC, EDGE>(a, b, win, g, ca, cb, r, gh, !oka, !okb);
+  };
+  auto hrow = [&](double* w, int r) {
+    load_row<NV, BC>(w, win + ch, g, r, gh);
+    if constexpr (BC == kDirichlet) ghost_if<NV>(w, gh, h_side, h_out);
+  };
 
   constexpr int R = PF + 2;  // PF rows of loads in flight
   double A[R][NV], B[R][NV], H[R][NV], GA[R][NV], GB[R][NV];
   Prim PA[R], PB[R];
-  load_pair<NV, BC, EDGE>(A[R - 1], B[R - 1], win, g, ca, cb, j0 - 1);
-  load_pair<NV, BC, EDGE>(A[0], B[0], win, g, ca, cb, j0);
-  load_row<NV, BC>(H[0], win + ch, g, j0);
+  prow(A[R - 1], B[R - 1], j0 - 1);
+  prow(A[0], B[0], j0);
+  hrow(H[0], j0);
 #pragma unroll
   for (int p = 1; p <= PF; ++p) {
-    load_pair<NV, BC, EDGE>(A[p], B[p], win, g, ca, cb, min(j0 + p, j1));
-    load_row<NV, BC>(H[p], win + ch, g, min(j0 + p, j1 - 1));
+    prow(A[p], B[p], min(j0 + p, j1));
+    hrow(H[p], min(j0 + p, j1 - 1));
   }
   m.prim(A[R - 1], PA[R - 1]);
   m.prim(B[R - 1], PB[R - 1]);
@@ -330,8 +392,8 @@ __device__ __forceinline__ void march_strip2(const M& m, const double* __restric
     for (int u = 0; u < R; ++u) {
       const int j = jb + u;
       const int c = u, n = (u + 1) % R, l = (u + R - 1) % R;
-      load_pair<NV, BC, EDGE>(A[l], B[l], win, g, ca, cb, min(j + 1 + PF, j1));
-      load_row<NV, BC>(H[(u + PF + 1) % R], win + ch, g, min(j + 1 + PF, j1 - 1));
+      prow(A[l], B[l], min(j + 1 + PF, j1));
+      hrow(H[(u + PF + 1) % R], min(j + 1 + PF, j1 - 1));
       m.prim(A[n], PA[n]);
       m.prim(B[n], PB[n]);
       m.template flux<1>(A[c], PA[c], A[n], PA[n], GA[n]);
@@ -369,7 +431,8 @@ __device__ __forceinline__ void march_strip2(const M& m, const double* __restric
         GridGeom gu = g;
         gu.ld = g.uld;
         gu.plane = g.uplane;
-        load_pair<2, BC, EDGE>(ua, ub, ug, gu, ca, cb, j);
+        // rows past the strip read the clamped gas velocity (never stored)
+        load_pair<2, BC == kDirichlet ? kTransmissive : BC, EDGE>(ua, ub, ug, gu, ca, cb, j);
         m.source(Oa, ua[0], ua[1], dt);
         m.source(Ob, ub[0], ub[1], dt);
       }

@@ -111,6 +111,12 @@ class Solver:
         logical(p, out)[:, :, :W.shape[2]].copy_(W)
         return out
 
+    def set_boundary_states(self, ghost) -> None:
+        """Dirichlet ghost states, shape (4, nVar): west, east, south, north."""
+        g = np.ascontiguousarray(np.asarray(ghost, dtype=np.float64).reshape(4, self.nv))
+        check(lib().fvm_set_boundary_states(self.h, g.ctypes.data_as(C.c_void_p)),
+              "fvm_set_boundary_states")
+
     def _bind_stream(self):
         lib().fvm_set_stream(self.h, _stream_handle(self.device))
 

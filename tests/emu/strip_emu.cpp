@@ -12,12 +12,14 @@
 // the grid must have been written and each padding column (i >= nx) must not.
 // The input is a uniform state, which the step leaves bitwise unchanged
 // (advection and Euler: equal fluxes cancel; spray: K = 0 and the gas velocity
-// equals the droplet velocity, so the source vanishes).
+// equals the droplet velocity, so the source vanishes); Dirichlet ghosts
+// (bc 2) hold the same state.
 #include <hip/hip_runtime.h>
 
 #include <cstdio>
 #include <cstdlib>
 #include <thread>
+#include <type_traits>
 #include <vector>
 
 thread_local emu_dim3 emu_threadIdx;
@@ -52,7 +54,7 @@ using namespace fvm;
 template <class M, int BC>
 static void run_strip(const M& m, const double* win, double* wout, const double* ug,
                       const GridGeom& g, int cpl, int xs, int j0, int j1, double mux, double muy,
-                      double dt) {
+                      double dt, const double* gh) {
   std::barrier<> bar(64);
   g_bar = &bar;
   std::vector<std::thread> lanes;
@@ -64,14 +66,14 @@ static void run_strip(const M& m, const double* win, double* wout, const double*
       if (xs >= g.nx) return;  // uniform: the whole wave leaves
       if (cpl == 1) {
         if (xs + kWave <= g.nx)
-          march_strip1<M, BC, false>(m, win, wout, ug, g, xs, j0, j1, mux, muy, dt, bx, by);
+          march_strip1<M, BC, false>(m, win, wout, ug, g, xs, j0, j1, mux, muy, dt, bx, by, gh);
         else
-          march_strip1<M, BC, true>(m, win, wout, ug, g, xs, j0, j1, mux, muy, dt, bx, by);
+          march_strip1<M, BC, true>(m, win, wout, ug, g, xs, j0, j1, mux, muy, dt, bx, by, gh);
       } else {
         if (xs + 2 * kWave <= g.nx)
-          march_strip2<M, BC, false>(m, win, wout, ug, g, xs, j0, j1, mux, muy, dt, bx, by);
+          march_strip2<M, BC, false>(m, win, wout, ug, g, xs, j0, j1, mux, muy, dt, bx, by, gh);
         else
-          march_strip2<M, BC, true>(m, win, wout, ug, g, xs, j0, j1, mux, muy, dt, bx, by);
+          march_strip2<M, BC, true>(m, win, wout, ug, g, xs, j0, j1, mux, muy, dt, bx, by, gh);
       }
     });
   for (auto& t : lanes) t.join();
@@ -160,6 +162,11 @@ int main(int argc, char** argv) {
   mc.s_eps = 0.01;
   mc.log_s_eps = std::log(0.01);
 
+  // Dirichlet ghosts: the uniform state on every side
+  double gh[4 * kMaxVar] = {};
+  for (int side = 0; side < 4; ++side)
+    for (int v = 0; v < nv; ++v) gh[side * kMaxVar + v] = at(win, v, 0, 0);
+
   // the step kernel's tiles: WPB strips side by side, `rows` rows each
   const int sw = strip_width(cpl);
   const int tiles_x = (nx + sw * wpb - 1) / (sw * wpb), tiles_y = (ny + rows - 1) / rows;
@@ -168,18 +175,18 @@ int main(int argc, char** argv) {
     for (int tx = 0; tx < tiles_x; ++tx)
       for (int w = 0; w < wpb; ++w) {
         const int xs = (tx * wpb + w) * sw, j0 = ty * rows, j1 = std::min(j0 + rows, ny);
-        if (model == 0 && bc == 0)
-          run_strip<Adv, 0>(Adv(mc), win, wout, ug, g, cpl, xs, j0, j1, mux, muy, dt);
-        else if (model == 0)
-          run_strip<Adv, 1>(Adv(mc), win, wout, ug, g, cpl, xs, j0, j1, mux, muy, dt);
-        else if (model == 1 && bc == 0)
-          run_strip<Euler, 0>(Euler(mc), win, wout, ug, g, cpl, xs, j0, j1, mux, muy, dt);
-        else if (model == 1)
-          run_strip<Euler, 1>(Euler(mc), win, wout, ug, g, cpl, xs, j0, j1, mux, muy, dt);
-        else if (bc == 0)
-          run_strip<Spray, 0>(Spray(mc), win, wout, ug, g, cpl, xs, j0, j1, mux, muy, dt);
-        else
-          run_strip<Spray, 1>(Spray(mc), win, wout, ug, g, cpl, xs, j0, j1, mux, muy, dt);
+        auto go = [&](auto bct) {
+          constexpr int B = decltype(bct)::value;
+          if (model == 0)
+            run_strip<Adv, B>(Adv(mc), win, wout, ug, g, cpl, xs, j0, j1, mux, muy, dt, gh);
+          else if (model == 1)
+            run_strip<Euler, B>(Euler(mc), win, wout, ug, g, cpl, xs, j0, j1, mux, muy, dt, gh);
+          else
+            run_strip<Spray, B>(Spray(mc), win, wout, ug, g, cpl, xs, j0, j1, mux, muy, dt, gh);
+        };
+        if (bc == 0) go(std::integral_constant<int, 0>());
+        else if (bc == 1) go(std::integral_constant<int, 1>());
+        else go(std::integral_constant<int, 2>());
       }
 
   long missing = 0, stray = 0, changed = 0;

@@ -41,7 +41,7 @@ def test_binding_constants_match_the_header():
     from paper_1701_05431_amd import _lib
     text = open(HEADER).read()
     defines = dict(re.findall(r"#define (FVM_[A-Z_]+) \(?(-?\d+)\)?", text))
-    assert len(defines) == 13
+    assert len(defines) == 14
     for name, value in defines.items():
         assert getattr(_lib, name) == int(value), name
 
@@ -83,6 +83,8 @@ def test_validation_on_host(L):
         assert not h.value
     rows = params_from(model=1, nx=64, ny=32, ld=70, layout=_lib.FVM_LAYOUT_ROWS)
     assert L.fvm_validate(rows) == _lib.FVM_OK
+    assert L.fvm_validate(params_from(model=1, nx=64, ny=32, bc=_lib.FVM_DIRICHLET)) == _lib.FVM_OK
+    assert L.fvm_validate(params_from(model=1, nx=64, ny=32, bc=3)) == _lib.FVM_EINVAL
     sp = params_from(model=2, nx=8, ny=8, theta=0.0)
     assert L.fvm_validate(sp) == _lib.FVM_EINVAL
     sp = params_from(model=2, nx=8, ny=8, s_eps=1.5)
@@ -104,6 +106,16 @@ def test_create_destroy_and_unbound_calls(L):
     assert L.fvm_set_tiling(h, 16, 2) == _lib.FVM_OK
     assert L.fvm_set_tiling(h, 16, 3) == _lib.FVM_EINVAL
     assert L.fvm_set_tiling(h, -1, 2) == _lib.FVM_EINVAL
+    ghost = (C.c_double * 16)(*([1.0] * 16))
+    # ghost states only for Dirichlet boundaries
+    assert L.fvm_set_boundary_states(h, ghost) == _lib.FVM_EINVAL
+    assert L.fvm_destroy(h) == _lib.FVM_OK
+    pd = params_from(model=1, nx=64, ny=32, bc=_lib.FVM_DIRICHLET)
+    assert L.fvm_create(pd, C.byref(h)) == _lib.FVM_OK
+    assert L.fvm_set_boundary_states(h, ghost) == _lib.FVM_OK
+    ghost[5] = float("nan")
+    assert L.fvm_set_boundary_states(h, ghost) == _lib.FVM_EINVAL
+    assert L.fvm_set_boundary_states(h, None) == _lib.FVM_EINVAL
     assert L.fvm_destroy(h) == _lib.FVM_OK
     assert L.fvm_destroy(None) == _lib.FVM_OK
     assert L.fvm_strerror(-4) == b"non-finite or non-physical state"
@@ -125,3 +137,5 @@ def test_batch_create_validation(L):
     assert L.fvm_batch_create(2, arr, (C.c_size_t * 2)(0, 4 * 64 * 64 + 8), C.byref(h)) == _lib.FVM_EINVAL
     sp = (_lib.Params * 1)(params_from(model=2, nx=8, ny=8))
     assert L.fvm_batch_create(1, sp, (C.c_size_t * 1)(0), C.byref(h)) == _lib.FVM_EUNSUPPORTED
+    dp = (_lib.Params * 1)(params_from(model=1, nx=8, ny=8, bc=_lib.FVM_DIRICHLET))
+    assert L.fvm_batch_create(1, dp, (C.c_size_t * 1)(0), C.byref(h)) == _lib.FVM_EUNSUPPORTED

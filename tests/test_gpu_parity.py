@@ -43,10 +43,10 @@ def ulps(a, b):
     return abs(a - b) / math.ulp(abs(b))
 
 
-def oparams(p: _lib.Params):
+def oparams(p: _lib.Params, ghost=None):
     return orc.params(p.model, p.nx, p.ny, bc=p.bc, npx=p.npart_x, npy=p.npart_y, lx=p.lx,
                       ly=p.ly, gamma=p.gamma, ax=p.ax, ay=p.ay, K=p.K, theta=p.theta,
-                      s_eps=p.s_eps, cfl=p.cfl, dt_max=p.dt_max)
+                      s_eps=p.s_eps, cfl=p.cfl, dt_max=p.dt_max, ghost=ghost)
 
 
 def gpu_state(s: Solver) -> np.ndarray:
@@ -189,6 +189,81 @@ def test_lane_layouts_agree_bitwise(model, bc, nx):
         assert np.array_equal(res[0][0], r[0]) and np.array_equal(res[0][1], r[1])
     ref, odts = orc.run(oparams(params_from(model=model, bc=bc, nx=nx, ny=ny, **kw)), W, 5, ug=ug)
     assert rel_linf(res[1][0], ref) <= TOL
+
+
+def _dirichlet_case(model, nx, ny, seed):
+    """State, gas velocity, extra parameters and ghost states (west, east,
+    south, north) of a Dirichlet test case."""
+    ug = None
+    if model == 0:
+        W = inputs.advection_state(nx, ny, seed)
+        kw = dict(ax=0.6, ay=-0.8)
+        ghost = np.array([[0.9], [-0.4], [0.2], [1.3]])
+    elif model == 1:
+        W = inputs.riemann_state(nx, ny, seed)
+        kw = {}
+        ghost = np.stack([inputs.conservative_from_primitive(*q) for q in
+                          [(0.6, 0.2, -0.1, 0.5), (1.1, -0.3, 0.05, 0.9),
+                           (0.8, 0.1, 0.25, 0.4), (0.4, -0.05, -0.2, 0.7)]])
+    else:
+        W, ug = inputs.spray_state(nx, ny, seed)
+        kw = dict(cfl=0.9)
+        # states of the same family, taken from a larger field
+        Wg, _ = inputs.spray_state(8, 8, seed + 1)
+        ghost = np.stack([Wg[:, 1, 2], Wg[:, 5, 6], Wg[:, 3, 0], Wg[:, 7, 4]])
+    return W, ug, kw, ghost
+
+
+@pytest.mark.parametrize("model", [0, 1, 2])
+@pytest.mark.parametrize("nx", [1, 64, 127, 128, 129, 300])
+def test_dirichlet_matches_oracle_in_every_layout(model, nx):
+    """Dirichlet boundaries: both storage layouts and both lane layouts give
+    bitwise the same 5 adaptive steps, which are the oracle's."""
+    ny = 37
+    ld = nx + (nx % 2)
+    W, ug, kw, ghost = _dirichlet_case(model, nx, ny, nx + 3)
+    res = []
+    for layout in (_lib.FVM_LAYOUT_PLANES, _lib.FVM_LAYOUT_ROWS):
+        for cpl in (1, 2):
+            p = params_from(model=model, bc=_lib.FVM_DIRICHLET, nx=nx, ny=ny, ld=ld,
+                            layout=layout, **kw)
+            s = Solver(p, ug=ug)
+            s.set_boundary_states(ghost)
+            assert s.set_cells_per_lane(cpl) == cpl
+            s.set_state(W)
+            d = s.run(5, record_dt=True).cpu().numpy()
+            assert s.sync() == 0
+            res.append((gpu_state(s), d))
+    for r in res[1:]:
+        assert np.array_equal(res[0][0], r[0]) and np.array_equal(res[0][1], r[1])
+    P = oparams(params_from(model=model, bc=_lib.FVM_DIRICHLET, nx=nx, ny=ny, **kw), ghost)
+    ref = orc.run_dts(P, W, res[0][1], ug=ug)
+    assert rel_linf(res[0][0], ref) <= TOL
+    _, odts = orc.run(P, W, 1, ug=ug)
+    assert ulps(res[0][1][0], odts[0]) <= DT_ULP
+
+
+def test_dirichlet_ghost_states_change_between_runs():
+    """New ghost states apply to the next run (cached launch graphs are
+    rebuilt); the adjoint refuses Dirichlet boundaries."""
+    n = 96
+    W, _, _, ghost = _dirichlet_case(1, n, n, 5)
+    p = params_from(model=1, bc=_lib.FVM_DIRICHLET, nx=n, ny=n, npart_x=2, npart_y=3)
+    s = Solver(p)
+    s.set_boundary_states(ghost)
+    s.set_state(W)
+    d1 = s.run(4, record_dt=True).cpu().numpy()
+    mid = gpu_state(s)
+    ghost2 = ghost[::-1].copy()
+    s.set_boundary_states(ghost2)
+    d2 = s.run(4, record_dt=True).cpu().numpy()
+    got = gpu_state(s)
+    ref = orc.run_dts(oparams(p, ghost), W, d1)
+    assert rel_linf(mid, ref) <= TOL
+    ref = orc.run_dts(oparams(p, ghost2), ref, d2)
+    assert rel_linf(got, ref) <= TOL
+    with pytest.raises(_lib.FvmError):
+        s.adjoint_step(W, 1e-4, np.ones_like(W))
 
 
 def test_pitch_padding_is_untouched():

@@ -5,7 +5,8 @@ tests/emu/strip_emu.cpp compiles the kernels' strip functions as plain C++
 buffer exactly as large as the C ABI's contract. For each model, boundary,
 storage layout, lane layout and a set of widths, heights and tile shapes
 (exact fits, ragged last strips and rows, workgroups wider than the grid),
-it checks that no access leaves the buffers, that every cell of the grid is
+it checks (periodic, transmissive and Dirichlet boundaries) that no access
+leaves the buffers, that every cell of the grid is
 written once a full sweep of tiles has run, that padding columns are never
 written, and that a uniform state is left bitwise unchanged.
 """
@@ -39,7 +40,7 @@ def emu(tmp_path_factory):
 
 def test_strips_stay_in_bounds_and_cover_the_grid(emu):
     cases = []
-    for model, bc, layout, cpl in itertools.product((0, 1, 2), (0, 1), (0, 1), (1, 2)):
+    for model, bc, layout, cpl in itertools.product((0, 1, 2), (0, 1, 2), (0, 1), (1, 2)):
         for nx, ny, ld, rows, wpb in SHAPES:
             cases.append((model, bc, nx, ny, ld, layout, cpl, rows, wpb))
     env = dict(os.environ, ASAN_OPTIONS="detect_leaks=0:abort_on_error=0")
