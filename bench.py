@@ -195,6 +195,43 @@ def bench_adjoint(reps, layout="rows", tuning=TUNING):
             "status": s.sync()}
 
 
+def bench_adjoint_step_4096(reps, layout="rows", tuning=TUNING):
+    """One adjoint step of the 4096^2 Euler grid (reads W^n and lam^{n+1},
+    writes lam^n: 96 algorithmic bytes per cell), timed per launch."""
+    import ctypes as C
+    import torch
+    import numpy as np
+    from paper_1701_05431_amd import inputs
+    from paper_1701_05431_amd._lib import check, lib
+    from paper_1701_05431_amd.solver import Solver, params_from
+    pre = inputs.EULER_4096
+    s = Solver(params_from(pre, layout=LAYOUTS[layout]))
+    W0 = torch.from_numpy(inputs.riemann_state(pre.nx, pre.ny, 0))
+    W = s._as_state(W0)  # storage in the grid's layout
+    g = torch.Generator().manual_seed(0)
+    la = s._as_state(torch.randn((s.nv, pre.ny, pre.nx), dtype=torch.float64, generator=g))
+    lb = torch.empty_like(la)
+    s.set_state(W0)
+    s.autotune(tuning)  # also picks the adjoint kernel's tile shape
+    dt = s.cfl_dt()[0]
+    L = lib()
+    ptr = lambda t: C.c_void_p(t.data_ptr())
+    s._bind_stream()
+
+    def two():
+        check(L.fvm_adjoint_step(s.h, ptr(W), dt, ptr(la), ptr(lb)), "fvm_adjoint_step")
+        check(L.fvm_adjoint_step(s.h, ptr(W), dt, ptr(lb), ptr(la)), "fvm_adjoint_step")
+
+    two()
+    sec = timed(two, reps) / 2
+    assert bool(torch.isfinite(la).all())
+    cells = pre.nx * pre.ny
+    gbs = 96.0 * cells / sec / 1e9
+    return {"workload": "euler_adjoint_step_4096x4096", "us_per_step": sec * 1e6,
+            "bytes_per_cell": 96, "hbm_gbs": gbs, "hbm_frac": gbs / HBM_PEAK_GBS,
+            "gcell_updates_per_s": cells / sec / 1e9}
+
+
 def bench_advection(steps):
     import torch
     from paper_1701_05431_amd import inputs
@@ -267,7 +304,7 @@ def main():
     ap.add_argument("--rows", type=int, default=0)
     ap.add_argument("--wpb", type=int, default=0)
     ap.add_argument("--only-euler", action="store_true")
-    ap.add_argument("--only", choices=["spray", "batch", "adjoint", "advection"],
+    ap.add_argument("--only", choices=["spray", "batch", "adjoint", "adjoint4096", "advection"],
                     help="run just this secondary workload (for profiling) and print its record")
     ap.add_argument("--no-autotune", action="store_true")
     ap.add_argument("--tuning", default=TUNING,
@@ -289,7 +326,8 @@ def main():
         copy_probe(args.copy_probe, 10)
         return
     if args.only:
-        run = {"spray": lambda: bench_spray(args.steps, args.warmup, not args.no_autotune,
+        run = {"adjoint4096": lambda: bench_adjoint_step_4096(50, args.layout, args.tuning),
+               "spray": lambda: bench_spray(args.steps, args.warmup, not args.no_autotune,
                                             args.layout, args.tuning),
                "batch": lambda: bench_batch(args.steps, args.warmup, args.layout, args.tuning),
                "adjoint": lambda: bench_adjoint(1, args.layout, args.tuning),
@@ -316,6 +354,8 @@ def main():
         work["batch"] = bench_batch(100, 4, args.layout, args.tuning)
         log("adjoint")
         work["adjoint"] = bench_adjoint(3, args.layout, args.tuning)
+        log("adjoint step 4096")
+        work["adjoint_step_4096"] = bench_adjoint_step_4096(50, args.layout, args.tuning)
         log("advection")
         work["advection"] = bench_advection(100)
     cpu = None

@@ -236,6 +236,10 @@ int fvm_adjoint_step(fvm_grid* g, const double* w, double dt,
 int fvm_set_tiling(fvm_grid* g, int rows_per_strip, int waves_per_block);
 int fvm_get_tiling(const fvm_grid* g, int* rows_per_strip, int* waves_per_block);
 
+/* Tile shape of the adjoint kernel (rows per strip, waves per block; 0
+ * keeps the current value); results do not depend on it. */
+int fvm_set_adjoint_tiling(fvm_grid* g, int rows_per_strip, int waves_per_block);
+
 /* Lanes of the fused step: 1 = one cell per lane (any pitch), 2 = two
  * adjacent cells per lane with 16-byte accesses (needs an even ld and 16-byte
  * aligned buffers; otherwise the call falls back to 1), 0 = the model's
@@ -248,10 +252,13 @@ int fvm_get_cells_per_lane(const fvm_grid* g);
  * dry-run steps of every candidate (dt = 0, which leaves the bound state bit
  * for bit unchanged) on the bound buffers and stream, applies the fastest,
  * and, if cache_path is non-NULL, appends it to that text file; a later call
- * with the same device, model and grid shape reuses the stored choice without
- * timing. This is the analogue of the paper's per-codelet performance models
- * (Sec. 5.3.2): the task size that runs fastest is chosen by measurement.
- * Synchronises the stream. */
+ * with the same device, model, grid shape and layout reuses the stored
+ * choice without timing. For advection and Euler grids without Dirichlet
+ * boundaries it then picks the adjoint kernel's tile shape the same way
+ * (dry adjoint launches with dt = 0 that write the ping-pong buffer not
+ * holding the current state). This is the analogue of the paper's
+ * per-codelet performance models (Sec. 5.3.2): the task size that runs
+ * fastest is chosen by measurement. Synchronises the stream. */
 int fvm_autotune(fvm_grid* g, const char* cache_path);
 
 /* ---- batches of independent grids -------------------------------------- */

@@ -29,6 +29,11 @@
 #include "fvm_internal.hpp"
 #include "fvm_models.hpp"
 
+// Rows of (W, lambda) loads in flight per adjoint strip.
+#ifndef FVM_ADJ_PREFETCH
+#define FVM_ADJ_PREFETCH 2
+#endif
+
 namespace fvm {
 
 struct AdjAdv {
@@ -55,12 +60,13 @@ struct AdjEuler {
   struct Prim { double r, u, v, p, c; };
   double gamma, gm1;
   __device__ explicit AdjEuler(const ModelConsts& m) : gamma(m.gamma), gm1(m.gm1) {}
+  // (the forward step's refined reciprocal and square root)
   __device__ __forceinline__ void prim(const double* w, Prim& q) const {
-    q.r = 1.0 / w[0];
+    q.r = recip(w[0]);
     q.u = w[1] * q.r;
     q.v = w[2] * q.r;
     q.p = gm1 * fma(-0.5, fma(w[1], q.u, w[2] * q.v), w[3]);
-    q.c = sqrt(gamma * q.p * q.r);
+    q.c = root(gamma * q.p * q.r);
   }
   // out = A(W)^T d along axis D
   template <int D>
@@ -82,7 +88,7 @@ struct AdjEuler {
   __device__ __forceinline__ void dspeed(const Prim& q, double* gs) const {
     const double un = D == 0 ? q.u : q.v;
     const double sg = un >= 0.0 ? 1.0 : -1.0;
-    const double k = 0.5 * gamma * q.r / q.c;
+    const double k = 0.5 * gamma * q.r * recip(q.c);
     const double hq2 = 0.5 * (q.u * q.u + q.v * q.v);
     gs[0] = -sg * un * q.r + k * (gm1 * hq2 - q.p * q.r);
     gs[1] = -k * gm1 * q.u;
@@ -182,64 +188,69 @@ __global__ __launch_bounds__(WPB * kWave) void adjoint_kernel(AdjointArgs a) {
   const double* wb = a.w + ic;
   const double* lb = a.lam_in + ic;
 
-  double Wc[NV], Lc[NV], Wn[NV], Ln[NV], Bs[NV], As[NV];
-  Prim Pc, Pn;
-  load_adj_row<NV, BC>(Wc, Lc, wb, lb, g, j0 - 1, ghost_col);
-  load_adj_row<NV, BC>(Wn, Ln, wb, lb, g, j0, ghost_col);
-  m.prim(Wc, Pc);
-  m.prim(Wn, Pn);
+  // Register ring of R = PF + 2 rows of (W, lambda): row j in slot c, row j+1
+  // in slot n, rows up to j+1+PF loading into the slot row j-1 vacated. The
+  // row loop is unrolled R times so every slot index is static; rows past
+  // the strip are computed from clamped loads and not stored.
+  constexpr int PF = FVM_ADJ_PREFETCH;
+  constexpr int R = PF + 2;
+  double W[R][NV], L[R][NV], Bs[NV], As[NV];
+  Prim P[R];
+  load_adj_row<NV, BC>(W[R - 1], L[R - 1], wb, lb, g, j0 - 1, ghost_col);
+  load_adj_row<NV, BC>(W[0], L[0], wb, lb, g, j0, ghost_col);
+#pragma unroll
+  for (int p = 1; p <= PF; ++p)
+    load_adj_row<NV, BC>(W[p], L[p], wb, lb, g, min(j0 + p, j1), ghost_col);
+  m.prim(W[R - 1], P[R - 1]);
+  m.prim(W[0], P[0]);
   {
     double d[NV];
 #pragma unroll
-    for (int v = 0; v < NV; ++v) d[v] = Ln[v] - Lc[v];
-    m.template face<1>(Wc, Pc, Wn, Pn, d, As, Bs);  // As: the row below's share
+    for (int v = 0; v < NV; ++v) d[v] = L[0][v] - L[R - 1][v];
+    m.template face<1>(W[R - 1], P[R - 1], W[0], P[0], d, As, Bs);  // As: the row below's share
   }
-#pragma unroll
-  for (int v = 0; v < NV; ++v) {
-    Wc[v] = Wn[v];
-    Lc[v] = Ln[v];
-  }
-  Pc = Pn;
 
-  for (int j = j0; j < j1; ++j) {
-    load_adj_row<NV, BC>(Wn, Ln, wb, lb, g, j + 1, ghost_col);
-    m.prim(Wn, Pn);
-    double d[NV], Ay[NV], By[NV], Wr[NV], Lr[NV], Ax[NV], Bx[NV];
-    Prim Pr;
+  for (int jb = j0; jb < j1; jb += R) {
 #pragma unroll
-    for (int v = 0; v < NV; ++v) d[v] = Ln[v] - Lc[v];
-    m.template face<1>(Wc, Pc, Wn, Pn, d, Ay, By);
-    m.shift_next(Wc, Pc, Wr, Pr);
+    for (int u = 0; u < R; ++u) {
+      const int j = jb + u;
+      const int c = u, n = (u + 1) % R, l = (u + R - 1) % R;
+      load_adj_row<NV, BC>(W[l], L[l], wb, lb, g, min(j + 1 + PF, j1), ghost_col);
+      m.prim(W[n], P[n]);
+      double d[NV], Ay[NV], By[NV], Wr[NV], Lr[NV], Ax[NV], Bx[NV];
+      Prim Pr;
 #pragma unroll
-    for (int v = 0; v < NV; ++v) {
-      Lr[v] = from_next(Lc[v]);
-      d[v] = Lr[v] - Lc[v];
+      for (int v = 0; v < NV; ++v) d[v] = L[n][v] - L[c][v];
+      m.template face<1>(W[c], P[c], W[n], P[n], d, Ay, By);
+      m.shift_next(W[c], P[c], Wr, Pr);
+#pragma unroll
+      for (int v = 0; v < NV; ++v) {
+        Lr[v] = from_next(L[c][v]);
+        d[v] = Lr[v] - L[c][v];
+      }
+      m.template face<0>(W[c], P[c], Wr, Pr, d, Ax, Bx);
+      const bool south = BC == 1 && j == 0;
+      const bool north = BC == 1 && j == g.ny - 1;
+      const size_t cell = static_cast<size_t>(j) * g.ld + ic;
+#pragma unroll
+      for (int v = 0; v < NV; ++v) {
+        const double bw = from_prev(Bx[v]);
+        const double aw = from_prev(Ax[v]);
+        double sx = Ax[v] + bw;
+        if (west) sx += aw;
+        if (east) sx += Bx[v];
+        double sy = Ay[v] + Bs[v];
+        if (south) sy += As[v];
+        if (north) sy += By[v];
+        const double lo = L[c][v] + (mux * sx + muy * sy);
+        if (out && j < j1) a.lam_out[v * g.plane + cell] = lo;
+      }
+#pragma unroll
+      for (int v = 0; v < NV; ++v) {
+        Bs[v] = By[v];
+        As[v] = 0.0;
+      }
     }
-    m.template face<0>(Wc, Pc, Wr, Pr, d, Ax, Bx);
-    const bool south = BC == 1 && j == 0;
-    const bool north = BC == 1 && j == g.ny - 1;
-    const size_t cell = static_cast<size_t>(j) * g.ld + ic;
-#pragma unroll
-    for (int v = 0; v < NV; ++v) {
-      const double bw = from_prev(Bx[v]);
-      const double aw = from_prev(Ax[v]);
-      double sx = Ax[v] + bw;
-      if (west) sx += aw;
-      if (east) sx += Bx[v];
-      double sy = Ay[v] + Bs[v];
-      if (south) sy += As[v];
-      if (north) sy += By[v];
-      const double lo = Lc[v] + (mux * sx + muy * sy);
-      if (out) a.lam_out[v * g.plane + cell] = lo;
-    }
-#pragma unroll
-    for (int v = 0; v < NV; ++v) {
-      Wc[v] = Wn[v];
-      Lc[v] = Ln[v];
-      Bs[v] = By[v];
-      As[v] = 0.0;
-    }
-    Pc = Pn;
   }
 }
 

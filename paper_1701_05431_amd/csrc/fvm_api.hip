@@ -648,6 +648,70 @@ static double time_dry(fvm_grid* g, int n, int reps) {
   return us;
 }
 
+// Times `reps` dry adjoint launches in the current adjoint tiling: W is the
+// current state, lambda the other ping-pong buffer (which holds no state),
+// read and written in place; with dt = 0 every cell writes back the value it
+// read, so the launches move the real traffic and change nothing.
+static double time_adjoint_dry(fvm_grid* g, int reps) {
+  AdjointArgs a{};
+  a.w = g->cur;
+  a.lam_in = g->other(g->cur);
+  a.lam_out = g->other(g->cur);
+  a.dts = nullptr;
+  a.dt_arg = 0.0;
+  a.g = g->g;
+  a.t = adjoint_tiling(g->g, g->adj_rows, g->adj_wpb);
+  a.m = g->m;
+  hipEvent_t e0, e1;
+  if (hipEventCreate(&e0) != hipSuccess) return -1.0;
+  if (hipEventCreate(&e1) != hipSuccess) {
+    (void)hipEventDestroy(e0);
+    return -1.0;
+  }
+  double us = -1.0;
+  bool ok = launch_adjoint(a, g->p.model, g->stream) == hipSuccess;  // warm-up
+  ok = ok && hipEventRecord(e0, g->stream) == hipSuccess;
+  for (int r = 0; r < reps && ok; ++r) ok = launch_adjoint(a, g->p.model, g->stream) == hipSuccess;
+  ok = ok && hipEventRecord(e1, g->stream) == hipSuccess && hipEventSynchronize(e1) == hipSuccess;
+  float ms = 0.0f;
+  if (ok && hipEventElapsedTime(&ms, e0, e1) == hipSuccess) us = 1e3 * ms / reps;
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  return us;
+}
+
+// The adjoint kernel's tile shape (advection and Euler, not Dirichlet).
+static int tune_adjoint(fvm_grid* g, const char* cache_path, const std::string& key) {
+  if (g->p.model == FVM_SPRAY || g->p.bc == FVM_DIRICHLET) return FVM_OK;
+  int rows = 0, wpb = 0, cpl = 0;
+  if (cache_lookup(cache_path, key, &rows, &wpb, &cpl) && valid_tiling(rows, wpb)) {
+    g->adj_rows = rows;
+    g->adj_wpb = wpb;
+    return FVM_OK;
+  }
+  const int wpbs[4] = {1, 2, 4, 8};
+  const int rowss[9] = {4, 8, 16, 32, 48, 64, 96, 128, 256};
+  double best = 1e300;
+  int br = g->adj_rows, bw = g->adj_wpb;
+  for (int w : wpbs)
+    for (int r : rowss) {
+      if (r > g->p.ny && r != rowss[0]) continue;
+      g->adj_rows = r;
+      g->adj_wpb = w;
+      const double us = time_adjoint_dry(g, 4);
+      if (us < 0) return FVM_EDEVICE;
+      if (us < best) {
+        best = us;
+        br = r;
+        bw = w;
+      }
+    }
+  g->adj_rows = br;
+  g->adj_wpb = bw;
+  cache_store(cache_path, key, br, bw, 1, best);
+  return FVM_OK;
+}
+
 extern "C" {
 
 int fvm_autotune(fvm_grid* g, const char* cache_path) {
@@ -665,7 +729,7 @@ int fvm_autotune(fvm_grid* g, const char* cache_path) {
     g->cpl_req = cpl;
     g->clear_graphs();
     choose_layout(g);
-    return FVM_OK;
+    return tune_adjoint(g, cache_path, key + " adjoint");
   }
   const int cpls[2] = {2, 1};
   const int wpbs[4] = {1, 2, 4, 8};
@@ -702,7 +766,7 @@ int fvm_autotune(fvm_grid* g, const char* cache_path) {
   choose_layout(g);
   g->speeds_valid = true;  // the dry runs recomputed the maxima of the unchanged state
   cache_store(cache_path, key, br, bw, bc, best);
-  return FVM_OK;
+  return tune_adjoint(g, cache_path, key + " adjoint");
 }
 
 int fvm_set_cells_per_lane(fvm_grid* g, int cpl) {
@@ -713,6 +777,16 @@ int fvm_set_cells_per_lane(fvm_grid* g, int cpl) {
 }
 
 int fvm_get_cells_per_lane(const fvm_grid* g) { return g ? g->cpl : 0; }
+
+int fvm_set_adjoint_tiling(fvm_grid* g, int rows, int wpb) {
+  if (!g) return FVM_EINVAL;
+  const int r = rows ? rows : g->adj_rows;
+  const int w = wpb ? wpb : g->adj_wpb;
+  if (!valid_tiling(r, w)) return FVM_EINVAL;
+  g->adj_rows = r;
+  g->adj_wpb = w;
+  return FVM_OK;
+}
 
 int fvm_get_tiling(const fvm_grid* g, int* rows, int* wpb) {
   if (!g || !rows || !wpb) return FVM_EINVAL;

@@ -530,6 +530,25 @@ def test_adjoint_step_covers_every_column(nx):
     assert rel_linf(got[:, :, :nx].cpu().numpy(), ref) <= TOL
 
 
+def test_adjoint_tiling_invariance_bitwise():
+    nx, ny = 300, 77
+    W = inputs.riemann_state(nx, ny, 13)
+    lam = np.random.default_rng(5).standard_normal(W.shape)
+    outs = []
+    for bc in (0, 1):
+        p = params_from(model=1, bc=bc, nx=nx, ny=ny)
+        s = Solver(p)
+        _, _, dt = orc.cfl(oparams(p), W)
+        res = []
+        for rows, wpb in ((64, 4), (1, 1), (7, 2), (33, 8), (256, 4)):
+            s.set_adjoint_tiling(rows, wpb)
+            res.append(s.adjoint_step(W, dt, lam).cpu().numpy())
+        for r in res[1:]:
+            assert np.array_equal(r, res[0]), bc
+        outs.append(res[0])
+    assert not np.array_equal(outs[0], outs[1])
+
+
 def test_fvrun_gradient_matches_oracle_and_fd():
     n = 32
     W0 = inputs.riemann_state(n, n, 0)
