@@ -91,9 +91,7 @@ __global__ FVM_STEP_BOUNDS(WPB) void batch_kernel(BatchArgs a) {
       const int j1 = min(j0 + a.rows, G.g.ny);
       const double* win = a.win + G.offset;
       double* wout = a.wout + G.offset;
-      if (!wide && FVM_LEGACY_STRIP)
-        march_strip<M, BC>(m, win, wout, nullptr, G.g, xs, j0, j1, mux, muy, dt, bx, by);
-      else if (!wide && xs + kWave <= G.g.nx)
+      if (!wide && xs + kWave <= G.g.nx)
         march_strip1<M, BC, false>(m, win, wout, nullptr, G.g, xs, j0, j1, mux, muy, dt, bx, by);
       else if (!wide)
         march_strip1<M, BC, true>(m, win, wout, nullptr, G.g, xs, j0, j1, mux, muy, dt, bx, by);

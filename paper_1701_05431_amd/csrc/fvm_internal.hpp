@@ -12,7 +12,7 @@ struct fvm_params;
 namespace fvm {
 
 constexpr int kWave = 64;       // CDNA wavefront width
-constexpr int kOutPerWave = 62; // cells a 64-lane wave strip updates (2 halo lanes)
+constexpr int kOutPerWave = 62; // cells an adjoint strip updates (lanes 0 and 63: halo)
 constexpr int kMaxVar = 6;      // largest nVar (spray)
 
 // Boundary conditions (template argument BC of the kernels).
@@ -74,14 +74,7 @@ struct GridGeom {
 GridGeom grid_geometry(const fvm_params& p);
 
 // Cells a wave strip updates: 64 with one cell per lane, 128 with two.
-// (FVM_LEGACY_STRIP selects the older one-cell strip whose lanes 0 and 63
-// are the halo: 62 cells.)
-#ifndef FVM_LEGACY_STRIP
-#define FVM_LEGACY_STRIP 0
-#endif
-__host__ __device__ constexpr int strip_width(int cpl) {
-  return cpl == 2 ? 2 * kWave : (FVM_LEGACY_STRIP ? kOutPerWave : kWave);
-}
+__host__ __device__ constexpr int strip_width(int cpl) { return cpl == 2 ? 2 * kWave : kWave; }
 
 // Tile decomposition of one grid for a launch.
 struct Tiling {

@@ -2,21 +2,22 @@
 //
 // One launch performs one whole time step (Sec. 2.2.1 eq. VF_scheme + the
 // split source of Sec. 2.2.2 + the time-step reduction of eq. CFL_cond) on
-// a grid held as FP64 structure-of-arrays planes in HBM.
+// a grid held as FP64 rows in HBM (one row of nx values per variable and
+// grid row, planar or row-interleaved).
 //
-// Work decomposition. A wave (64 lanes) owns a strip of 64 consecutive
-// columns [xs-1, xs+62] and marches up a range of rows. Lane l holds the
-// state of column xs-1+l for the current row and the next row in registers;
-// the rows below and above come from the march (each y-face flux is computed
-// once and carried to the next row), and the left/right neighbours come from
-// the adjacent lanes by DPP moves (each x-face flux is computed once by the
-// lane on its left and handed to the lane on its right). Lanes 1..62 write
-// their updated cells; lanes 0 and 63 only supply the halo. This replaces the
-// paper's overlap strips and its copyOverlaps / internalResiduals /
-// borderResiduals / update tasks: a subdomain border is an ordinary neighbour
-// read straight from HBM, and every cell goes through the same code path, so
-// the result does not depend on how the grid is split into subdomains or
-// tiles.
+// Work decomposition. A wave (64 lanes) owns a strip of 128 consecutive
+// columns (two cells per lane, 16-byte accesses) or 64 (one per lane) and
+// marches up a range of rows. Each lane keeps its cells of the current row
+// and of the rows in flight in registers; the rows below and above come from
+// the march (each y-face flux is computed once and carried to the next row),
+// the left/right neighbours from the adjacent lanes by DPP moves (each x-face
+// flux is computed once and handed to the lane on its right), and the two
+// faces at the strip's ends from a halo cell that lanes 0 and 63 load. This
+// replaces the paper's overlap strips and its copyOverlaps / internalResiduals
+// / borderResiduals / update tasks: a subdomain border is an ordinary
+// neighbour read straight from HBM, and every cell goes through the same code
+// path, so the result does not depend on how the grid is split into
+// subdomains or tiles.
 //
 // Each state is read once and written once per step (plus the halo rows and
 // columns of each strip). The new state's speeds are reduced in the same
@@ -35,7 +36,7 @@
 
 namespace fvm {
 
-// One wave strip of the CPL layout (1: 62 cells per wave, any pitch; 2: 128
+// One wave strip of the CPL layout (1: 64 cells per wave, any pitch; 2: 128
 // cells per wave, 16-byte aligned accesses).
 // (gh: the Dirichlet ghost states, BC == kDirichlet only)
 template <class M, int BC, int CPL>
@@ -46,9 +47,7 @@ __device__ __forceinline__ void strip(const M& m, const double* __restrict__ win
                                       unsigned long long& by, const double* gh) {
   if (xs >= g.nx) return;
   if (CPL == 1) {
-    if constexpr (FVM_LEGACY_STRIP && BC != kDirichlet)
-      march_strip<M, BC>(m, win, wout, ug, g, xs, j0, j1, mux, muy, dt, bx, by);
-    else if (xs + kWave <= g.nx)
+    if (xs + kWave <= g.nx)
       march_strip1<M, BC, false>(m, win, wout, ug, g, xs, j0, j1, mux, muy, dt, bx, by, gh);
     else
       march_strip1<M, BC, true>(m, win, wout, ug, g, xs, j0, j1, mux, muy, dt, bx, by, gh);

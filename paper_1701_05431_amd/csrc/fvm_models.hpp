@@ -15,17 +15,8 @@
 
 #include "fvm_internal.hpp"
 
-// Rows of loads kept in flight per wave strip (register ring depth).
-#ifndef FVM_PREFETCH_ADV
-#define FVM_PREFETCH_ADV 4
-#endif
-#ifndef FVM_PREFETCH_EULER
-#define FVM_PREFETCH_EULER 3
-#endif
-#ifndef FVM_PREFETCH_SPRAY
-#define FVM_PREFETCH_SPRAY 2
-#endif
-// ... and for the two-cells-per-lane layout
+// Rows of loads kept in flight per wave strip (register ring depth), for
+// the two-cells-per-lane layout
 #ifndef FVM_PREFETCH2_ADV
 #define FVM_PREFETCH2_ADV 2
 #endif
@@ -135,7 +126,6 @@ __device__ __forceinline__ int wave_index() {
 // a linear flux in exact arithmetic).
 struct Adv {
   static constexpr int NV = 1;
-  static constexpr int kPrefetch = FVM_PREFETCH_ADV;
   static constexpr int kPrefetch2 = FVM_PREFETCH2_ADV;
   static constexpr int kPrefetch1 = FVM_PREFETCH1_ADV;
   struct Prim {};
@@ -168,7 +158,6 @@ struct Adv {
 // sigma = max(|u_L.n| + c_L, |u_R.n| + c_R)  (Sec. 2.2.1).
 struct Euler {
   static constexpr int NV = 4;
-  static constexpr int kPrefetch = FVM_PREFETCH_EULER;
   static constexpr int kPrefetch2 = FVM_PREFETCH2_EULER;
   static constexpr int kPrefetch1 = FVM_PREFETCH1_EULER;
   struct Prim { double u, v, p, c; };
@@ -229,7 +218,6 @@ struct Euler {
 // (m_0, m_{1/2}, m_{2/2}).
 struct Spray {
   static constexpr int NV = 6;
-  static constexpr int kPrefetch = FVM_PREFETCH_SPRAY;
   static constexpr int kPrefetch2 = FVM_PREFETCH2_SPRAY;
   static constexpr int kPrefetch1 = FVM_PREFETCH1_SPRAY;
   struct Prim { double ux, uy; };

@@ -107,97 +107,25 @@ __device__ __forceinline__ unsigned long long wave_max64(unsigned long long x) {
   return x;
 }
 
-// ---- one strip ---------------------------------------------------------------
-// Updates rows [j0, j1) of columns [xs, xs+62) ∩ [0, nx) and folds the new
-// cells' speeds into (bx, by).
-template <class M, int BC>
-__device__ __forceinline__ void march_strip(const M& m, const double* __restrict__ win,
-                                            double* __restrict__ wout,
-                                            const double* __restrict__ ug, const GridGeom& g,
-                                            int xs, int j0, int j1, double mux, double muy,
-                                            double dt, unsigned long long& bx,
-                                            unsigned long long& by) {
-  static_assert(BC != kDirichlet, "the one-cell strips handle Dirichlet boundaries");
-  constexpr int NV = M::NV;
-  using Prim = typename M::Prim;
-  const int lane = threadIdx.x & (kWave - 1);
-  const int i = xs - 1 + lane;
-  const int ic = col_index<BC>(i, g.nx);
-  const bool out = (lane >= 1) & (lane <= kOutPerWave) & (i < g.nx);
-  const double* base = win + ic;
+// ---- the marching wave strip ----------------------------------------------------------
+// A wave strip updates rows [j0, j1) of a band of consecutive columns and
+// folds the new cells' speeds into (bx, by). Both lane layouts below keep a
+// register ring of R = PF + 2 rows: while row j is updated, rows j+1 .. j+PF
+// are loaded or in flight and the load of row j+1+PF goes into the slot that
+// held row j-1 (slot of row r: (r - j0) mod R, row j0-1 in slot R-1). The row
+// loop is unrolled R times so every slot is a fixed set of registers and no
+// row is copied; the primitives and the y-face flux below each row live in
+// rings of the same period. Rows past the strip's last halo row j1 are never
+// needed: their loads re-read row j1 and the rows computed past j1 - 1 are
+// not stored, so the unrolled body carries no branches.
 
-  // Register ring of R = PF + 2 rows: while row j is updated, rows j+1 ..
-  // j+PF are loaded or in flight and the load of row j+1+PF is issued into
-  // the slot that held row j-1. Slot of row r: (r - j0) mod R (row j0-1 ->
-  // slot R-1). The loop is unrolled R times so every slot is a fixed set of
-  // registers and no row is ever copied. The primitives and the y-face flux
-  // below each row live in rings of the same period.
-  constexpr int PF = M::kPrefetch;
-  constexpr int R = PF + 2;
-  double W[R][NV], G[R][NV];
-  Prim P[R];
-  // Rows past the strip's last halo row j1 are never needed: their loads
-  // re-read row j1 (an L2 hit) and the rows computed past j1 - 1 are not
-  // stored, so the unrolled body carries no branches.
-  load_row<NV, BC>(W[R - 1], base, g, j0 - 1);
-  load_row<NV, BC>(W[0], base, g, j0);
-#pragma unroll
-  for (int p = 1; p <= PF; ++p) load_row<NV, BC>(W[p], base, g, min(j0 + p, j1));
-  m.prim(W[R - 1], P[R - 1]);
-  m.prim(W[0], P[0]);
-  m.template flux<1>(W[R - 1], P[R - 1], W[0], P[0], G[0]);
-
-  for (int jb = j0; jb < j1; jb += R) {
-#pragma unroll
-    for (int u = 0; u < R; ++u) {
-      const int j = jb + u;
-      {
-        const int c = u, n = (u + 1) % R, l = (u + R - 1) % R;
-        load_row<NV, BC>(W[l], base, g, min(j + 1 + PF, j1));
-        m.prim(W[n], P[n]);
-        double Fe[NV], Wr[NV], Wo[NV];
-        Prim Pr;
-        m.template flux<1>(W[c], P[c], W[n], P[n], G[n]);
-        m.shift_next(W[c], P[c], Wr, Pr);
-        m.template flux<0>(W[c], P[c], Wr, Pr, Fe);
-#pragma unroll
-        for (int v = 0; v < NV; ++v) {
-          const double Fw = from_prev(Fe[v]);
-          Wo[v] = W[c][v] - fma(mux, Fe[v] - Fw, muy * (G[n][v] - G[c][v]));
-        }
-        const size_t cell = static_cast<size_t>(j) * g.ld + ic;
-        if constexpr (NV == 6) {
-          // rows past the strip are computed but not stored; keep their
-          // gas-velocity reads inside the field
-          const size_t uc = ucell(g, min(j, j1 - 1), ic);
-          m.source(Wo, ug[uc], ug[g.uplane + uc], dt);
-        }
-        if (out && j < j1) {
-#pragma unroll
-          for (int v = 0; v < NV; ++v)
-            __builtin_nontemporal_store(Wo[v], wout + v * g.plane + cell);
-          double sx, sy;
-          m.speeds(Wo, sx, sy);
-          bx = umax64(bx, bits(sx));
-          by = umax64(by, bits(sy));
-        }
-      }
-#if FVM_SCHED_BARRIER
-      // keep the scheduler from interleaving consecutive rows, which would
-      // lengthen live ranges and cost occupancy
-      __builtin_amdgcn_sched_barrier(0);
-#endif
-    }
-  }
-}
-
-// ---- one strip, one cell per lane, aligned -------------------------------------------
+// ---- one cell per lane -------------------------------------------------------------
 // Lane l holds cell xs+l: a wave updates 64 consecutive cells (one aligned
-// 512-byte segment per plane and row). The left face of lane 0 and the right
-// face of lane 63 come from a halo cell (lane 0: column xs-1, lane 63: column
-// xs+64) passed through the same flux code, as in the two-cells layout; the
-// other x-faces use DPP moves. EDGE strips reach past the grid's last column
-// (addresses through the boundary map, stores masked).
+// 512-byte segment per variable and row). The left face of lane 0 and the
+// right face of lane 63 come from a halo cell (lane 0: column xs-1, lane 63:
+// column xs+64) passed through the same flux code, as in the two-cells layout;
+// the other x-faces use DPP moves. EDGE strips reach past the grid's last
+// column (addresses through the boundary map, stores masked).
 template <class M, int BC, bool EDGE>
 __device__ __forceinline__ void march_strip1(const M& m, const double* __restrict__ win,
                                              double* __restrict__ wout,
