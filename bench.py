@@ -232,6 +232,36 @@ def bench_adjoint_step_4096(reps, layout="rows", tuning=TUNING):
             "gcell_updates_per_s": cells / sec / 1e9}
 
 
+def bench_slab(steps, warmup, layout="rows", tuning=TUNING):
+    """One GPU's share of the 4096^2 Euler grid cut into 8 slabs of 512 rows:
+    the slab steps with its south and north halo rows read from neighbour
+    buffers (the rows an exchange between GPUs would deliver)."""
+    import torch
+    from paper_1701_05431_amd import inputs
+    from paper_1701_05431_amd.solver import Solver, params_from
+    pre = inputs.EULER_4096
+    rows = pre.ny // 8
+    W = inputs.riemann_state(pre.nx, pre.ny, 0)
+    q = 3  # a slab in the middle of the grid
+    s = Solver(params_from(pre, ny=rows, npart_y=1, ly=rows / pre.ny, layout=LAYOUTS[layout]))
+    s.set_state(torch.from_numpy(W[:, q * rows:(q + 1) * rows]))
+    s.autotune(tuning)
+    south = torch.from_numpy(W[:, q * rows - 1, :].copy()).cuda().contiguous()
+    north = torch.from_numpy(W[:, (q + 1) * rows, :].copy()).cuda().contiguous()
+    s.set_halo_rows(south, north)
+    s.run(warmup)
+    sec = timed(lambda: s.run(steps))
+    cells = pre.nx * rows
+    per = sec / steps
+    gbs = 64.0 * cells / per / 1e9
+    return {"workload": "euler_slab_4096x512_halo_rows", "steps": steps, "status": s.sync(),
+            "us_per_step": per * 1e6, "gcell_updates_per_s": cells / per / 1e9,
+            "hbm_gbs": gbs, "hbm_frac": gbs / HBM_PEAK_GBS,
+            "halo_bytes_per_step": 2 * 4 * pre.nx * 8,
+            "tiling": {"rows_per_strip": s.tiling()[0], "waves_per_block": s.tiling()[1],
+                       "cells_per_lane": s.cells_per_lane()}}
+
+
 def bench_advection(steps):
     import torch
     from paper_1701_05431_amd import inputs
@@ -304,7 +334,8 @@ def main():
     ap.add_argument("--rows", type=int, default=0)
     ap.add_argument("--wpb", type=int, default=0)
     ap.add_argument("--only-euler", action="store_true")
-    ap.add_argument("--only", choices=["spray", "batch", "adjoint", "adjoint4096", "advection"],
+    ap.add_argument("--only", choices=["spray", "batch", "adjoint", "adjoint4096", "slab",
+                                       "advection"],
                     help="run just this secondary workload (for profiling) and print its record")
     ap.add_argument("--no-autotune", action="store_true")
     ap.add_argument("--tuning", default=TUNING,
@@ -327,6 +358,7 @@ def main():
         return
     if args.only:
         run = {"adjoint4096": lambda: bench_adjoint_step_4096(50, args.layout, args.tuning),
+               "slab": lambda: bench_slab(args.steps, args.warmup, args.layout, args.tuning),
                "spray": lambda: bench_spray(args.steps, args.warmup, not args.no_autotune,
                                             args.layout, args.tuning),
                "batch": lambda: bench_batch(args.steps, args.warmup, args.layout, args.tuning),
@@ -356,6 +388,8 @@ def main():
         work["adjoint"] = bench_adjoint(3, args.layout, args.tuning)
         log("adjoint step 4096")
         work["adjoint_step_4096"] = bench_adjoint_step_4096(50, args.layout, args.tuning)
+        log("slab with halo rows")
+        work["slab"] = bench_slab(200, 20, args.layout, args.tuning)
         log("advection")
         work["advection"] = bench_advection(100)
     cpu = None

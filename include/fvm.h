@@ -138,6 +138,18 @@ int fvm_bind(fvm_grid* g, double* w_a, double* w_b, const double* ug,
  * or a non-finite value. Until the first call the ghost states are zero. */
 int fvm_set_boundary_states(fvm_grid* g, const double* ghost);
 
+/* Halo rows (the one-GPU share of the multi-GPU decomposition into slabs):
+ * south and north are caller-owned device buffers, each one row of the
+ * state in the layout [v * ld + i] (nVar * ld doubles), that the steps read
+ * as rows j = -1 and j = ny instead of applying the boundary condition
+ * there -- the rows a slab receives from its neighbours, as the overlap
+ * strips of Sec. 3.2 / 4.1 carry them between subdomains. NULL leaves that
+ * side to the boundary condition. The buffers are read when each step runs,
+ * so the caller may refresh them between steps on the same stream. The
+ * adjoint calls return FVM_EUNSUPPORTED while a halo row is set, and so does
+ * this call for a grid with Dirichlet boundaries. */
+int fvm_set_halo_rows(fvm_grid* g, const double* south, const double* north);
+
 /* Changes the stream later calls enqueue on. */
 int fvm_set_stream(fvm_grid* g, void* stream);
 

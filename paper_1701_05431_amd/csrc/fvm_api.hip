@@ -19,7 +19,7 @@
 #include "fvm_internal.hpp"
 
 namespace fvm {
-void* step_kernel_ptr(int model, int bc, int wpb, int cpl);
+void* step_kernel_ptr(int model, int bc, int wpb, int cpl, bool halo);
 hipError_t launch_step(const StepArgs& a, int model, hipStream_t st);
 hipError_t launch_cfl(const CflArgs& a, int model, hipStream_t st);
 hipError_t launch_clear_scratch(GridScratch* s, int n, hipStream_t st);
@@ -42,6 +42,7 @@ GridGeom grid_geometry(const fvm_params& p) {
     g.uld = p.ld;
     g.uplane = g.plane;
   }
+  g.rld = p.ld;
   g.dx = p.lx / p.nx;
   g.dy = p.ly / p.ny;
   g.cfl = p.cfl;
@@ -194,6 +195,7 @@ struct fvm_grid {
   double* cur = nullptr;
   const double* ug = nullptr;
   double ghost[4 * kMaxVar] = {};  // Dirichlet states, ghost[side * kMaxVar + v]
+  Halo halo{};                     // rows from the caller's buffers
   GridScratch* scr = nullptr;
   hipStream_t stream = nullptr;
   bool bound = false;
@@ -225,6 +227,7 @@ struct fvm_grid {
     a.t = tiling(g, rows, wpb, cpl);
     a.m = m;
     for (int k = 0; k < 4 * kMaxVar; ++k) a.ghost[k] = ghost[k];
+    a.halo = halo;
     return a;
   }
 };
@@ -321,6 +324,15 @@ int fvm_set_boundary_states(fvm_grid* g, const double* ghost) {
   for (int side = 0; side < 4; ++side)
     for (int v = 0; v < g->nv; ++v) g->ghost[side * kMaxVar + v] = ghost[side * g->nv + v];
   g->clear_graphs();  // the cached graphs hold the previous states
+  return FVM_OK;
+}
+
+int fvm_set_halo_rows(fvm_grid* g, const double* south, const double* north) {
+  if (!g) return FVM_EINVAL;
+  if (g->p.bc == FVM_DIRICHLET && (south || north)) return FVM_EUNSUPPORTED;
+  g->halo.s = south;
+  g->halo.n = north;
+  g->clear_graphs();  // the cached graphs hold the previous pointers
   return FVM_OK;
 }
 
@@ -447,7 +459,7 @@ static int graph_for(fvm_grid* g, int kind, int n, double* start, const double* 
   if (hipGraphCreate(&c.graph, 0) != hipSuccess) return FVM_EDEVICE;
   hipGraphNode_t prev = nullptr;
   const double* in = start;
-  void* fn = step_kernel_ptr(g->p.model, g->p.bc, g->wpb, g->cpl);
+  void* fn = step_kernel_ptr(g->p.model, g->p.bc, g->wpb, g->cpl, g->halo.s || g->halo.n);
   std::vector<StepArgs> args(n);
   for (int s = 0; s < n; ++s) {
     double* out = g->other(in);
@@ -799,6 +811,7 @@ int fvm_adjoint_step(fvm_grid* g, const double* w, double dt, const double* lam_
                      double* lam_out) {
   if (!g || !g->bound || !w || !lam_in || !lam_out || lam_in == lam_out) return FVM_EINVAL;
   if (g->p.model == FVM_SPRAY || g->p.bc == FVM_DIRICHLET) return FVM_EUNSUPPORTED;
+  if (g->halo.s || g->halo.n) return FVM_EUNSUPPORTED;
   if (!(dt >= 0.0) || !std::isfinite(dt)) return FVM_EINVAL;
   AdjointArgs a{};
   a.w = w;
@@ -819,6 +832,7 @@ int fvm_adjoint_run(fvm_grid* g, double* const* ckpts, int ckpt_every, const dou
     return FVM_EINVAL;
   if (ckpt_every > 1 && !seg_buf) return FVM_EINVAL;
   if (g->p.model == FVM_SPRAY || g->p.bc == FVM_DIRICHLET) return FVM_EUNSUPPORTED;
+  if (g->halo.s || g->halo.n) return FVM_EUNSUPPORTED;
   const int nck = (nsteps + ckpt_every - 1) / ckpt_every;
   for (int s = 0; s < nck; ++s)
     if (!ckpts[s]) return FVM_EINVAL;

@@ -35,7 +35,7 @@
 
 namespace fvm {
 
-void* step_kernel_ptr(int model, int bc, int wpb, int cpl);
+void* step_kernel_ptr(int model, int bc, int wpb, int cpl, bool halo);
 hipError_t launch_cfl(const CflArgs& a, int model, hipStream_t st);
 hipError_t launch_clear_scratch(GridScratch* s, int n, hipStream_t st);
 
@@ -430,7 +430,7 @@ static int batch_graph(fvm_batch* b, int kind, int nsteps, double* log, int log_
         a.t.tiles_y = r.tiles_y;
         a.t.ntiles = a.t.tiles_x * a.t.tiles_y;
         a.m = b->m;
-        ok = add(step_kernel_ptr(b->model, b->bc, b->wpb, r.cpl), dim3(a.t.ntiles),
+        ok = add(step_kernel_ptr(b->model, b->bc, b->wpb, r.cpl, false), dim3(a.t.ntiles),
                  dim3(b->wpb * kWave),
                  &a);
       }

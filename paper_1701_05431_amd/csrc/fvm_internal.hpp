@@ -67,7 +67,17 @@ struct GridGeom {
   double cfl, dt_max;
   double hmin;                // min(dx, dy) for the fixed-dt check
   size_t uplane;
-  int uld, pad;
+  int uld;
+  int rld;                    // pitch of one variable's row (the caller's ld)
+};
+
+// Rows j = -1 (s) and j = ny (n) read from the caller's buffers instead of
+// the boundary rule, one row each with variable v of column i at
+// [v * rld + i]: the halo rows a slab of a larger grid receives from its
+// neighbours. A null pointer leaves that side to the boundary condition.
+struct Halo {
+  const double* s;
+  const double* n;
 };
 
 // Geometry of a validated parameter set (fvm_api.hip).
@@ -102,6 +112,7 @@ struct StepArgs {
   Tiling t;
   ModelConsts m;
   double ghost[4 * kMaxVar];  // Dirichlet states: ghost[side * kMaxVar + v]
+  Halo halo;
 };
 
 struct CflArgs {

@@ -38,27 +38,33 @@ namespace fvm {
 
 // One wave strip of the CPL layout (1: 64 cells per wave, any pitch; 2: 128
 // cells per wave, 16-byte aligned accesses).
-// (gh: the Dirichlet ghost states, BC == kDirichlet only)
-template <class M, int BC, int CPL>
+// (gh: the Dirichlet ghost states, BC == kDirichlet only; HALO: rows -1 and
+// ny may come from the halo buffers)
+template <class M, int BC, int CPL, bool HALO>
 __device__ __forceinline__ void strip(const M& m, const double* __restrict__ win,
                                       double* __restrict__ wout, const double* __restrict__ ug,
                                       const GridGeom& g, int xs, int j0, int j1, double mux,
                                       double muy, double dt, unsigned long long& bx,
-                                      unsigned long long& by, const double* gh) {
+                                      unsigned long long& by, const double* gh,
+                                      const Halo& halo) {
   if (xs >= g.nx) return;
   if (CPL == 1) {
     if (xs + kWave <= g.nx)
-      march_strip1<M, BC, false>(m, win, wout, ug, g, xs, j0, j1, mux, muy, dt, bx, by, gh);
+      march_strip1<M, BC, false, HALO>(m, win, wout, ug, g, xs, j0, j1, mux, muy, dt, bx, by,
+                                       gh, halo);
     else
-      march_strip1<M, BC, true>(m, win, wout, ug, g, xs, j0, j1, mux, muy, dt, bx, by, gh);
+      march_strip1<M, BC, true, HALO>(m, win, wout, ug, g, xs, j0, j1, mux, muy, dt, bx, by, gh,
+                                      halo);
   } else if (xs + 2 * kWave <= g.nx) {
-    march_strip2<M, BC, false>(m, win, wout, ug, g, xs, j0, j1, mux, muy, dt, bx, by, gh);
+    march_strip2<M, BC, false, M::kPrefetch2, HALO>(m, win, wout, ug, g, xs, j0, j1, mux, muy,
+                                                    dt, bx, by, gh, halo);
   } else {
-    march_strip2<M, BC, true>(m, win, wout, ug, g, xs, j0, j1, mux, muy, dt, bx, by, gh);
+    march_strip2<M, BC, true, M::kPrefetch2, HALO>(m, win, wout, ug, g, xs, j0, j1, mux, muy,
+                                                   dt, bx, by, gh, halo);
   }
 }
 
-template <class M, int BC, int WPB, int CPL>
+template <class M, int BC, int WPB, int CPL, bool HALO>
 __global__ FVM_STEP_BOUNDS(WPB) void step_kernel(StepArgs a) {
   const M m(a.m);
   bool cfl_fail;
@@ -72,7 +78,8 @@ __global__ FVM_STEP_BOUNDS(WPB) void step_kernel(StepArgs a) {
   const int j0 = ty * a.t.rows;
   const int j1 = min(j0 + a.t.rows, a.g.ny);
   unsigned long long bx = 0, by = 0;
-  strip<M, BC, CPL>(m, a.win, a.wout, a.ug, a.g, xs, j0, j1, mux, muy, dt_eff, bx, by, a.ghost);
+  strip<M, BC, CPL, HALO>(m, a.win, a.wout, a.ug, a.g, xs, j0, j1, mux, muy, dt_eff, bx, by,
+                          a.ghost, a.halo);
   if (block_commit<WPB>(bx, by, a.scr, gridDim.x) && threadIdx.x == 0) {
     if (cfl_fail) atomicOr(&a.scr->status, kStatusCfl);
     finalize_grid(a.scr, a.g, dt_eff, a.dt_log, a.dt_log_cap, a.dt_log_stride, nullptr);
@@ -116,42 +123,47 @@ namespace fvm {
 
 using StepFn = void (*)(StepArgs);
 
-template <class M, int BC, int CPL>
+template <class M, int BC, int CPL, bool HALO>
 static StepFn step_fn_wpb(int wpb) {
   switch (wpb) {
-    case 1: return &step_kernel<M, BC, 1, CPL>;
-    case 2: return &step_kernel<M, BC, 2, CPL>;
-    case 4: return &step_kernel<M, BC, 4, CPL>;
-    case 8: return &step_kernel<M, BC, 8, CPL>;
+    case 1: return &step_kernel<M, BC, 1, CPL, HALO>;
+    case 2: return &step_kernel<M, BC, 2, CPL, HALO>;
+    case 4: return &step_kernel<M, BC, 4, CPL, HALO>;
+    case 8: return &step_kernel<M, BC, 8, CPL, HALO>;
     default: return nullptr;
   }
 }
 
+// Halo rows are combined with periodic or transmissive x-boundaries only.
 template <class M, int CPL>
-static StepFn step_fn_cpl(int bc, int wpb) {
+static StepFn step_fn_cpl(int bc, int wpb, bool halo) {
   switch (bc) {
-    case kPeriodic: return step_fn_wpb<M, kPeriodic, CPL>(wpb);
-    case kTransmissive: return step_fn_wpb<M, kTransmissive, CPL>(wpb);
-    case kDirichlet: return step_fn_wpb<M, kDirichlet, CPL>(wpb);
+    case kPeriodic:
+      return halo ? step_fn_wpb<M, kPeriodic, CPL, true>(wpb)
+                  : step_fn_wpb<M, kPeriodic, CPL, false>(wpb);
+    case kTransmissive:
+      return halo ? step_fn_wpb<M, kTransmissive, CPL, true>(wpb)
+                  : step_fn_wpb<M, kTransmissive, CPL, false>(wpb);
+    case kDirichlet: return halo ? nullptr : step_fn_wpb<M, kDirichlet, CPL, false>(wpb);
     default: return nullptr;
   }
 }
 
 template <class M>
-static StepFn step_fn_bc(int bc, int wpb, int cpl) {
-  return cpl == 2 ? step_fn_cpl<M, 2>(bc, wpb) : step_fn_cpl<M, 1>(bc, wpb);
+static StepFn step_fn_bc(int bc, int wpb, int cpl, bool halo) {
+  return cpl == 2 ? step_fn_cpl<M, 2>(bc, wpb, halo) : step_fn_cpl<M, 1>(bc, wpb, halo);
 }
 
-void* step_kernel_ptr(int model, int bc, int wpb, int cpl) {
+void* step_kernel_ptr(int model, int bc, int wpb, int cpl, bool halo) {
   StepFn f = nullptr;
-  if (model == 0) f = step_fn_bc<Adv>(bc, wpb, cpl);
-  else if (model == 1) f = step_fn_bc<Euler>(bc, wpb, cpl);
-  else if (model == 2) f = step_fn_bc<Spray>(bc, wpb, cpl);
+  if (model == 0) f = step_fn_bc<Adv>(bc, wpb, cpl, halo);
+  else if (model == 1) f = step_fn_bc<Euler>(bc, wpb, cpl, halo);
+  else if (model == 2) f = step_fn_bc<Spray>(bc, wpb, cpl, halo);
   return reinterpret_cast<void*>(f);
 }
 
 hipError_t launch_step(const StepArgs& a, int model, hipStream_t st) {
-  void* f = step_kernel_ptr(model, a.g.bc, a.t.wpb, a.t.cpl);
+  void* f = step_kernel_ptr(model, a.g.bc, a.t.wpb, a.t.cpl, a.halo.s || a.halo.n);
   if (!f) return hipErrorInvalidValue;
   StepArgs copy = a;
   void* args[] = {&copy};

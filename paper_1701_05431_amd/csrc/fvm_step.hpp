@@ -67,13 +67,30 @@ __device__ __forceinline__ void ghost_if(double* w, const double* gh, int side, 
   for (int v = 0; v < NV; ++v) w[v] = use ? gh[side * kMaxVar + v] : w[v];
 }
 
-// Row r of a strip's column(s); r may be -1 or ny (the ghost rows). With
-// Dirichlet boundaries those rows are the south / north states (r is uniform
-// across the wave, so is the branch).
+// Row r (-1 or ny) of column c from a halo buffer, if that side has one;
+// returns whether it did (r is uniform across the wave, so is the branch).
+template <int NV>
+__device__ __forceinline__ bool halo_row(double* w, const Halo& h, const GridGeom& g, int r,
+                                         int c) {
+  const double* src = r < 0 ? h.s : h.n;
+  if (!src) return false;
+#pragma unroll
+  for (int v = 0; v < NV; ++v) w[v] = src[v * g.rld + c];
+  return true;
+}
+
+// Row r of a strip's column c (base = w + c); r may be -1 or ny (the ghost
+// rows). Those rows come from the halo buffers when the side has one, else
+// from the boundary rule: with Dirichlet boundaries the south / north states
+// (r is uniform across the wave, so are the branches).
 template <int NV, int BC>
 __device__ __forceinline__ void load_row(double* w, const double* __restrict__ base,
                                          const GridGeom& g, int r,
-                                         const double* gh = nullptr) {
+                                         const double* gh = nullptr, const Halo* h = nullptr,
+                                         int c = 0) {
+  if (h && (r < 0 || r >= g.ny)) {
+    if (halo_row<NV>(w, *h, g, r, c)) return;
+  }
   if constexpr (BC == kDirichlet) {
     if (r < 0 || r >= g.ny) {
       ghost_state<NV>(w, gh, r < 0 ? kSouth : kNorth);
@@ -126,14 +143,14 @@ __device__ __forceinline__ unsigned long long wave_max64(unsigned long long x) {
 // column xs+64) passed through the same flux code, as in the two-cells layout;
 // the other x-faces use DPP moves. EDGE strips reach past the grid's last
 // column (addresses through the boundary map, stores masked).
-template <class M, int BC, bool EDGE>
+template <class M, int BC, bool EDGE, bool HALO = false>
 __device__ __forceinline__ void march_strip1(const M& m, const double* __restrict__ win,
                                              double* __restrict__ wout,
                                              const double* __restrict__ ug, const GridGeom& g,
                                              int xs, int j0, int j1, double mux, double muy,
                                              double dt, unsigned long long& bx,
                                              unsigned long long& by,
-                                             const double* gh = nullptr) {
+                                             const double* gh = nullptr, Halo halo = {}) {
   constexpr int NV = M::NV;
   using Prim = typename M::Prim;
   const int lane = threadIdx.x & (kWave - 1);
@@ -148,11 +165,11 @@ __device__ __forceinline__ void march_strip1(const M& m, const double* __restric
   const bool h_out = hx < 0 || hx >= g.nx;
   const int h_side = first ? kWest : kEast;
   auto wrow = [&](double* w, int r) {
-    load_row<NV, BC>(w, base, g, r, gh);
+    load_row<NV, BC>(w, base, g, r, gh, HALO ? &halo : nullptr, cx);
     if constexpr (BC == kDirichlet && EDGE) ghost_if<NV>(w, gh, kEast, x >= g.nx);
   };
   auto hrow = [&](double* w, int r) {
-    load_row<NV, BC>(w, win + ch, g, r, gh);
+    load_row<NV, BC>(w, win + ch, g, r, gh, HALO ? &halo : nullptr, ch);
     if constexpr (BC == kDirichlet) ghost_if<NV>(w, gh, h_side, h_out);
   };
 
@@ -241,7 +258,13 @@ template <int NV, int BC, bool EDGE>
 __device__ __forceinline__ void load_pair(double* a, double* b, const double* __restrict__ w,
                                           const GridGeom& g, int ca, int cb, int r,
                                           const double* gh = nullptr, bool a_out = false,
-                                          bool b_out = false) {
+                                          bool b_out = false, const Halo* h = nullptr) {
+  if (h && (r < 0 || r >= g.ny)) {
+    if (halo_row<NV>(a, *h, g, r, ca)) {
+      halo_row<NV>(b, *h, g, r, cb);
+      return;
+    }
+  }
   if constexpr (BC == kDirichlet) {
     if (r < 0 || r >= g.ny) {  // uniform
       ghost_state<NV>(a, gh, r < 0 ? kSouth : kNorth);
@@ -268,14 +291,14 @@ __device__ __forceinline__ void load_pair(double* a, double* b, const double* __
   }
 }
 
-template <class M, int BC, bool EDGE, int PF = M::kPrefetch2>
+template <class M, int BC, bool EDGE, int PF = M::kPrefetch2, bool HALO = false>
 __device__ __forceinline__ void march_strip2(const M& m, const double* __restrict__ win,
                                              double* __restrict__ wout,
                                              const double* __restrict__ ug, const GridGeom& g,
                                              int xs, int j0, int j1, double mux, double muy,
                                              double dt, unsigned long long& bx,
                                              unsigned long long& by,
-                                             const double* gh = nullptr) {
+                                             const double* gh = nullptr, Halo halo = {}) {
   constexpr int NV = M::NV;
   using Prim = typename M::Prim;
   const int lane = threadIdx.x & (kWave - 1);
@@ -290,10 +313,10 @@ __device__ __forceinline__ void march_strip2(const M& m, const double* __restric
   const bool h_out = hx < 0 || hx >= g.nx;
   const int h_side = first ? kWest : kEast;
   auto prow = [&](double* a, double* b, int r) {
-    load_pair<NV, BC, EDGE>(a, b, win, g, ca, cb, r, gh, !oka, !okb);
+    load_pair<NV, BC, EDGE>(a, b, win, g, ca, cb, r, gh, !oka, !okb, HALO ? &halo : nullptr);
   };
   auto hrow = [&](double* w, int r) {
-    load_row<NV, BC>(w, win + ch, g, r, gh);
+    load_row<NV, BC>(w, win + ch, g, r, gh, HALO ? &halo : nullptr, ch);
     if constexpr (BC == kDirichlet) ghost_if<NV>(w, gh, h_side, h_out);
   };
 

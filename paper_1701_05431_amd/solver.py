@@ -117,6 +117,16 @@ class Solver:
         check(lib().fvm_set_boundary_states(self.h, g.ctypes.data_as(C.c_void_p)),
               "fvm_set_boundary_states")
 
+    def set_halo_rows(self, south=None, north=None) -> None:
+        """Rows j = -1 and j = ny from device tensors of shape (nVar, ld)
+        (contiguous float64), or None for the boundary condition."""
+        for t in (south, north):
+            if t is not None and (t.dtype != torch.float64 or not t.is_contiguous()
+                                  or tuple(t.shape) != (self.nv, self.p.ld)):
+                raise ValueError("halo rows must be contiguous float64 of shape (nVar, ld)")
+        self._halo = (south, north)  # keep them alive while the plan reads them
+        check(lib().fvm_set_halo_rows(self.h, _ptr(south), _ptr(north)), "fvm_set_halo_rows")
+
     def _bind_stream(self):
         lib().fvm_set_stream(self.h, _stream_handle(self.device))
 

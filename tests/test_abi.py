@@ -113,6 +113,9 @@ def test_create_destroy_and_unbound_calls(L):
     pd = params_from(model=1, nx=64, ny=32, bc=_lib.FVM_DIRICHLET)
     assert L.fvm_create(pd, C.byref(h)) == _lib.FVM_OK
     assert L.fvm_set_boundary_states(h, ghost) == _lib.FVM_OK
+    # halo rows only with periodic or transmissive boundaries (no device access here)
+    assert L.fvm_set_halo_rows(h, C.c_void_p(256), None) == _lib.FVM_EUNSUPPORTED
+    assert L.fvm_set_halo_rows(h, None, None) == _lib.FVM_OK
     ghost[5] = float("nan")
     assert L.fvm_set_boundary_states(h, ghost) == _lib.FVM_EINVAL
     assert L.fvm_set_boundary_states(h, None) == _lib.FVM_EINVAL

@@ -266,6 +266,58 @@ def test_dirichlet_ghost_states_change_between_runs():
         s.adjoint_step(W, 1e-4, np.ones_like(W))
 
 
+@pytest.mark.parametrize("model", [1, 2])
+@pytest.mark.parametrize("bc", [0, 1])
+@pytest.mark.parametrize("layout,cpl", [(0, 2), (1, 2), (1, 1)])
+def test_slabs_with_halo_rows_equal_the_whole_grid(model, bc, layout, cpl):
+    """The one-GPU share of the slab decomposition: a grid cut into 4 slabs
+    of whole rows, each stepped on its own with the neighbours' boundary
+    rows copied into its halo buffers before every step (periodic: the
+    first and last slabs exchange too; transmissive: those sides keep the
+    boundary rule), gives bit for bit the whole-grid steps with the same
+    dts."""
+    nx, ny, k = 260, 96, 4
+    ld = nx + (nx % 2)
+    h = ny // k
+    if model == 1:
+        W = inputs.riemann_state(nx, ny, 21)
+        ug, kw = None, {}
+    else:
+        W, ug = inputs.spray_state(nx, ny, 21)
+        kw = dict(cfl=0.9)
+    full = Solver(params_from(model=model, bc=bc, nx=nx, ny=ny, ld=ld, layout=layout, **kw),
+                  ug=ug)
+    assert full.set_cells_per_lane(cpl) == cpl
+    full.set_state(W)
+    dts = full.run(4, record_dt=True).cpu().numpy()
+    ref = gpu_state(full)
+    slabs, halos = [], []
+    for q in range(k):
+        # the slab's own gas velocity and physical extent (dy unchanged)
+        p = params_from(model=model, bc=bc, nx=nx, ny=h, ld=ld, layout=layout, ly=h / ny, **kw)
+        sl = Solver(p, ug=None if ug is None else ug[:, q * h:(q + 1) * h])
+        assert sl.set_cells_per_lane(cpl) == cpl
+        sl.set_state(W[:, q * h:(q + 1) * h])
+        south = torch.zeros((sl.nv, ld), dtype=torch.float64, device="cuda")
+        north = torch.zeros_like(south)
+        has_s = q > 0 or bc == 0
+        has_n = q < k - 1 or bc == 0
+        sl.set_halo_rows(south if has_s else None, north if has_n else None)
+        slabs.append(sl)
+        halos.append((south, north, has_s, has_n))
+    for dt in dts:
+        cur = [sl.current() for sl in slabs]
+        for q, (south, north, has_s, has_n) in enumerate(halos):
+            if has_s:
+                south.copy_(cur[(q - 1) % k][:, -1, :])
+            if has_n:
+                north.copy_(cur[(q + 1) % k][:, 0, :])
+        for sl in slabs:
+            sl.run_dts([dt])
+    got = np.concatenate([gpu_state(sl) for sl in slabs], axis=1)
+    assert np.array_equal(got, ref)
+
+
 def test_pitch_padding_is_untouched():
     nx, ny, ld = 70, 33, 96
     W = inputs.riemann_state(nx, ny, 2)
