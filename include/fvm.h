@@ -315,9 +315,16 @@ int fvm_batch_sync(fvm_batch* b);
 /* Tile shape of the persistent launch (rows per strip, waves per block). */
 int fvm_batch_set_tiling(fvm_batch* b, int rows_per_strip, int waves_per_block);
 
-/* Autotuner of the persistent launch's tile shape (dry runs with every dt
- * scaled to 0, states unchanged); cache as for fvm_autotune, keyed by the
- * device, model and the list of grid shapes. Synchronises the stream. */
+/* Launch schedule of the batched step: persistent != 0 (the default) runs a
+ * resident set of workgroups that take work items from an atomic queue;
+ * 0 launches one workgroup per item and lets the hardware dispatcher
+ * balance them. Results are bitwise the same either way. */
+int fvm_batch_set_schedule(fvm_batch* b, int persistent);
+
+/* Autotuner of the batched step's tile shape and schedule (dry runs with
+ * every dt scaled to 0, states unchanged); cache as for fvm_autotune, keyed
+ * by the device, model and the list of grid shapes. Synchronises the
+ * stream. */
 int fvm_batch_autotune(fvm_batch* b, const char* cache_path);
 
 #ifdef __cplusplus

@@ -56,7 +56,10 @@ __global__ void batch_log_rewind_kernel(GridScratch* g, int n) {
   if (k < n) g[k].nstep = 0;
 }
 
-template <class M, int BC, int WPB>
+// PERSIST: a resident set of workgroups takes items from the queue until it
+// runs dry; otherwise (grouped launch) workgroup b does item b and the
+// hardware dispatcher balances the load.
+template <class M, int BC, int WPB, bool PERSIST>
 __global__ FVM_STEP_BOUNDS(WPB) void batch_kernel(BatchArgs a) {
   // both lane layouts live in this kernel, so the Euler strips keep one row
   // of loads in flight (not two) to stay within 256 registers per lane
@@ -65,12 +68,17 @@ __global__ FVM_STEP_BOUNDS(WPB) void batch_kernel(BatchArgs a) {
   const int wave = wave_index();
   __shared__ int s_item;
   for (;;) {
-    // the workgroup's next item, through LDS: every thread reads it after
-    // the barrier
-    if (threadIdx.x == 0) s_item = static_cast<int>(atomicAdd(&a.bscr->queue, 1u));
-    __syncthreads();
-    const int item = s_item;
-    __syncthreads();
+    int item;
+    if constexpr (PERSIST) {
+      // the workgroup's next item, through LDS: every thread reads it
+      // after the barrier
+      if (threadIdx.x == 0) s_item = static_cast<int>(atomicAdd(&a.bscr->queue, 1u));
+      __syncthreads();
+      item = s_item;
+      __syncthreads();
+    } else {
+      item = static_cast<int>(blockIdx.x);
+    }
     if (item >= a.nitems) break;
     int lo = 0, hi = a.ngrids - 1;
     while (lo < hi) {
@@ -85,8 +93,11 @@ __global__ FVM_STEP_BOUNDS(WPB) void batch_kernel(BatchArgs a) {
     unsigned long long bx = 0, by = 0;
     if (k < G.nstrips) {
       const int sx = k % G.strips_x, ty = k / G.strips_x;
-      const bool wide = G.cpl == 2;  // uniform across the workgroup
-      const int xs = sx * (wide ? strip_width(2) : strip_width(1));
+      const bool wide_grid = G.cpl == 2;  // uniform across the workgroup
+      const int xs = sx * (wide_grid ? strip_width(2) : strip_width(1));
+      // a two-cells-per-lane grid's last strip with at most 64 columns left
+      // runs one cell per lane (bitwise the same cells, half the idle lanes)
+      const bool wide = wide_grid && xs + kWave < G.g.nx;
       const int j0 = ty * a.rows;
       const int j1 = min(j0 + a.rows, G.g.ny);
       const double* win = a.win + G.offset;
@@ -105,8 +116,9 @@ __global__ FVM_STEP_BOUNDS(WPB) void batch_kernel(BatchArgs a) {
     if (block_commit<WPB>(bx, by, s, static_cast<unsigned int>(G.nitems)) && threadIdx.x == 0)
       finalize_grid(s, G.g, dt, a.dt_log ? a.dt_log + G.user : nullptr, a.dt_log_cap, a.ngrids,
                     nullptr);
+    if constexpr (!PERSIST) break;
   }
-  if (threadIdx.x == 0) {
+  if (PERSIST && threadIdx.x == 0) {
     __threadfence();
     const unsigned int t = atomicAdd(&a.bscr->arrive, 1u);
     if (t == gridDim.x - 1) {
@@ -116,25 +128,26 @@ __global__ FVM_STEP_BOUNDS(WPB) void batch_kernel(BatchArgs a) {
   }
 }
 
-template <class M, int BC>
+template <class M, int BC, bool P>
 static void* batch_fn_wpb(int wpb) {
   switch (wpb) {
-    case 1: return reinterpret_cast<void*>(&batch_kernel<M, BC, 1>);
-    case 2: return reinterpret_cast<void*>(&batch_kernel<M, BC, 2>);
-    case 4: return reinterpret_cast<void*>(&batch_kernel<M, BC, 4>);
-    case 8: return reinterpret_cast<void*>(&batch_kernel<M, BC, 8>);
+    case 1: return reinterpret_cast<void*>(&batch_kernel<M, BC, 1, P>);
+    case 2: return reinterpret_cast<void*>(&batch_kernel<M, BC, 2, P>);
+    case 4: return reinterpret_cast<void*>(&batch_kernel<M, BC, 4, P>);
+    case 8: return reinterpret_cast<void*>(&batch_kernel<M, BC, 8, P>);
     default: return nullptr;
   }
 }
 
-template <class M>
+template <class M, bool P>
 static void* batch_fn_bc(int bc, int wpb) {
-  return bc == 0 ? batch_fn_wpb<M, 0>(wpb) : batch_fn_wpb<M, 1>(wpb);
+  return bc == 0 ? batch_fn_wpb<M, 0, P>(wpb) : batch_fn_wpb<M, 1, P>(wpb);
 }
 
-static void* batch_kernel_ptr(int model, int bc, int wpb) {
-  if (model == 0) return batch_fn_bc<Adv>(bc, wpb);
-  if (model == 1) return batch_fn_bc<Euler>(bc, wpb);
+static void* batch_kernel_ptr(int model, int bc, int wpb, bool persist = true) {
+  if (model == 0) return persist ? batch_fn_bc<Adv, true>(bc, wpb) : batch_fn_bc<Adv, false>(bc, wpb);
+  if (model == 1)
+    return persist ? batch_fn_bc<Euler, true>(bc, wpb) : batch_fn_bc<Euler, false>(bc, wpb);
   return nullptr;
 }
 
@@ -152,6 +165,7 @@ struct BatchGraph {
   const double* start;
   const double* log;
   int rows, wpb;
+  bool persist;
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
 };
@@ -166,6 +180,7 @@ struct fvm_batch {
   std::vector<int> order;        // processing order (largest first)
   ModelConsts m{};
   int rows = 32, wpb = 2;
+  bool persist = true;           // persistent workgroups or one per item
   double* w_a = nullptr;
   double* w_b = nullptr;
   double* cur = nullptr;
@@ -358,7 +373,7 @@ static int batch_graph(fvm_batch* b, int kind, int nsteps, double* log, int log_
                        hipGraphExec_t* exec) {
   for (auto it = b->graphs.begin(); it != b->graphs.end(); ++it) {
     if (it->kind == kind && it->nsteps == nsteps && it->start == b->cur && it->log == log &&
-        it->rows == b->rows && it->wpb == b->wpb) {
+        it->rows == b->rows && it->wpb == b->wpb && it->persist == b->persist) {
       b->graphs.splice(b->graphs.begin(), b->graphs, it);
       *exec = b->graphs.front().exec;
       return FVM_OK;
@@ -371,6 +386,7 @@ static int batch_graph(fvm_batch* b, int kind, int nsteps, double* log, int log_
   c.log = log;
   c.rows = b->rows;
   c.wpb = b->wpb;
+  c.persist = b->persist;
   if (hipGraphCreate(&c.graph, 0) != hipSuccess) return FVM_EDEVICE;
   hipGraphNode_t prev = nullptr;
   const double* in = b->cur;
@@ -407,8 +423,8 @@ static int batch_graph(fvm_batch* b, int kind, int nsteps, double* log, int log_
       a.rows = b->rows;
       a.dt_scale = kind == 2 ? 0.0 : 1.0;
       a.m = b->m;
-      ok = add(batch_kernel_ptr(b->model, b->bc, b->wpb),
-               dim3(std::min(b->nblocks, b->nitems)),
+      ok = add(batch_kernel_ptr(b->model, b->bc, b->wpb, b->persist),
+               dim3(b->persist ? std::min(b->nblocks, b->nitems) : b->nitems),
                dim3(b->wpb * kWave), &a);
     } else {
       for (int q = 0; q < b->n && ok; ++q) {
@@ -490,8 +506,8 @@ int fvm_batch_current(const fvm_batch* b, double** w) {
   return FVM_OK;
 }
 
-// Chooses the batch tiling by timing dry persistent launches (dt scaled to 0,
-// states unchanged) of every candidate; see fvm_autotune.
+// Chooses the batch tiling and schedule by timing dry launches (dt scaled to
+// 0, states unchanged) of every candidate; see fvm_autotune.
 int fvm_batch_autotune(fvm_batch* b, const char* cache_path) {
   if (!b || !b->bound) return FVM_EINVAL;
   unsigned long long h = 1469598103934665603ull;  // FNV-1a over the grid shapes
@@ -514,13 +530,17 @@ int fvm_batch_autotune(fvm_batch* b, const char* cache_path) {
   if (cache_path) {
     std::ifstream in(cache_path);
     std::string line;
-    int r = 0, w = 0, found = 0;
+    int r = 0, w = 0, ps = 1, found = 0;
     while (std::getline(in, line)) {
       const size_t bar = line.find(" | ");
       if (bar == std::string::npos || line.substr(0, bar) != key) continue;
-      if (std::sscanf(line.c_str() + bar + 3, "rows=%d wpb=%d", &r, &w) == 2) found = 1;
+      if (std::sscanf(line.c_str() + bar + 3, "rows=%d wpb=%d persist=%d", &r, &w, &ps) == 3)
+        found = 1;
     }
-    if (found) return fvm_batch_set_tiling(b, r, w);
+    if (found) {
+      b->persist = ps != 0;
+      return fvm_batch_set_tiling(b, r, w);
+    }
   }
   if (!b->speeds_valid) {
     const int rc = fvm_batch_cfl(b);
@@ -534,8 +554,12 @@ int fvm_batch_autotune(fvm_batch* b, const char* cache_path) {
   }
   double best = 1e300;
   int br = b->rows, bw = b->wpb;
+  bool bp = b->persist;
   int rc = FVM_OK;
-  for (int w : {1, 2, 4, 8}) {
+  for (int c = 0; c < 8 && !rc; ++c) {
+    const bool ps = c < 4;  // persistent, then grouped launches
+    const int w = 1 << (c % 4);
+    b->persist = ps;
     for (int r : {8, 16, 32, 48, 64, 96, 128}) {
       rc = fvm_batch_set_tiling(b, r, w);
       if (rc) break;
@@ -557,19 +581,28 @@ int fvm_batch_autotune(fvm_batch* b, const char* cache_path) {
         best = us;
         br = r;
         bw = w;
+        bp = ps;
       }
     }
-    if (rc) break;
   }
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
   if (rc) return rc;
+  b->persist = bp;
   rc = fvm_batch_set_tiling(b, br, bw);
   if (rc == FVM_OK && cache_path) {
     std::ofstream out(cache_path, std::ios::app);
-    out << key << " | rows=" << br << " wpb=" << bw << " us=" << best << "\n";
+    out << key << " | rows=" << br << " wpb=" << bw << " persist=" << (bp ? 1 : 0)
+        << " us=" << best << "\n";
   }
   return rc;
+}
+
+int fvm_batch_set_schedule(fvm_batch* b, int persistent) {
+  if (!b) return FVM_EINVAL;
+  b->persist = persistent != 0;
+  b->clear_graphs();
+  return FVM_OK;
 }
 
 int fvm_batch_sync(fvm_batch* b) {

@@ -332,8 +332,12 @@ class Batch:
         check(lib().fvm_batch_set_tiling(self.h, int(rows), int(waves_per_block)),
               "fvm_batch_set_tiling")
 
+    def set_schedule(self, persistent: bool = True) -> None:
+        """Persistent workgroups over a work queue, or one workgroup per item."""
+        check(lib().fvm_batch_set_schedule(self.h, int(bool(persistent))), "fvm_batch_set_schedule")
+
     def autotune(self, cache_path: str | None = None) -> None:
-        """Picks the persistent launch's tile shape by timing dry runs."""
+        """Picks the batched step's tile shape and schedule by timing dry runs."""
         path = cache_path.encode() if cache_path else None
         check(lib().fvm_batch_autotune(self.h, path), "fvm_batch_autotune")
 

@@ -540,6 +540,15 @@ def test_batch_equals_single_grid_runs():
     b2.set_states(states)
     dts2 = b2.run(9, record_dt=True, per_grid=True).cpu().numpy()
     got2 = [x.cpu().numpy() for x in b2.states()]
+    b3 = Batch(plist)  # one workgroup per item instead of persistent workgroups
+    b3.set_schedule(False)
+    b3.set_tiling(16, 4)
+    b3.set_states(states)
+    dts3 = b3.run(9, record_dt=True).cpu().numpy()
+    got3 = [x.cpu().numpy() for x in b3.states()]
+    assert np.array_equal(dts3, dts)
+    for k in range(len(sizes)):
+        assert np.array_equal(got3[k], got[k]), k
     for k, n in enumerate(sizes):
         s = Solver(plist[k])
         s.set_state(states[k])
