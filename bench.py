@@ -118,15 +118,16 @@ def bench_spray(steps, warmup, autotune=True, layout="rows", tuning=TUNING):
 def bench_batch(steps, warmup, layout="rows", tuning=TUNING):
     import torch
     from paper_1701_05431_amd import inputs
-    from paper_1701_05431_amd.solver import Batch, params_from
+    from paper_1701_05431_amd.solver import Batch, aligned_pitch, params_from
     sizes = inputs.batch_sizes(inputs.BATCH_COUNT, 0)
-    # pitches rounded up to even so that every grid takes two cells per lane
-    plist = [params_from(inputs.BATCH_256, nx=n, ny=n, ld=n + n % 2, layout=LAYOUTS[layout])
+    # pitches rounded up to 128 bytes: rows start on cache lines
+    plist = [params_from(inputs.BATCH_256, nx=n, ny=n, ld=aligned_pitch(n),
+                         layout=LAYOUTS[layout])
              for n in sizes]
     states = [inputs.riemann_state(n, n, k) for k, n in enumerate(sizes)]
     cells = sum(n * n for n in sizes)
     out = {"workload": inputs.BATCH_256.name, "grids": len(sizes), "cells": cells,
-           "pitch": "nx rounded up to even",
+           "pitch": "nx rounded up to a multiple of 16 doubles",
            "steps": steps}
     for name, per_grid in (("persistent", False), ("per_grid", True)):
         b = Batch(plist)

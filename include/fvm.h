@@ -318,8 +318,11 @@ int fvm_batch_set_tiling(fvm_batch* b, int rows_per_strip, int waves_per_block);
 /* Launch schedule of the batched step: persistent != 0 (the default) runs a
  * resident set of workgroups that take work items from an atomic queue;
  * 0 launches one workgroup per item and lets the hardware dispatcher
- * balance them. Results are bitwise the same either way. */
-int fvm_batch_set_schedule(fvm_batch* b, int persistent);
+ * balance them. fit_blocks != 0 cuts each grid into row blocks (at most the
+ * tiling's rows high) whose strip count fills whole workgroups where that
+ * costs fewer wave-rows than idle waves would; 0 (the default) keeps blocks
+ * of the tiling's height. Results are bitwise the same either way. */
+int fvm_batch_set_schedule(fvm_batch* b, int persistent, int fit_blocks);
 
 /* Autotuner of the batched step's tile shape and schedule (dry runs with
  * every dt scaled to 0, states unchanged); cache as for fvm_autotune, keyed

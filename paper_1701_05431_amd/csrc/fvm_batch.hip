@@ -1,12 +1,14 @@
 // fvm_batch.hip -- many independent grids of uneven sizes advanced together.
 //
 // One persistent launch per time step walks a work list of (grid, group of
-// strips) items, largest grids first, handed out by an atomic queue, so that
-// the small grids fill the gaps the large ones leave and no launch is smaller
-// than the chip. A grid's wave strips (the single-grid kernel's strips, `rows`
-// rows each) are numbered row-major and an item is WPB consecutive strips of
-// one grid, one per wave: a grid narrower than a workgroup stacks its waves
-// over several row blocks instead of leaving them idle. The device code per
+// strips) items, longest items (tallest row blocks) first, handed out by an
+// atomic queue, so that short items fill the gaps the long ones leave, the
+// step ends on short ones and no launch is smaller than the chip. A grid's wave strips (the single-grid kernel's strips, over
+// row blocks of near-equal height, at most the tuned `rows`) are numbered
+// row-major and an item is WPB consecutive strips of one grid, one per wave: a
+// grid narrower than a workgroup stacks its waves over several row blocks
+// instead of leaving them idle, and a small grid takes shorter blocks so that
+// it still has a strip for every wave. The device code per
 // strip is the single-grid kernel's, so a grid's result is bit-for-bit the
 // one of a single-grid launch. Each grid keeps its own adaptive dt: the item's
 // workgroup folds its speeds into the grid's maxima and the last item of a
@@ -62,7 +64,8 @@ __global__ void batch_log_rewind_kernel(GridScratch* g, int n) {
 template <class M, int BC, int WPB, bool PERSIST>
 __global__ FVM_STEP_BOUNDS(WPB) void batch_kernel(BatchArgs a) {
   // both lane layouts live in this kernel, so the Euler strips keep one row
-  // of loads in flight (not two) to stay within 256 registers per lane
+  // of loads in flight (not two) to stay within 256 registers per lane (two
+  // rows in flight, even with the one-cell strips left out, spill)
   constexpr int kPF = M::NV >= 4 ? 1 : M::kPrefetch2;
   const M m(a.m);
   const int wave = wave_index();
@@ -86,7 +89,7 @@ __global__ FVM_STEP_BOUNDS(WPB) void batch_kernel(BatchArgs a) {
       if (a.grids[mid].item0 <= item) lo = mid; else hi = mid - 1;
     }
     const BatchGrid G = a.grids[lo];
-    GridScratch* s = a.gscr + lo;
+    GridScratch* s = a.gscr + G.user;
     const double dt = s->dt * a.dt_scale;
     const double mux = dt / G.g.dx, muy = dt / G.g.dy;
     const int k = (item - G.item0) * WPB + wave;  // this wave's strip
@@ -98,8 +101,8 @@ __global__ FVM_STEP_BOUNDS(WPB) void batch_kernel(BatchArgs a) {
       // a two-cells-per-lane grid's last strip with at most 64 columns left
       // runs one cell per lane (bitwise the same cells, half the idle lanes)
       const bool wide = wide_grid && xs + kWave < G.g.nx;
-      const int j0 = ty * a.rows;
-      const int j1 = min(j0 + a.rows, G.g.ny);
+      const int j0 = ty * G.rows;
+      const int j1 = min(j0 + G.rows, G.g.ny);
       const double* win = a.win + G.offset;
       double* wout = a.wout + G.offset;
       if (!wide && xs + kWave <= G.g.nx)
@@ -165,7 +168,7 @@ struct BatchGraph {
   const double* start;
   const double* log;
   int rows, wpb;
-  bool persist;
+  bool persist, fit;
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
 };
@@ -177,10 +180,11 @@ struct fvm_batch {
   int model = 0, bc = 0, nv = 0;
   std::vector<fvm_params> p;
   std::vector<size_t> offsets;
-  std::vector<int> order;        // processing order (largest first)
+  std::vector<int> order;        // grids by decreasing area
   ModelConsts m{};
   int rows = 32, wpb = 2;
   bool persist = true;           // persistent workgroups or one per item
+  bool fit = false;              // row blocks chosen to fill whole workgroups
   double* w_a = nullptr;
   double* w_b = nullptr;
   double* cur = nullptr;
@@ -189,7 +193,7 @@ struct fvm_batch {
   bool bound = false, speeds_valid = false;
   int nitems = 0;
   int nblocks = 0;               // persistent workgroups
-  std::vector<BatchGrid> recs;   // in processing order
+  std::vector<BatchGrid> recs;   // in processing order (per-grid scratch: by caller index)
   std::list<BatchGraph> graphs;
 
   ~fvm_batch() { clear_graphs(); }
@@ -210,10 +214,12 @@ struct fvm_batch {
   }
   double* other(const double* w) const { return w == w_a ? w_b : w_a; }
 
+  static constexpr int kMinRows = 8;
+  static constexpr int kStripCostRows = 4;  // a strip's start-up, in rows
+
   // (re)builds the work list for the current tiling
   void plan() {
     recs.clear();
-    int item = 0;
     for (int k : order) {
       BatchGrid r{};
       r.offset = offsets[k];
@@ -226,12 +232,44 @@ struct fvm_batch {
       r.cpl = p[k].ld % 2 == 0 ? 2 : 1;
       const int w = strip_width(r.cpl);
       r.strips_x = (g.nx + w - 1) / w;
-      r.tiles_y = (g.ny + rows - 1) / rows;
+      // row blocks of near-equal height (a workgroup waits for its longest
+      // strip), at most `rows` high. A grid with fewer strips than a
+      // workgroup has waves is cut into shorter blocks, down to kMinRows, so
+      // that its item keeps the waves busy. With `fit`, the block count is
+      // the one that occupies the fewest wave-rows, counting the idle waves
+      // of a grid's last, partly filled item and a fixed cost per strip, so
+      // a grid whose strip count does not divide into whole workgroups takes
+      // somewhat shorter blocks instead
+      const int ty0 = (g.ny + rows - 1) / rows;
+      const int tyfill = std::max(ty0, std::min((wpb + r.strips_x - 1) / r.strips_x,
+                                                g.ny / kMinRows));
+      const int tymax = fit ? std::max(ty0, std::min(std::max(4 * ty0, tyfill), g.ny / kMinRows))
+                            : ty0;
+      int ty = fit ? ty0 : tyfill;
+      long long best = -1;
+      for (int t = ty0; fit && t <= tymax; ++t) {
+        const long long ns = static_cast<long long>(r.strips_x) * t;
+        const long long cost =
+            (ns + wpb - 1) / wpb * wpb * ((g.ny + t - 1) / t + kStripCostRows);
+        if (best < 0 || cost < best) {
+          best = cost;
+          ty = t;
+        }
+      }
+      r.rows = (g.ny + ty - 1) / ty;
+      r.tiles_y = (g.ny + r.rows - 1) / r.rows;
       r.nstrips = r.strips_x * r.tiles_y;
       r.nitems = (r.nstrips + wpb - 1) / wpb;
+      recs.push_back(r);
+    }
+    // the queue hands out the longest items (tallest blocks) first, so the
+    // step ends on short ones; equal heights keep the larger grid first
+    std::stable_sort(recs.begin(), recs.end(),
+                     [](const BatchGrid& x, const BatchGrid& y) { return x.rows > y.rows; });
+    int item = 0;
+    for (auto& r : recs) {
       r.item0 = item;
       item += r.nitems;
-      recs.push_back(r);
     }
     nitems = item;
   }
@@ -358,7 +396,7 @@ int fvm_batch_cfl(fvm_batch* b) {
     const BatchGrid& r = b->recs[q];
     CflArgs a{};
     a.w = b->cur + r.offset;
-    a.scr = b->gscr() + q;
+    a.scr = b->gscr() + r.user;
     a.g = r.g;
     a.m = b->m;
     const long long cells = static_cast<long long>(r.g.nx) * r.g.ny;
@@ -373,7 +411,8 @@ static int batch_graph(fvm_batch* b, int kind, int nsteps, double* log, int log_
                        hipGraphExec_t* exec) {
   for (auto it = b->graphs.begin(); it != b->graphs.end(); ++it) {
     if (it->kind == kind && it->nsteps == nsteps && it->start == b->cur && it->log == log &&
-        it->rows == b->rows && it->wpb == b->wpb && it->persist == b->persist) {
+        it->rows == b->rows && it->wpb == b->wpb && it->persist == b->persist &&
+        it->fit == b->fit) {
       b->graphs.splice(b->graphs.begin(), b->graphs, it);
       *exec = b->graphs.front().exec;
       return FVM_OK;
@@ -387,6 +426,7 @@ static int batch_graph(fvm_batch* b, int kind, int nsteps, double* log, int log_
   c.rows = b->rows;
   c.wpb = b->wpb;
   c.persist = b->persist;
+  c.fit = b->fit;
   if (hipGraphCreate(&c.graph, 0) != hipSuccess) return FVM_EDEVICE;
   hipGraphNode_t prev = nullptr;
   const double* in = b->cur;
@@ -420,7 +460,6 @@ static int batch_graph(fvm_batch* b, int kind, int nsteps, double* log, int log_
       a.dt_log_cap = log_cap;
       a.ngrids = b->n;
       a.nitems = b->nitems;
-      a.rows = b->rows;
       a.dt_scale = kind == 2 ? 0.0 : 1.0;
       a.m = b->m;
       ok = add(batch_kernel_ptr(b->model, b->bc, b->wpb, b->persist),
@@ -432,14 +471,14 @@ static int batch_graph(fvm_batch* b, int kind, int nsteps, double* log, int log_
         StepArgs a{};
         a.win = in + r.offset;
         a.wout = out + r.offset;
-        a.scr = b->gscr() + q;
+        a.scr = b->gscr() + r.user;
         a.dt_log = log ? log + r.user : nullptr;
         a.dt_log_cap = log_cap;
         a.dt_log_stride = b->n;
         a.mode = kDtAdaptive;
         a.g = r.g;
         // the single-grid kernel's workgroup tiles
-        a.t.rows = b->rows;
+        a.t.rows = r.rows;
         a.t.wpb = b->wpb;
         a.t.cpl = r.cpl;
         a.t.tiles_x = (r.strips_x + b->wpb - 1) / b->wpb;
@@ -530,15 +569,17 @@ int fvm_batch_autotune(fvm_batch* b, const char* cache_path) {
   if (cache_path) {
     std::ifstream in(cache_path);
     std::string line;
-    int r = 0, w = 0, ps = 1, found = 0;
+    int r = 0, w = 0, ps = 1, ft = 0, found = 0;
     while (std::getline(in, line)) {
       const size_t bar = line.find(" | ");
       if (bar == std::string::npos || line.substr(0, bar) != key) continue;
-      if (std::sscanf(line.c_str() + bar + 3, "rows=%d wpb=%d persist=%d", &r, &w, &ps) == 3)
+      if (std::sscanf(line.c_str() + bar + 3, "rows=%d wpb=%d persist=%d fit=%d", &r, &w, &ps,
+                      &ft) == 4)
         found = 1;
     }
     if (found) {
       b->persist = ps != 0;
+      b->fit = ft != 0;
       return fvm_batch_set_tiling(b, r, w);
     }
   }
@@ -554,12 +595,14 @@ int fvm_batch_autotune(fvm_batch* b, const char* cache_path) {
   }
   double best = 1e300;
   int br = b->rows, bw = b->wpb;
-  bool bp = b->persist;
+  bool bp = b->persist, bf = b->fit;
   int rc = FVM_OK;
-  for (int c = 0; c < 8 && !rc; ++c) {
-    const bool ps = c < 4;  // persistent, then grouped launches
-    const int w = 1 << (c % 4);
+  for (int c = 0; c < 16 && !rc; ++c) {
+    const bool ps = c < 8;  // persistent, then grouped launches
+    const bool ft = c % 2 == 1;
+    const int w = 1 << ((c / 2) % 4);
     b->persist = ps;
+    b->fit = ft;
     for (int r : {8, 16, 32, 48, 64, 96, 128}) {
       rc = fvm_batch_set_tiling(b, r, w);
       if (rc) break;
@@ -582,6 +625,7 @@ int fvm_batch_autotune(fvm_batch* b, const char* cache_path) {
         br = r;
         bw = w;
         bp = ps;
+        bf = ft;
       }
     }
   }
@@ -589,20 +633,21 @@ int fvm_batch_autotune(fvm_batch* b, const char* cache_path) {
   (void)hipEventDestroy(e1);
   if (rc) return rc;
   b->persist = bp;
+  b->fit = bf;
   rc = fvm_batch_set_tiling(b, br, bw);
   if (rc == FVM_OK && cache_path) {
     std::ofstream out(cache_path, std::ios::app);
     out << key << " | rows=" << br << " wpb=" << bw << " persist=" << (bp ? 1 : 0)
-        << " us=" << best << "\n";
+        << " fit=" << (bf ? 1 : 0) << " us=" << best << "\n";
   }
   return rc;
 }
 
-int fvm_batch_set_schedule(fvm_batch* b, int persistent) {
+int fvm_batch_set_schedule(fvm_batch* b, int persistent, int fit_blocks) {
   if (!b) return FVM_EINVAL;
   b->persist = persistent != 0;
-  b->clear_graphs();
-  return FVM_OK;
+  b->fit = fit_blocks != 0;
+  return fvm_batch_set_tiling(b, b->rows, b->wpb);
 }
 
 int fvm_batch_sync(fvm_batch* b) {

@@ -144,6 +144,7 @@ struct BatchGrid {            // per-grid record in device memory
   GridGeom g;
   int strips_x;               // wave strips across the grid
   int tiles_y;                // row blocks
+  int rows;                   // rows per block (the last block may be shorter)
   int nstrips;                // strips_x * tiles_y wave strips, numbered row-major
   int nitems;                 // work items: groups of WPB consecutive strips
   int item0;                  // first work item of the grid
@@ -168,9 +169,8 @@ struct BatchArgs {
   BatchScratch* bscr;
   double* dt_log;             // nullable, dt_log[step * ngrids + grid]
   int dt_log_cap;             // steps the log can hold
-  int ngrids;                 // records sorted by item0 (largest grids first)
+  int ngrids;                 // records sorted by item0 (tallest row blocks first)
   int nitems;                 // work items of all grids
-  int rows;
   double dt_scale;            // 1; 0 for the tuner's dry runs (state unchanged)
   ModelConsts m;
 };

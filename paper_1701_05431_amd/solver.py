@@ -34,6 +34,13 @@ def params_from(preset=None, **kw) -> _lib.Params:
     return p
 
 
+def aligned_pitch(nx: int, align: int = 16) -> int:
+    """The smallest row pitch (in doubles) >= nx that is a multiple of align:
+    with the default 16, every row of every variable starts on a 128-byte
+    line, so a wave's row of a strip touches no line it does not use."""
+    return (nx + align - 1) // align * align
+
+
 def _ptr(t: torch.Tensor | None):
     return None if t is None else C.c_void_p(t.data_ptr())
 
@@ -332,9 +339,11 @@ class Batch:
         check(lib().fvm_batch_set_tiling(self.h, int(rows), int(waves_per_block)),
               "fvm_batch_set_tiling")
 
-    def set_schedule(self, persistent: bool = True) -> None:
-        """Persistent workgroups over a work queue, or one workgroup per item."""
-        check(lib().fvm_batch_set_schedule(self.h, int(bool(persistent))), "fvm_batch_set_schedule")
+    def set_schedule(self, persistent: bool = True, fit_blocks: bool = False) -> None:
+        """Persistent workgroups over a work queue, or one workgroup per item;
+        fit_blocks: row blocks sized so that strips fill whole workgroups."""
+        check(lib().fvm_batch_set_schedule(self.h, int(bool(persistent)), int(bool(fit_blocks))),
+              "fvm_batch_set_schedule")
 
     def autotune(self, cache_path: str | None = None) -> None:
         """Picks the batched step's tile shape and schedule by timing dry runs."""

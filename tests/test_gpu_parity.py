@@ -19,7 +19,7 @@ import torch
 from oracle import fv as orc
 from paper_1701_05431_amd import inputs
 from paper_1701_05431_amd import _lib
-from paper_1701_05431_amd.solver import Batch, Solver, params_from, fvrun
+from paper_1701_05431_amd.solver import Batch, Solver, aligned_pitch, params_from, fvrun
 
 pytestmark = pytest.mark.gpu
 
@@ -546,9 +546,16 @@ def test_batch_equals_single_grid_runs():
     b3.set_states(states)
     dts3 = b3.run(9, record_dt=True).cpu().numpy()
     got3 = [x.cpu().numpy() for x in b3.states()]
-    assert np.array_equal(dts3, dts)
+    b4 = Batch(plist)  # row blocks fitted to whole workgroups
+    b4.set_schedule(True, fit_blocks=True)
+    b4.set_tiling(32, 8)
+    b4.set_states(states)
+    dts4 = b4.run(9, record_dt=True).cpu().numpy()
+    got4 = [x.cpu().numpy() for x in b4.states()]
+    assert np.array_equal(dts3, dts) and np.array_equal(dts4, dts)
     for k in range(len(sizes)):
         assert np.array_equal(got3[k], got[k]), k
+        assert np.array_equal(got4[k], got[k]), k
     for k, n in enumerate(sizes):
         s = Solver(plist[k])
         s.set_state(states[k])
@@ -745,13 +752,13 @@ def test_spray_2048_full_size_bench_config():
 
 
 def test_batch_256_full_workload_bench_config():
-    """The 256-grid workload as the benchmark runs it (even pitches, row
+    """The 256-grid workload as the benchmark runs it (128-byte pitches, row
     storage, tuned persistent tiling): 3 steps, the largest, a middle and the
     smallest grid against the oracle, every grid's dts against its own
     single-grid run's."""
     sizes = inputs.batch_sizes(inputs.BATCH_COUNT, 0)
-    plist = [params_from(inputs.BATCH_256, nx=n, ny=n, ld=n + n % 2, layout=_lib.FVM_LAYOUT_ROWS)
-             for n in sizes]
+    plist = [params_from(inputs.BATCH_256, nx=n, ny=n, ld=aligned_pitch(n),
+                         layout=_lib.FVM_LAYOUT_ROWS) for n in sizes]
     states = [inputs.riemann_state(n, n, k) for k, n in enumerate(sizes)]
     b = Batch(plist)
     b.set_states(states)
