@@ -93,6 +93,61 @@ def bench_euler(args):
                 tiling=s.tiling(), cpl=s.cells_per_lane(), solver=s)
 
 
+def bench_output(steps, warmup, layout="rows", tuning=TUNING):
+    """Asynchronous output on the Euler 4096^2 workload: `steps` steps with
+    and without a snapshot every steps/2 steps (written to the null device,
+    so the disk is left out), timed on the compute stream only; and the
+    gather kernel alone (one read and one write of the state)."""
+    import torch
+    from paper_1701_05431_amd import inputs
+    from paper_1701_05431_amd.solver import AsyncOutput, Solver, params_from
+    pre = inputs.EULER_4096
+    s = Solver(params_from(pre, layout=LAYOUTS[layout]))
+    s.set_state(torch.from_numpy(inputs.riemann_state(pre.nx, pre.ny, 0)))
+    s.autotune(tuning)
+    out = AsyncOutput(s)
+    s.run(warmup)
+    out.snapshot(os.devnull)
+    out.wait()
+    torch.cuda.synchronize()
+
+    def compute_stream_time(fn):
+        a = torch.cuda.Event(enable_timing=True)
+        b = torch.cuda.Event(enable_timing=True)
+        a.record()
+        fn()
+        b.record()
+        b.synchronize()
+        return a.elapsed_time(b) / 1e3
+
+    plain = compute_stream_time(lambda: s.run(steps))
+    half = max(1, steps // 2)
+
+    def with_output():
+        out.snapshot(os.devnull, step=0)
+        s.run(half)
+        out.snapshot(os.devnull, step=half)
+        s.run(steps - half)
+
+    overlapped = compute_stream_time(with_output)
+    out.wait()
+    torch.cuda.synchronize()
+    reps = 5
+    gather = []
+    for _ in range(reps):
+        gather.append(compute_stream_time(lambda: out.snapshot(os.devnull)))
+        out.wait()
+    out.close()
+    st = s.sync()
+    g = sorted(gather)[reps // 2]
+    state_bytes = 4 * 8 * pre.nx * pre.ny
+    return {"workload": pre.name, "steps": steps, "status": st, "snapshots": 2,
+            "ms_plain": plain * 1e3, "ms_with_output": overlapped * 1e3,
+            "overhead_frac": overlapped / plain - 1.0,
+            "gather_us": g * 1e6, "gather_gbs": 2 * state_bytes / g / 1e9,
+            "snapshot_bytes": state_bytes, "path": "null device"}
+
+
 def bench_spray(steps, warmup, autotune=True, layout="rows", tuning=TUNING):
     import torch
     from paper_1701_05431_amd import inputs
@@ -336,7 +391,7 @@ def main():
     ap.add_argument("--wpb", type=int, default=0)
     ap.add_argument("--only-euler", action="store_true")
     ap.add_argument("--only", choices=["spray", "batch", "adjoint", "adjoint4096", "slab",
-                                       "advection"],
+                                       "advection", "output"],
                     help="run just this secondary workload (for profiling) and print its record")
     ap.add_argument("--no-autotune", action="store_true")
     ap.add_argument("--tuning", default=TUNING,
@@ -364,7 +419,9 @@ def main():
                                             args.layout, args.tuning),
                "batch": lambda: bench_batch(args.steps, args.warmup, args.layout, args.tuning),
                "adjoint": lambda: bench_adjoint(1, args.layout, args.tuning),
-               "advection": lambda: bench_advection(args.steps)}[args.only]
+               "advection": lambda: bench_advection(args.steps),
+               "output": lambda: bench_output(args.steps, args.warmup, args.layout,
+                                              args.tuning)}[args.only]
         print(json.dumps(run()), flush=True)
         return
 

@@ -60,6 +60,7 @@ extern "C" {
 #define FVM_ECFL (-3)         /* fixed-dt step failed the CFL check          */
 #define FVM_ENONFINITE (-4)   /* NaN/inf speed, rho <= 0, p < 0, m_k < 0     */
 #define FVM_EUNSUPPORTED (-5) /* operation not available for this model      */
+#define FVM_EIO (-6)          /* a snapshot file could not be written        */
 
 /* ---- models and boundary conditions ------------------------------------ */
 #define FVM_ADV 0    /* u_t + a.grad u = 0, flux a+ u_L + a- u_R             */
@@ -329,6 +330,47 @@ int fvm_batch_set_schedule(fvm_batch* b, int persistent, int fit_blocks);
  * by the device, model and the list of grid shapes. Synchronises the
  * stream. */
 int fvm_batch_autotune(fvm_batch* b, const char* cache_path);
+
+/* ---- asynchronous solution output (Sec. 4.3) ----------------------------
+ * The solution is dumped without holding up the time steps: a gather kernel
+ * copies the current state, in stream order on the grid's stream, into one
+ * contiguous output buffer (one dense plane per variable, pitch nx: the
+ * global buffer whose NPartX x NPartY subdomain blocks are the per-part views
+ * of that pitch, filled by all parts at once); the device-to-host copy of that
+ * buffer runs on a second stream and the file is written by a host thread of
+ * the output stage, while the grid's stream goes on with the next steps.
+ *
+ * Snapshot file: a 64-byte little-endian header
+ *   char magic[8] = "FVMSNAP1"; int32 model, nvar, nx, ny;
+ *   int64 step; double time, lx, ly; int32 npart_x, npart_y;
+ * followed by nvar * ny * nx doubles, variable v of cell (i, j) at
+ * (v * ny + j) * nx + i. */
+typedef struct fvm_output fvm_output;
+
+/* Output stage for a bound grid. staging: device buffer of
+ * nVar * ny * nx doubles; host: pinned host buffer (hipHostMalloc or a pinned
+ * tensor) of the same size; copy_stream: the hipStream_t (as void*) the
+ * device-to-host copies run on, not the grid's stream. The caller owns the
+ * three and keeps them alive until fvm_output_destroy returns; the grid must
+ * outlive the stage and keep its shape. Starts the writer thread. */
+int fvm_output_create(fvm_grid* g, double* staging, double* host, void* copy_stream,
+                      fvm_output** out);
+
+/* Enqueues one snapshot of the grid's current state, to be written to `path`
+ * (copied) with the given step number and time in the header. Returns once
+ * the gather and the copy are enqueued; it waits on the host only while the
+ * previous snapshot's file is still being written from the host buffer.
+ * Returns the first error of an earlier snapshot (FVM_EIO, FVM_EDEVICE) if
+ * there was one. */
+int fvm_output_snapshot(fvm_output* o, const char* path, long long step, double time);
+
+/* Waits until every snapshot enqueued so far is on disk; returns FVM_OK or
+ * the first error. */
+int fvm_output_wait(fvm_output* o);
+
+/* Waits for the pending snapshots, stops the writer thread and frees the
+ * stage; returns what fvm_output_wait would. */
+int fvm_output_destroy(fvm_output* o);
 
 #ifdef __cplusplus
 }

@@ -12,6 +12,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libfvm.so")
 
 FVM_OK, FVM_EINVAL, FVM_EDEVICE, FVM_ECFL, FVM_ENONFINITE, FVM_EUNSUPPORTED = 0, -1, -2, -3, -4, -5
+FVM_EIO = -6
 FVM_ADV, FVM_EULER, FVM_SPRAY = 0, 1, 2
 FVM_PERIODIC, FVM_TRANSMISSIVE, FVM_DIRICHLET = 0, 1, 2
 FVM_LAYOUT_PLANES, FVM_LAYOUT_ROWS = 0, 1
@@ -83,6 +84,10 @@ SIGNATURES = {
     "fvm_batch_sync": (C.c_int, [_V]),
     "fvm_batch_set_tiling": (C.c_int, [_V, C.c_int, C.c_int]),
     "fvm_batch_autotune": (C.c_int, [_V, C.c_char_p]),
+    "fvm_output_create": (C.c_int, [_V, _V, _V, _V, C.POINTER(_V)]),
+    "fvm_output_snapshot": (C.c_int, [_V, C.c_char_p, C.c_longlong, C.c_double]),
+    "fvm_output_wait": (C.c_int, [_V]),
+    "fvm_output_destroy": (C.c_int, [_V]),
 }
 
 _lib = None

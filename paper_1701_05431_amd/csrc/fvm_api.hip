@@ -16,6 +16,7 @@
 #include <vector>
 
 #include "../../include/fvm.h"
+#include "fvm_host.hpp"
 #include "fvm_internal.hpp"
 
 namespace fvm {
@@ -242,6 +243,7 @@ const char* fvm_strerror(int status) {
     case FVM_ECFL: return "fixed time step violates the CFL condition";
     case FVM_ENONFINITE: return "non-finite or non-physical state";
     case FVM_EUNSUPPORTED: return "operation not supported for this model";
+    case FVM_EIO: return "file output failed";
     default: return "unknown status";
   }
 }
@@ -347,6 +349,22 @@ int fvm_current(const fvm_grid* g, double** w) {
   *w = g->cur;
   return FVM_OK;
 }
+
+}  // extern "C"
+
+namespace fvm {
+int grid_view(const fvm_grid* g, GridView* v) {
+  if (!g || !v || !g->bound) return FVM_EINVAL;
+  v->p = g->p;
+  v->g = g->g;
+  v->nv = g->nv;
+  v->cur = g->cur;
+  v->stream = g->stream;
+  return FVM_OK;
+}
+}  // namespace fvm
+
+extern "C" {
 
 int fvm_set_state(fvm_grid* g, const double* src, int src_on_device) {
   if (!g || !src || !g->bound) return FVM_EINVAL;

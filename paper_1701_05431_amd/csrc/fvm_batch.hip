@@ -3,12 +3,13 @@
 // One persistent launch per time step walks a work list of (grid, group of
 // strips) items, longest items (tallest row blocks) first, handed out by an
 // atomic queue, so that short items fill the gaps the long ones leave, the
-// step ends on short ones and no launch is smaller than the chip. A grid's wave strips (the single-grid kernel's strips, over
-// row blocks of near-equal height, at most the tuned `rows`) are numbered
-// row-major and an item is WPB consecutive strips of one grid, one per wave: a
-// grid narrower than a workgroup stacks its waves over several row blocks
-// instead of leaving them idle, and a small grid takes shorter blocks so that
-// it still has a strip for every wave. The device code per
+// step ends on short ones and no launch is smaller than the chip. A grid's
+// wave strips (the single-grid kernel's strips, over row blocks of
+// near-equal height, at most the tuned `rows`) are numbered row-major and an
+// item is WPB consecutive strips of one grid, one per wave: a grid narrower
+// than a workgroup stacks its waves over several row blocks instead of
+// leaving them idle, and a small grid takes shorter blocks so that it still
+// has a strip for every wave. The device code per
 // strip is the single-grid kernel's, so a grid's result is bit-for-bit the
 // one of a single-grid launch. Each grid keeps its own adaptive dt: the item's
 // workgroup folds its speeds into the grid's maxima and the last item of a
@@ -148,7 +149,8 @@ static void* batch_fn_bc(int bc, int wpb) {
 }
 
 static void* batch_kernel_ptr(int model, int bc, int wpb, bool persist = true) {
-  if (model == 0) return persist ? batch_fn_bc<Adv, true>(bc, wpb) : batch_fn_bc<Adv, false>(bc, wpb);
+  if (model == 0)
+    return persist ? batch_fn_bc<Adv, true>(bc, wpb) : batch_fn_bc<Adv, false>(bc, wpb);
   if (model == 1)
     return persist ? batch_fn_bc<Euler, true>(bc, wpb) : batch_fn_bc<Euler, false>(bc, wpb);
   return nullptr;
@@ -613,7 +615,8 @@ int fvm_batch_autotune(fvm_batch* b, const char* cache_path) {
       bool ok = hipGraphLaunch(exec, b->stream) == hipSuccess;
       ok = ok && hipEventRecord(e0, b->stream) == hipSuccess;
       for (int k = 0; k < 2 && ok; ++k) ok = hipGraphLaunch(exec, b->stream) == hipSuccess;
-      ok = ok && hipEventRecord(e1, b->stream) == hipSuccess && hipEventSynchronize(e1) == hipSuccess;
+      ok = ok && hipEventRecord(e1, b->stream) == hipSuccess &&
+           hipEventSynchronize(e1) == hipSuccess;
       float ms = 0.0f;
       if (!ok || hipEventElapsedTime(&ms, e0, e1) != hipSuccess) {
         rc = FVM_EDEVICE;

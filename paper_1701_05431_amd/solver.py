@@ -8,6 +8,8 @@ from __future__ import annotations
 
 import ctypes as C
 import math
+import os
+import struct
 
 import numpy as np
 import torch
@@ -172,7 +174,8 @@ class Solver:
 
     def run(self, nsteps: int, record_dt: bool = False):
         self._bind_stream()
-        dts = torch.zeros(max(nsteps, 1), dtype=torch.float64, device=self.device) if record_dt else None
+        dts = (torch.zeros(max(nsteps, 1), dtype=torch.float64, device=self.device)
+               if record_dt else None)
         check(lib().fvm_run(self.h, int(nsteps), _ptr(dts)), "fvm_run")
         return dts[:nsteps] if record_dt else None
 
@@ -325,8 +328,8 @@ class Batch:
 
     def states(self):
         cur = self.current()
-        return [self.view(cur, k)[:, :, :self.plist[k].nx].clone(memory_format=torch.contiguous_format)
-                for k in range(self.n)]
+        return [self.view(cur, k)[:, :, :self.plist[k].nx].clone(
+            memory_format=torch.contiguous_format) for k in range(self.n)]
 
     def run(self, nsteps: int, record_dt: bool = False, per_grid: bool = False):
         dts = (torch.zeros(max(nsteps, 1) * self.n, dtype=torch.float64, device=self.device)
@@ -352,6 +355,68 @@ class Batch:
 
     def sync(self) -> int:
         return int(lib().fvm_batch_sync(self.h))
+
+
+SNAPSHOT_HEADER = 64
+
+
+class AsyncOutput:
+    """Non-blocking solution dumps of one grid (Sec. 4.3): `snapshot` enqueues
+    the gather of the current state into a device staging buffer on the
+    solver's stream, its copy to pinned host memory on a side stream and the
+    file write on the library's writer thread, and returns; the time steps
+    enqueued after it overlap the copy and the write."""
+
+    def __init__(self, solver: Solver):
+        self.solver = solver
+        p = solver.p
+        n = solver.nv * p.ny * p.nx
+        self.staging = torch.empty(n, dtype=torch.float64, device=solver.device)
+        self.host = torch.empty(n, dtype=torch.float64, pin_memory=True)
+        self.copy_stream = torch.cuda.Stream(device=solver.device)
+        solver._bind_stream()
+        h = C.c_void_p()
+        check(lib().fvm_output_create(solver.h, _ptr(self.staging), _ptr(self.host),
+                                      C.c_void_p(self.copy_stream.cuda_stream), C.byref(h)),
+              "fvm_output_create")
+        self.h = h
+
+    def snapshot(self, path: str, step: int = 0, time: float = 0.0) -> None:
+        self.solver._bind_stream()
+        check(lib().fvm_output_snapshot(self.h, os.fsencode(path), int(step), float(time)),
+              "fvm_output_snapshot")
+
+    def wait(self) -> None:
+        check(lib().fvm_output_wait(self.h), "fvm_output_wait")
+
+    def close(self) -> None:
+        h, self.h = getattr(self, "h", None), None
+        if h is not None and h.value:
+            check(lib().fvm_output_destroy(h), "fvm_output_destroy")
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def read_snapshot(path: str):
+    """(header dict, array (nvar, ny, nx)) of a snapshot file."""
+    with open(path, "rb") as f:
+        head = f.read(SNAPSHOT_HEADER)
+        if len(head) != SNAPSHOT_HEADER or head[:8] != b"FVMSNAP1":
+            raise ValueError(f"{path}: not a snapshot file")
+        model, nvar, nx, ny = struct.unpack_from("<4i", head, 8)
+        (step,) = struct.unpack_from("<q", head, 24)
+        time, lx, ly = struct.unpack_from("<3d", head, 32)
+        npx, npy = struct.unpack_from("<2i", head, 56)
+        data = np.fromfile(f, dtype="<f8", count=nvar * ny * nx)
+    if data.size != nvar * ny * nx:
+        raise ValueError(f"{path}: truncated")
+    meta = dict(model=model, nvar=nvar, nx=nx, ny=ny, step=step, time=time, lx=lx, ly=ly,
+                npart_x=npx, npart_y=npy)
+    return meta, data.reshape(nvar, ny, nx)
 
 
 class FVRun(torch.autograd.Function):
