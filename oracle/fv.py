@@ -34,6 +34,7 @@ class Params(C.Structure):
         ("K", C.c_double), ("theta", C.c_double), ("s_eps", C.c_double),
         ("cfl", C.c_double), ("dt_max", C.c_double),
         ("ghost", (C.c_double * 6) * 4),  # Dirichlet: west, east, south, north
+        ("closure", C.c_int),  # spray: 0 lognormal fit, 1 entropy maximiser
     ]
 
 
@@ -41,10 +42,13 @@ def params(model: int, nx: int, ny: int, *, bc: int = PERIODIC, npx: int = 1,
            npy: int = 1, lx: float = 1.0, ly: float = 1.0, gamma: float = 1.4,
            ax: float = 0.0, ay: float = 0.0, K: float = 1.0, theta: float = 0.1,
            s_eps: float = 0.01, cfl: float = 0.45, dt_max: float = 0.0,
-           ghost=None) -> Params:
-    """ghost: Dirichlet states, 4 x nVar (west, east, south, north)."""
+           ghost=None, closure: int = 0) -> Params:
+    """ghost: Dirichlet states, 4 x nVar (west, east, south, north);
+    closure: the spray's n(S=0), m_{-1/2} from a lognormal fit (0) or the
+    entropy maximiser (1)."""
     P = Params(model, bc, nx, ny, npx, npy, lx, ly, gamma, ax, ay, K, theta,
                s_eps, cfl, dt_max)
+    P.closure = closure
     if ghost is not None:
         g = np.asarray(ghost, dtype=np.float64)
         for side in range(4):
@@ -81,7 +85,8 @@ def lib():
             "orc_phys_flux": (None, [P, _D, C.c_int, _D, _D]),
             "orc_num_flux": (None, [P, _D, _D, C.c_int, _D]),
             "orc_cell_speeds": (C.c_int, [P, _D, _D, _D]),
-            "orc_spray_closure": (None, [P, _D, _D, _D]),
+            "orc_spray_closure": (C.c_int, [P, _D, _D, _D]),
+            "orc_maxent": (C.c_int, [_D, _D, _D, _D]),
             "orc_spray_source": (None, [P, _D, _D, _D]),
             "orc_set_threads": (None, [C.c_int]),
             "orc_get_threads": (C.c_int, []),
@@ -155,8 +160,22 @@ def cell_speeds(P: Params, w):
 def spray_closure(P: Params, w):
     w = _f64(w)
     mmh, n0 = C.c_double(), C.c_double()
-    lib().orc_spray_closure(C.byref(P), _ptr(w), C.byref(mmh), C.byref(n0))
+    rc = lib().orc_spray_closure(C.byref(P), _ptr(w), C.byref(mmh), C.byref(n0))
+    if rc:
+        raise OracleError(-4, "spray_closure")
     return mmh.value, n0.value
+
+
+def maxent(m):
+    """The entropy maximiser n(S) = exp(sum_k lam_k S^{k/2}) on [0, 1] with
+    fractional moments m = (m_0, m_{1/2}, m_{2/2}, m_{3/2}): returns
+    (lam, m_{-1/2}, n(S=0)); raises if the moments cannot be matched."""
+    m = _f64(m)
+    lam = np.zeros(4)
+    mmh, n0 = C.c_double(), C.c_double()
+    if lib().orc_maxent(_ptr(m), _ptr(lam), C.byref(mmh), C.byref(n0)):
+        raise OracleError(-4, "maxent")
+    return lam, mmh.value, n0.value
 
 
 def spray_source(P: Params, w, ug) -> np.ndarray:

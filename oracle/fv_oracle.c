@@ -43,8 +43,14 @@
  *   R5 the spray transport uses the kinetic (pressureless) upwind flux
  *      F = W_L (u_L.n)+ + W_R (u_R.n)-, with u = q/m_{2/2}.
  *   R6 the spray closure (the paper reconstructs n(S) by entropy maximisation
- *      in a reference it cites) is replaced by a lognormal fit to
- *      (m_0, m_{1/2}, m_{2/2}); n(S=0) is read as the fitted density at S_eps.
+ *      in a reference it cites, without giving the algorithm). Two closures:
+ *      closure 0, a lognormal fit to (m_0, m_{1/2}, m_{2/2}) with n(S=0)
+ *      read as the fitted density at S_eps; closure 1, the entropy maximiser
+ *      itself, n(S) = exp(sum_k lambda_k S^{k/2}) on S in [0,1] matching the
+ *      four moments, found by Newton's method on the convex dual with a
+ *      backtracking line search and composite Gauss-Legendre quadrature in
+ *      x = S^{1/2} (parity of this closure is pinned against an independent
+ *      adaptive quadrature, not against the paper, which prints no values).
  *   R7 transmissive boundaries: a ghost cell equal to the boundary cell.
  *      Dirichlet boundaries (mentioned in Sec. 4.2 for the overlap of a
  *      subdomain at the domain's edge): the ghost cell holds a prescribed
@@ -81,6 +87,7 @@ typedef struct {
   double K, theta, s_eps;
   double cfl, dt_max;
   double ghost[4][ORC_MAXV];  /* Dirichlet ghost states: west, east, south, north */
+  int closure;                /* spray: 0 lognormal fit, 1 entropy maximiser (R6) */
 } orc_params;
 
 int orc_nvar(int model)
@@ -210,7 +217,7 @@ static int cell_speeds(const orc_params* P, const double* w, double* sx,
  *   L1 = ln(m_{1/2}/m_0) = mu/2 + s^2/8,  L2 = ln(m_{2/2}/m_0) = mu + s^2/2,
  *   s^2 = 4 (L2 - 2 L1),  mu = 2 L1 - s^2/4.
  * Returns m_{-1/2} and the density at S_eps. */
-static void spray_closure(const orc_params* P, const double* w, double* mmh,
+static void lognormal_closure(const orc_params* P, const double* w, double* mmh,
                           double* n0)
 {
   double m0 = w[0], m1 = w[1], m2 = w[2];
@@ -224,6 +231,196 @@ static void spray_closure(const orc_params* P, const double* w, double* mmh,
   *n0 = m0 / (P->s_eps * sqrt(2.0 * M_PI * s2)) * exp(-(z * z) / (2.0 * s2));
 }
 
+/* Gauss-Legendre rule of n points on [-1, 1]: the nodes are the roots of the
+ * Legendre polynomial P_n, found by Newton's method from Tricomi's initial
+ * guesses, with P_n and P_n' from the three-term recurrence
+ * k P_k = (2k-1) z P_{k-1} - (k-1) P_{k-2}; the weights are
+ * 2 / ((1 - z^2) P_n'(z)^2). */
+static void gauss_legendre(int n, double* x, double* w)
+{
+  for (int i = 0; i < n; ++i) {
+    double z = cos(M_PI * (i + 0.75) / (n + 0.5));
+    double dp = 1.0;
+    for (int it = 0; it < 100; ++it) {
+      double pk = 1.0, pkm1 = 0.0;
+      for (int k = 1; k <= n; ++k) {
+        double pkm2 = pkm1;
+        pkm1 = pk;
+        pk = ((2.0 * k - 1.0) * z * pkm1 - (k - 1.0) * pkm2) / k;
+      }
+      dp = n * (z * pk - pkm1) / (z * z - 1.0);
+      double dz = pk / dp;
+      z -= dz;
+      if (fabs(dz) <= 1e-17) break;
+    }
+    x[i] = z;
+    w[i] = 2.0 / ((1.0 - z * z) * dp * dp);
+  }
+}
+
+/* Composite rule on x in [0, 1]: ME_PANELS panels of ME_NODES points. */
+#define ME_PANELS 64
+#define ME_NODES 16
+#define ME_Q (ME_PANELS * ME_NODES)
+static double me_x[ME_Q], me_w[ME_Q];
+static int me_ready = 0;
+
+static void maxent_rule(void)
+{
+  if (me_ready) return;
+#pragma omp critical(orc_maxent_rule)
+  {
+    if (!me_ready) {
+      double t[ME_NODES], v[ME_NODES];
+      gauss_legendre(ME_NODES, t, v);
+      for (int p = 0; p < ME_PANELS; ++p)
+        for (int q = 0; q < ME_NODES; ++q) {
+          double a = (double)p / ME_PANELS, h = 1.0 / ME_PANELS;
+          me_x[p * ME_NODES + q] = a + 0.5 * h * (t[q] + 1.0);
+          me_w[p * ME_NODES + q] = 0.5 * h * v[q];
+        }
+      me_ready = 1;
+    }
+  }
+}
+
+/* With S = x^2 (dS = 2x dx) and n(S) = exp(lambda_0 + lambda_1 x +
+ * lambda_2 x^2 + lambda_3 x^3):
+ *   mu[j+1] = int_0^1 S^{j/2} n(S) dS = 2 int_0^1 x^{j+1} n dx,  j = -1..6,
+ * so mu[1..4] are the model's m_{0/2..3/2} and mu[0] = m_{-1/2}. */
+static void maxent_moments(const double* lam, double* mu)
+{
+  for (int j = 0; j < 8; ++j) mu[j] = 0.0;
+  for (int q = 0; q < ME_Q; ++q) {
+    double x = me_x[q];
+    double e = 2.0 * me_w[q] * exp(lam[0] + x * (lam[1] + x * (lam[2] + x * lam[3])));
+    double xp = 1.0;
+    for (int j = 0; j < 8; ++j) {
+      mu[j] += e * xp;
+      xp *= x;
+    }
+  }
+}
+
+/* Solves the 4x4 symmetric positive definite system H d = b (Cholesky);
+ * returns 1 if H is not positive definite. */
+static int spd_solve4(const double H[4][4], const double* b, double* d)
+{
+  double L[4][4] = {{0}};
+  for (int i = 0; i < 4; ++i)
+    for (int j = 0; j <= i; ++j) {
+      double s = H[i][j];
+      for (int k = 0; k < j; ++k) s -= L[i][k] * L[j][k];
+      if (i == j) {
+        if (!(s > 0.0)) return 1;
+        L[i][i] = sqrt(s);
+      } else {
+        L[i][j] = s / L[j][j];
+      }
+    }
+  double y[4];
+  for (int i = 0; i < 4; ++i) {
+    double s = b[i];
+    for (int k = 0; k < i; ++k) s -= L[i][k] * y[k];
+    y[i] = s / L[i][i];
+  }
+  for (int i = 3; i >= 0; --i) {
+    double s = y[i];
+    for (int k = i + 1; k < 4; ++k) s -= L[k][i] * d[k];
+    d[i] = s / L[i][i];
+  }
+  return 0;
+}
+
+/* The entropy maximiser of reading R6 (closure 1): the lambda minimising the
+ * convex dual Phi(lambda) = int_0^1 n dS - sum_k lambda_k m_{k/2}, whose
+ * gradient is the moment mismatch g_k = mu_k(lambda) - m_{k/2} and whose
+ * Hessian is the moment matrix H_kl = mu_{k+l}. Newton steps from the normal
+ * density in x that matches the mean and variance of x under n dS; while
+ * the relative mismatch max_k |g_k|/m_{k/2} exceeds 1e-3 each step is cut
+ * back until Phi decreases enough (Armijo), closer in the full step is
+ * taken. Converged when the relative mismatch is <= 1e-14, or <= 1e-12 once
+ * a step no longer halves it (the rounding floor of the quadrature sums).
+ * Returns 0 and (lambda, m_{-1/2}, n(S=0) = exp(lambda_0)), or 1 if the
+ * moments are not realisable or Newton does not converge. */
+int orc_maxent(const double* m, double* lam_out, double* mmh, double* n0)
+{
+  maxent_rule();
+  if (!(m[0] > ORC_TINY)) return 1;
+  double a = m[1] / m[0], var = m[2] / m[0] - a * a;
+  if (!(var > 0.0)) return 1;
+  double lam[4] = {0.0, a / var, -0.5 / var, 0.0}, mu[8];
+  maxent_moments(lam, mu);
+  if (!(mu[1] > 0.0)) return 1;
+  lam[0] = log(m[0] / mu[1]);
+  maxent_moments(lam, mu);
+  int ok = 0;
+  double prev = INFINITY;
+  for (int it = 0; it < 200; ++it) {
+    double g[4], rel = 0.0;
+    for (int k = 0; k < 4; ++k) {
+      g[k] = mu[k + 1] - m[k];
+      double r = fabs(g[k]) / m[k];
+      if (!(r <= rel)) rel = r; /* NaN-sticky */
+    }
+    if (!(rel == rel)) return 1;
+    if (rel <= 1e-14 || (rel <= 1e-12 && rel > 0.5 * prev)) {
+      ok = 1;
+      break;
+    }
+    prev = rel;
+    double H[4][4], d[4], b[4];
+    for (int k = 0; k < 4; ++k) {
+      b[k] = -g[k];
+      for (int l = 0; l < 4; ++l) H[k][l] = mu[k + l + 1];
+    }
+    if (spd_solve4(H, b, d)) return 1;
+    double t = 1.0, trial[4], mt[8];
+    if (rel > 1e-3) {
+      double phi = mu[1], slope = 0.0;
+      for (int k = 0; k < 4; ++k) {
+        phi -= lam[k] * m[k];
+        slope += g[k] * d[k];
+      }
+      int accepted = 0;
+      for (int ls = 0; ls < 60 && !accepted; ++ls) {
+        for (int k = 0; k < 4; ++k) trial[k] = lam[k] + t * d[k];
+        maxent_moments(trial, mt);
+        double pt = mt[1];
+        for (int k = 0; k < 4; ++k) pt -= trial[k] * m[k];
+        if (pt <= phi + 1e-4 * t * slope)
+          accepted = 1;
+        else
+          t *= 0.5;
+      }
+      if (!accepted) return 1;
+    } else {
+      for (int k = 0; k < 4; ++k) trial[k] = lam[k] + d[k];
+      maxent_moments(trial, mt);
+    }
+    for (int k = 0; k < 4; ++k) lam[k] = trial[k];
+    for (int j = 0; j < 8; ++j) mu[j] = mt[j];
+  }
+  if (!ok) return 1;
+  for (int k = 0; k < 4; ++k) lam_out[k] = lam[k];
+  *mmh = mu[0];
+  *n0 = exp(lam[0]);
+  return 0;
+}
+
+/* m_{-1/2} and n(S=0) from the closure the parameters select; returns 1 if
+ * the entropy maximiser fails. */
+static int spray_closure(const orc_params* P, const double* w, double* mmh,
+                         double* n0)
+{
+  if (P->closure == 1) {
+    double lam[4];
+    return orc_maxent(w, lam, mmh, n0);
+  }
+  lognormal_closure(P, w, mmh, n0);
+  return 0;
+}
+
 /* Source S(W) of Sec. 6.1 eq. (Essadki): evaporation on the four moments and
  * on the momentum, drag m_0 (u_g - u)/theta on the momentum. */
 static void spray_source(const orc_params* P, const double* w,
@@ -234,7 +431,12 @@ static void spray_source(const orc_params* P, const double* w,
   if (!(m0 > ORC_TINY) || !(m1 > ORC_TINY) || !(m2 > ORC_TINY)) return;
   double ux = w[4] / m2, uy = w[5] / m2;
   double mmh, n0;
-  spray_closure(P, w, &mmh, &n0);
+  if (spray_closure(P, w, &mmh, &n0)) {
+    /* moments the entropy maximiser cannot match: the cell becomes
+     * non-finite, which the next speed check reports */
+    for (int k = 0; k < 6; ++k) S[k] = NAN;
+    return;
+  }
   double K = P->K;
   S[0] = -K * n0;
   S[1] = -(K / 2.0) * mmh;
@@ -267,10 +469,10 @@ int orc_cell_speeds(const orc_params* P, const double* w, double* sx,
   return cell_speeds(P, w, sx, sy);
 }
 
-void orc_spray_closure(const orc_params* P, const double* w, double* mmh,
-                       double* n0)
+int orc_spray_closure(const orc_params* P, const double* w, double* mmh,
+                      double* n0)
 {
-  spray_closure(P, w, mmh, n0);
+  return spray_closure(P, w, mmh, n0);
 }
 
 void orc_spray_source(const orc_params* P, const double* w, const double* ug,

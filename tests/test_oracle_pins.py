@@ -528,6 +528,90 @@ def test_spray_drag_only(orc):
 
 
 # --------------------------------------------------------------------------
+# the entropy-maximising closure (reading of Sec. 6.2)
+# --------------------------------------------------------------------------
+
+def _exp_cubic_moments(lam):
+    """Fractional moments m_{k/2}, k = -1..3, of n(S) = exp(sum lam_k S^{k/2})
+    on [0, 1] by adaptive Gauss-Kronrod quadrature in S (independent of the
+    oracle's composite Gauss-Legendre rule in x = S^{1/2})."""
+    from scipy import integrate
+    n = lambda S: math.exp(lam[0] + lam[1] * S ** 0.5 + lam[2] * S + lam[3] * S ** 1.5)
+    return [integrate.quad(lambda S: S ** (k / 2) * n(S), 0.0, 1.0, epsabs=0, epsrel=1e-13,
+                           limit=400)[0] for k in range(-1, 4)]
+
+
+def test_maxent_uniform_density_closed_form(orc):
+    """n(S) = c on [0, 1]: m_{k/2} = c / (1 + k/2), so lambda = (ln c, 0, 0, 0),
+    n(S=0) = c and m_{-1/2} = 2c."""
+    c = 0.7
+    lam, mmh, n0 = orc.maxent([c / (1 + k / 2) for k in range(4)])
+    assert abs(lam[0] - math.log(c)) < 1e-11 and np.max(np.abs(lam[1:])) < 1e-10
+    assert abs(mmh - 2 * c) < 1e-12 * 2 * c
+    assert abs(n0 - c) < 1e-11 * c
+
+
+@pytest.mark.parametrize("lam", [(0.3, 2.0, -9.0, 4.0), (-2.0, 40.0, -60.0, 10.0),
+                                 (1.0, -3.0, 2.0, -1.0), (-30.0, 160.0, -200.0, 20.0)])
+def test_maxent_recovers_exp_cubic_densities(orc, lam):
+    """The entropy maximiser with the moments of an exp-cubic density in
+    S^{1/2} is that density (the maximiser is unique): its parameters, its
+    value at S = 0 and its m_{-1/2} come back."""
+    mm = _exp_cubic_moments(lam)
+    got, mmh, n0 = orc.maxent(mm[1:])
+    assert np.max(np.abs(got - np.array(lam)) / np.maximum(1.0, np.abs(lam))) < 1e-8
+    assert abs(mmh - mm[0]) < 1e-12 * mm[0]
+    assert abs(n0 - math.exp(lam[0])) < 1e-9 * math.exp(lam[0])
+
+
+def test_maxent_rejects_unrealisable_moments(orc):
+    """A point mass (zero variance of S^{1/2}) and a negative m_0 have no
+    density of the exponential family."""
+    x = 0.4
+    with pytest.raises(orc.OracleError):
+        orc.maxent([1.0, x, x * x, x ** 3])
+    with pytest.raises(orc.OracleError):
+        orc.maxent([-1.0, 0.5, 0.3, 0.2])
+
+
+def test_maxent_closure_feeds_the_source(orc):
+    """With closure 1 the evaporation source takes n(S=0) and m_{-1/2} from
+    the entropy maximiser; the other components do not depend on the
+    closure (Sec. 6.1 eq. Essadki)."""
+    lam = (-2.0, 40.0, -60.0, 10.0)
+    mm = _exp_cubic_moments(lam)
+    w = np.array(mm[1:] + [mm[3] * 0.3, -mm[3] * 0.1])
+    ug = np.array([0.5, 0.2])
+    K, theta = 1.3, 0.2
+    P1 = orc.params(orc.SPRAY, 4, 4, K=K, theta=theta, closure=1)
+    P0 = orc.params(orc.SPRAY, 4, 4, K=K, theta=theta, closure=0)
+    S1, S0 = orc.spray_source(P1, w, ug), orc.spray_source(P0, w, ug)
+    assert abs(S1[0] + K * math.exp(lam[0])) < 1e-9 * K * math.exp(lam[0])
+    assert abs(S1[1] + 0.5 * K * mm[0]) < 1e-12 * 0.5 * K * mm[0]
+    assert np.array_equal(S1[2:], S0[2:])
+    assert orc.spray_closure(P1, w)[0] == orc.maxent(w[:4])[1]
+
+
+def test_maxent_spray_partitions_bitwise(orc):
+    """The entropy-maximising closure keeps the result independent of the
+    subdomain count, bit for bit, on the spray workload's kind of state."""
+    # K = 0.2: at this coarse grid's dt (about 0.05) the explicit evaporation
+    # step with K = 1 takes a quarter of m_{2/2} in one step and leaves the
+    # moment space; finer grids (smaller dt) keep K = 1
+    n = 16
+    W, ug = inputs.spray_state(n, n, 3)
+    ref = None
+    for npx, npy in ((1, 1), (2, 4), (4, 4)):
+        P = orc.params(orc.SPRAY, n, n, npx=npx, npy=npy, cfl=0.9, K=0.2, closure=1)
+        W1, dts = orc.run(P, W, 2, ug=ug)
+        assert np.all(np.isfinite(W1))
+        if ref is None:
+            ref = (W1, dts)
+        else:
+            assert np.array_equal(W1, ref[0]) and np.array_equal(dts, ref[1])
+
+
+# --------------------------------------------------------------------------
 # fixed-dt check and error paths
 # --------------------------------------------------------------------------
 
