@@ -71,6 +71,9 @@ extern "C" {
 #define FVM_TRANSMISSIVE 1 /* ghost cell = boundary cell (zero gradient)      */
 #define FVM_DIRICHLET 2    /* ghost cell = a prescribed state per side         */
 
+#define FVM_CLOSURE_LOGNORMAL 0 /* spray n(S=0), m_{-1/2}: lognormal fit       */
+#define FVM_CLOSURE_MAXENT 1    /* the entropy maximiser (Sec. 6.2)             */
+
 #define FVM_LAYOUT_PLANES 0 /* w[(v * ny + j) * ld + i]                       */
 #define FVM_LAYOUT_ROWS 1   /* w[(j * nVar + v) * ld + i]; nVar * ld <= 2^31-1 */
 
@@ -90,6 +93,10 @@ typedef struct fvm_params {
   double s_eps;  /* spray: size at which n(S=0) is evaluated (0 < s_eps < 1) */
   double cfl;    /* Courant number C of the adaptive step (> 0)              */
   double dt_max; /* time step when every speed is zero (0 = error)           */
+  int closure;   /* spray: FVM_CLOSURE_LOGNORMAL (fused into the step) or
+                    FVM_CLOSURE_MAXENT (a transport step, then a source pass
+                    that reconstructs n(S) per cell; periodic or transmissive
+                    boundaries, no halo rows); 0 for the other models       */
 } fvm_params;
 
 typedef struct fvm_grid fvm_grid;

@@ -430,8 +430,9 @@ static void spray_source(const orc_params* P, const double* w,
   for (int k = 0; k < 6; ++k) S[k] = 0.0;
   if (!(m0 > ORC_TINY) || !(m1 > ORC_TINY) || !(m2 > ORC_TINY)) return;
   double ux = w[4] / m2, uy = w[5] / m2;
-  double mmh, n0;
-  if (spray_closure(P, w, &mmh, &n0)) {
+  /* with K = 0 the evaporation terms vanish and the closure is not needed */
+  double mmh = 0.0, n0 = 0.0;
+  if (P->K != 0.0 && spray_closure(P, w, &mmh, &n0)) {
     /* moments the entropy maximiser cannot match: the cell becomes
      * non-finite, which the next speed check reports */
     for (int k = 0; k < 6; ++k) S[k] = NAN;

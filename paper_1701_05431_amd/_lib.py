@@ -13,6 +13,7 @@ LIB_PATH = os.path.join(HERE, "libfvm.so")
 
 FVM_OK, FVM_EINVAL, FVM_EDEVICE, FVM_ECFL, FVM_ENONFINITE, FVM_EUNSUPPORTED = 0, -1, -2, -3, -4, -5
 FVM_EIO = -6
+FVM_CLOSURE_LOGNORMAL, FVM_CLOSURE_MAXENT = 0, 1
 FVM_ADV, FVM_EULER, FVM_SPRAY = 0, 1, 2
 FVM_PERIODIC, FVM_TRANSMISSIVE, FVM_DIRICHLET = 0, 1, 2
 FVM_LAYOUT_PLANES, FVM_LAYOUT_ROWS = 0, 1
@@ -32,7 +33,7 @@ class Params(C.Structure):
         ("lx", C.c_double), ("ly", C.c_double), ("gamma", C.c_double),
         ("ax", C.c_double), ("ay", C.c_double), ("K", C.c_double),
         ("theta", C.c_double), ("s_eps", C.c_double), ("cfl", C.c_double),
-        ("dt_max", C.c_double),
+        ("dt_max", C.c_double), ("closure", C.c_int),
     ]
 
 

@@ -85,7 +85,15 @@ bool valid_params(const fvm_params* p) {
     if (!(p->theta > 0)) return false;
     if (!(p->s_eps > 0 && p->s_eps < 1)) return false;
   }
+  if (p->closure != FVM_CLOSURE_LOGNORMAL && p->closure != FVM_CLOSURE_MAXENT) return false;
+  if (p->closure == FVM_CLOSURE_MAXENT && p->model != FVM_SPRAY) return false;
   return true;
+}
+
+// The kernel family of a grid: the model, or the transport-then-source pair
+// of the spray with the entropy-maximising closure.
+static int kernel_model(const fvm_params& p) {
+  return p.model == FVM_SPRAY && p.closure == FVM_CLOSURE_MAXENT ? kSprayMaxEnt : p.model;
 }
 
 ModelConsts model_consts(const fvm_params& p) {
@@ -268,6 +276,7 @@ int fvm_create(const fvm_params* p, fvm_grid** out) {
   if (!out) return FVM_EINVAL;
   *out = nullptr;
   if (!valid_params(p)) return FVM_EINVAL;
+  if (p->closure == FVM_CLOSURE_MAXENT && p->bc == FVM_DIRICHLET) return FVM_EUNSUPPORTED;
   fvm_grid* g = new (std::nothrow) fvm_grid();
   if (!g) return FVM_EINVAL;
   g->p = *p;
@@ -331,7 +340,8 @@ int fvm_set_boundary_states(fvm_grid* g, const double* ghost) {
 
 int fvm_set_halo_rows(fvm_grid* g, const double* south, const double* north) {
   if (!g) return FVM_EINVAL;
-  if (g->p.bc == FVM_DIRICHLET && (south || north)) return FVM_EUNSUPPORTED;
+  if ((g->p.bc == FVM_DIRICHLET || g->p.closure == FVM_CLOSURE_MAXENT) && (south || north))
+    return FVM_EUNSUPPORTED;
   g->halo.s = south;
   g->halo.n = north;
   g->clear_graphs();  // the cached graphs hold the previous pointers
@@ -455,7 +465,7 @@ int fvm_step(fvm_grid* g, double dt) {
   if (rc) return rc;
   StepArgs a = g->step_args(g->cur, g->other(g->cur), kDtFixedCheck);
   a.dt_arg = dt;
-  rc = dev_err(launch_step(a, g->p.model, g->stream));
+  rc = dev_err(launch_step(a, kernel_model(g->p), g->stream));
   if (rc == FVM_OK) g->cur = a.wout;
   return rc;
 }
@@ -477,7 +487,8 @@ static int graph_for(fvm_grid* g, int kind, int n, double* start, const double* 
   if (hipGraphCreate(&c.graph, 0) != hipSuccess) return FVM_EDEVICE;
   hipGraphNode_t prev = nullptr;
   const double* in = start;
-  void* fn = step_kernel_ptr(g->p.model, g->p.bc, g->wpb, g->cpl, g->halo.s || g->halo.n);
+  const int km = kernel_model(g->p);
+  void* fn = step_kernel_ptr(km, g->p.bc, g->wpb, g->cpl, g->halo.s || g->halo.n);
   std::vector<StepArgs> args(n);
   for (int s = 0; s < n; ++s) {
     double* out = g->other(in);
@@ -503,6 +514,20 @@ static int graph_for(fvm_grid* g, int kind, int n, double* start, const double* 
       return FVM_EDEVICE;
     }
     prev = node;
+    if (km == kSprayMaxEnt) {  // the source pass completes the step
+      MaxEntLaunch ml = maxent_launch(args[s]);
+      void* mp[] = {&args[s], &ml.rule};
+      hipKernelNodeParams sp{};
+      sp.func = ml.fn;
+      sp.gridDim = ml.grid;
+      sp.blockDim = ml.block;
+      sp.kernelParams = mp;
+      if (hipGraphAddKernelNode(&node, c.graph, &prev, 1, &sp) != hipSuccess) {
+        (void)hipGraphDestroy(c.graph);
+        return FVM_EDEVICE;
+      }
+      prev = node;
+    }
     in = out;
   }
   if (hipGraphInstantiate(&c.exec, c.graph, nullptr, nullptr, 0) != hipSuccess) {
@@ -586,7 +611,7 @@ int fvm_run_ckpt(fvm_grid* g, int nsteps, int ckpt_every, double* const* ckpts,
     StepArgs a = g->step_args(in, out, kDtAdaptive);
     a.dt_log = dts_dev;
     a.dt_log_cap = dts_dev ? nsteps : 0;
-    rc = dev_err(launch_step(a, g->p.model, g->stream));
+    rc = dev_err(launch_step(a, kernel_model(g->p), g->stream));
     if (rc) return rc;
     in = out;
   }
@@ -747,9 +772,9 @@ extern "C" {
 int fvm_autotune(fvm_grid* g, const char* cache_path) {
   if (!g || !g->bound) return FVM_EINVAL;
   char kbuf[256];
-  std::snprintf(kbuf, sizeof kbuf, "%s grid model=%d bc=%d nx=%d ny=%d ld=%d layout=%d",
+  std::snprintf(kbuf, sizeof kbuf, "%s grid model=%d bc=%d nx=%d ny=%d ld=%d layout=%d%s",
                 device_arch().c_str(), g->p.model, g->p.bc, g->p.nx, g->p.ny, g->p.ld,
-                g->p.layout);
+                g->p.layout, g->p.closure == FVM_CLOSURE_MAXENT ? " maxent" : "");
   const std::string key = kbuf;
   int rows = 0, wpb = 0, cpl = 0;
   if (cache_lookup(cache_path, key, &rows, &wpb, &cpl) && valid_tiling(rows, wpb) &&
@@ -867,7 +892,7 @@ int fvm_adjoint_run(fvm_grid* g, double* const* ckpts, int ckpt_every, const dou
       StepArgs a = g->step_args(in, out, kDtArray);
       a.dts = dts_dev;
       a.k = k;
-      int rc = dev_err(launch_step(a, g->p.model, g->stream));
+      int rc = dev_err(launch_step(a, kernel_model(g->p), g->stream));
       if (rc) return rc;
       in = out;
     }

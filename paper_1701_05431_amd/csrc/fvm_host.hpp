@@ -17,4 +17,14 @@ struct GridView {
 };
 int grid_view(const fvm_grid* g, GridView* v);
 
+// The entropy-maximising spray source pass (fvm_maxent.hip): launched after
+// the transport-only step kernel, on the step's output buffer.
+struct MaxEntLaunch {
+  void* fn;
+  dim3 grid, block;
+  MaxEntRule rule;
+};
+MaxEntLaunch maxent_launch(const StepArgs& a);
+hipError_t launch_maxent_source(const StepArgs& a, hipStream_t st);
+
 }  // namespace fvm

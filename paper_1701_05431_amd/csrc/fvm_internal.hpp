@@ -15,6 +15,10 @@ constexpr int kWave = 64;       // CDNA wavefront width
 constexpr int kOutPerWave = 62; // cells an adjoint strip updates (lanes 0 and 63: halo)
 constexpr int kMaxVar = 6;      // largest nVar (spray)
 
+// Kernel families: the three models (fvm_params.model) and the spray with
+// the entropy-maximising closure (a transport step, then a source pass).
+enum : int { kSprayMaxEnt = 3 };
+
 // Boundary conditions (template argument BC of the kernels).
 enum : int { kPeriodic = 0, kTransmissive = 1, kDirichlet = 2 };
 // Sides of the domain, in the order of the Dirichlet ghost states.
@@ -173,6 +177,12 @@ struct BatchArgs {
   int nitems;                 // work items of all grids
   double dt_scale;            // 1; 0 for the tuner's dry runs (state unchanged)
   ModelConsts m;
+};
+
+// The entropy-maximising spray source pass (fvm_maxent.hip) takes its
+// quadrature rule as a kernel argument.
+struct MaxEntRule {  // 8-point Gauss-Legendre rule on [0, 1]
+  double x[8], w[8];
 };
 
 }  // namespace fvm

@@ -30,6 +30,7 @@
 #include <cfloat>
 #include <cstdint>
 
+#include "fvm_host.hpp"
 #include "fvm_internal.hpp"
 #include "fvm_models.hpp"
 #include "fvm_step.hpp"
@@ -80,9 +81,11 @@ __global__ FVM_STEP_BOUNDS(WPB) void step_kernel(StepArgs a) {
   unsigned long long bx = 0, by = 0;
   strip<M, BC, CPL, HALO>(m, a.win, a.wout, a.ug, a.g, xs, j0, j1, mux, muy, dt_eff, bx, by,
                           a.ghost, a.halo);
-  if (block_commit<WPB>(bx, by, a.scr, gridDim.x) && threadIdx.x == 0) {
-    if (cfl_fail) atomicOr(&a.scr->status, kStatusCfl);
-    finalize_grid(a.scr, a.g, dt_eff, a.dt_log, a.dt_log_cap, a.dt_log_stride, nullptr);
+  if constexpr (M::kCommit) {
+    if (block_commit<WPB>(bx, by, a.scr, gridDim.x) && threadIdx.x == 0) {
+      if (cfl_fail) atomicOr(&a.scr->status, kStatusCfl);
+      finalize_grid(a.scr, a.g, dt_eff, a.dt_log, a.dt_log_cap, a.dt_log_stride, nullptr);
+    }
   }
 }
 
@@ -154,11 +157,23 @@ static StepFn step_fn_bc(int bc, int wpb, int cpl, bool halo) {
   return cpl == 2 ? step_fn_cpl<M, 2>(bc, wpb, halo) : step_fn_cpl<M, 1>(bc, wpb, halo);
 }
 
+// The transport-only spray step (entropy-maximising closure): periodic and
+// transmissive boundaries, no halo rows.
+template <int CPL>
+static StepFn transport_fn(int bc, int wpb, bool halo) {
+  if (halo) return nullptr;
+  if (bc == kPeriodic) return step_fn_wpb<SprayTransport, kPeriodic, CPL, false>(wpb);
+  if (bc == kTransmissive) return step_fn_wpb<SprayTransport, kTransmissive, CPL, false>(wpb);
+  return nullptr;
+}
+
 void* step_kernel_ptr(int model, int bc, int wpb, int cpl, bool halo) {
   StepFn f = nullptr;
   if (model == 0) f = step_fn_bc<Adv>(bc, wpb, cpl, halo);
   else if (model == 1) f = step_fn_bc<Euler>(bc, wpb, cpl, halo);
   else if (model == 2) f = step_fn_bc<Spray>(bc, wpb, cpl, halo);
+  else if (model == kSprayMaxEnt)
+    f = cpl == 2 ? transport_fn<2>(bc, wpb, halo) : transport_fn<1>(bc, wpb, halo);
   return reinterpret_cast<void*>(f);
 }
 
@@ -167,7 +182,9 @@ hipError_t launch_step(const StepArgs& a, int model, hipStream_t st) {
   if (!f) return hipErrorInvalidValue;
   StepArgs copy = a;
   void* args[] = {&copy};
-  return hipLaunchKernel(f, dim3(a.t.ntiles), dim3(a.t.wpb * kWave), args, 0, st);
+  const hipError_t e = hipLaunchKernel(f, dim3(a.t.ntiles), dim3(a.t.wpb * kWave), args, 0, st);
+  if (e != hipSuccess || model != kSprayMaxEnt) return e;
+  return launch_maxent_source(a, st);
 }
 
 hipError_t launch_cfl(const CflArgs& a, int model, hipStream_t st) {

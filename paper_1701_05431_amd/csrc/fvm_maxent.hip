@@ -1,0 +1,262 @@
+// fvm_maxent.hip -- the spray source with the entropy-maximising closure
+// (Sec. 6.1 eq. Essadki, Sec. 6.2).
+//
+// The evaporation terms need n(S=0) and m_{-1/2}, which the moments
+// m_{0/2..3/2} do not determine; the paper takes them from the size
+// distribution of largest entropy with those moments (the algorithm is in a
+// reference it cites). With x = S^{1/2} that distribution is
+// n(S) = exp(l0 + l1 x + l2 x^2 + l3 x^3) on S in [0, 1]; its multipliers
+// minimise the convex dual Phi(l) = int n dS - sum_k l_k m_{k/2}, whose
+// gradient is the moment mismatch and whose Hessian is the 4 x 4 matrix of
+// the moments m_{(k+l)/2}. Each cell runs Newton's method on Phi from the
+// normal density in x with the cell's mean and variance of x (steps cut back
+// until Phi decreases while the mismatch is large), with every moment
+// integral taken by a composite 8-point Gauss-Legendre rule over 16 panels of
+// x. Then n(S=0) = exp(l0) and m_{-1/2} = int S^{-1/2} n dS.
+//
+// The pass runs after the transport-only step kernel: per cell it reads W*
+// and the gas velocity, writes W^{n+1} = W* + dt S(W*) in place, and reduces
+// the speeds of W^{n+1} into the grid's maxima; its last workgroup sets the
+// next dt (the step kernel's epilogue, moved here). Work per cell is some
+// tens of thousands of FP64 operations against 112 bytes of traffic: the pass
+// is bound by the FP64 vector units, not by HBM. A cell whose moments the
+// closure cannot match becomes NaN, which the speed reduction reports.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cfloat>
+#include <cmath>
+#include <cstdint>
+
+#include "fvm_host.hpp"
+#include "fvm_internal.hpp"
+#include "fvm_models.hpp"
+#include "fvm_step.hpp"
+
+namespace fvm {
+
+constexpr int kMePanels = 16;
+constexpr int kMeThreads = 256;
+constexpr int kMeMaxBlocks = 8192;
+
+// m[j] = int S^{(j-1)/2} n dS = 2 int x^j e^{p(x)} dx for j = 0..7: m[0] is
+// m_{-1/2}, m[1..4] the model's moments, m[5..7] the higher ones the Hessian
+// needs.
+__device__ __forceinline__ void me_moments(const double* l, const MaxEntRule& r, double* m) {
+#pragma unroll
+  for (int j = 0; j < 8; ++j) m[j] = 0.0;
+  constexpr double h = 1.0 / kMePanels;
+  for (int p = 0; p < kMePanels; ++p) {
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+      const double x = fma(r.x[q], h, p * h);
+      const double poly = fma(fma(fma(l[3], x, l[2]), x, l[1]), x, l[0]);
+      const double e = (2.0 * h) * r.w[q] * exp(poly);
+      double xp = e;
+#pragma unroll
+      for (int j = 0; j < 8; ++j) {
+        m[j] += xp;
+        xp *= x;
+      }
+    }
+  }
+}
+
+// Newton direction: solves H d = -g with H_kl = mu[k+l+1] by Cholesky;
+// false if H is not positive definite.
+__device__ __forceinline__ bool me_direction(const double* mu, const double* g, double* d) {
+  double L[4][4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j <= i; ++j) {
+      double s = mu[i + j + 1];
+#pragma unroll
+      for (int k = 0; k < j; ++k) s = fma(-L[i][k], L[j][k], s);
+      if (i == j) {
+        if (!(s > 0.0)) return false;
+        L[i][i] = sqrt(s);
+      } else {
+        L[i][j] = s / L[j][j];
+      }
+    }
+  double y[4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    double s = -g[i];
+#pragma unroll
+    for (int k = 0; k < i; ++k) s = fma(-L[i][k], y[k], s);
+    y[i] = s / L[i][i];
+  }
+#pragma unroll
+  for (int i = 3; i >= 0; --i) {
+    double s = y[i];
+#pragma unroll
+    for (int k = i + 1; k < 4; ++k) s = fma(-L[k][i], d[k], s);
+    d[i] = s / L[i][i];
+  }
+  return true;
+}
+
+// (m_{-1/2}, n(S=0)) of the entropy maximiser with moments w[0..3]; false
+// if the moments cannot be matched.
+__device__ bool maxent_closure(const double* w, const MaxEntRule& r, double& mmh, double& n0) {
+  const double a = w[1] / w[0];
+  const double var = w[2] / w[0] - a * a;
+  if (!(var > 0.0)) return false;
+  double l[4] = {0.0, a / var, -0.5 / var, 0.0}, mu[8];
+  me_moments(l, r, mu);
+  if (!(mu[1] > 0.0)) return false;
+  l[0] = log(w[0] / mu[1]);
+  me_moments(l, r, mu);
+  double prev = INFINITY;
+  for (int it = 0; it < 100; ++it) {
+    double g[4], rel = 0.0;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      g[k] = mu[k + 1] - w[k];
+      const double q = fabs(g[k]) / w[k];
+      rel = q <= rel ? rel : q;  // NaN-sticky
+    }
+    if (!(rel == rel)) return false;
+    if (rel <= 1e-14 || (rel <= 1e-12 && rel > 0.5 * prev)) {
+      mmh = mu[0];
+      n0 = exp(l[0]);
+      return true;
+    }
+    prev = rel;
+    double d[4];
+    if (!me_direction(mu, g, d)) return false;
+    double t = 1.0, trial[4], mt[8];
+    if (rel > 1e-3) {
+      // backtracking until Phi decreases by at least 1e-4 t g.d
+      double phi = mu[1], slope = 0.0;
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        phi = fma(-l[k], w[k], phi);
+        slope = fma(g[k], d[k], slope);
+      }
+      bool accepted = false;
+      for (int ls = 0; ls < 60 && !accepted; ++ls) {
+#pragma unroll
+        for (int k = 0; k < 4; ++k) trial[k] = fma(t, d[k], l[k]);
+        me_moments(trial, r, mt);
+        double pt = mt[1];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) pt = fma(-trial[k], w[k], pt);
+        if (pt <= phi + 1e-4 * t * slope)
+          accepted = true;
+        else
+          t *= 0.5;
+      }
+      if (!accepted) return false;
+    } else {
+#pragma unroll
+      for (int k = 0; k < 4; ++k) trial[k] = l[k] + d[k];
+      me_moments(trial, r, mt);
+    }
+#pragma unroll
+    for (int k = 0; k < 4; ++k) l[k] = trial[k];
+#pragma unroll
+    for (int j = 0; j < 8; ++j) mu[j] = mt[j];
+  }
+  return false;
+}
+
+__global__ __launch_bounds__(kMeThreads) void maxent_source_kernel(StepArgs a, MaxEntRule r) {
+  const Spray m(a.m);
+  bool cfl_fail;
+  const double dt = launch_dt(a, cfl_fail);
+  const double dte = cfl_fail ? 0.0 : dt;
+  const double K = a.m.K, inv_theta = a.m.inv_theta;
+  unsigned long long bx = 0, by = 0;
+  const long long ncell = static_cast<long long>(a.g.nx) * a.g.ny;
+  for (long long c = static_cast<long long>(blockIdx.x) * kMeThreads + threadIdx.x; c < ncell;
+       c += static_cast<long long>(kMeThreads) * gridDim.x) {
+    const int j = static_cast<int>(c / a.g.nx), i = static_cast<int>(c % a.g.nx);
+    double* cell = a.wout + static_cast<size_t>(j) * a.g.ld + i;
+    double w[6];
+#pragma unroll
+    for (int v = 0; v < 6; ++v) w[v] = cell[v * a.g.plane];
+    const double m0 = w[0], m1 = w[1], m2 = w[2];
+    // dt = 0 (a failed CFL check, a dry run) leaves the state as it is
+    if (dte != 0.0 && m0 > 1e-300 && m1 > 1e-300 && m2 > 1e-300) {
+      const size_t uc = ucell(a.g, j, i);
+      const double ugx = a.ug[uc], ugy = a.ug[a.g.uplane + uc];
+      // K = 0: no evaporation, and the closure is not needed
+      double mmh = 0.0, n0 = 0.0;
+      if (K == 0.0 || maxent_closure(w, r, mmh, n0)) {
+        const double r2 = 1.0 / m2;
+        const double ux = w[4] * r2, uy = w[5] * r2;
+        const double Km0 = K * m0;
+        w[0] = fma(dte, -K * n0, m0);
+        w[1] = fma(dte, -(0.5 * K) * mmh, m1);
+        w[2] = fma(dte, -Km0, m2);
+        w[3] = fma(dte, -(1.5 * K) * m1, w[3]);
+        w[4] = fma(dte, fma(-Km0, ux, m0 * (ugx - ux) * inv_theta), w[4]);
+        w[5] = fma(dte, fma(-Km0, uy, m0 * (ugy - uy) * inv_theta), w[5]);
+      } else {
+#pragma unroll
+        for (int v = 0; v < 6; ++v) w[v] = __builtin_nan("");
+      }
+#pragma unroll
+      for (int v = 0; v < 6; ++v) cell[v * a.g.plane] = w[v];
+    }
+    double sx, sy;
+    m.speeds(w, sx, sy);
+    bx = umax64(bx, bits(sx));
+    by = umax64(by, bits(sy));
+  }
+  if (block_commit<kMeThreads / kWave>(bx, by, a.scr, gridDim.x) && threadIdx.x == 0) {
+    if (cfl_fail) atomicOr(&a.scr->status, kStatusCfl);
+    finalize_grid(a.scr, a.g, dte, a.dt_log, a.dt_log_cap, a.dt_log_stride, nullptr);
+  }
+}
+
+// Gauss-Legendre rule of 8 points on [0, 1]: the roots of the Legendre
+// polynomial P_8 (by Newton's method on the three-term recurrence, from the
+// Chebyshev points) mapped from [-1, 1], weights 1 / ((1 - t^2) P_8'(t)^2).
+static MaxEntRule gauss_legendre_8() {
+  MaxEntRule r{};
+  constexpr int n = 8;
+  for (int i = 0; i < n; ++i) {
+    double t = std::cos(M_PI * (i + 0.5) / n), dp = 1.0;
+    for (int it = 0; it < 64; ++it) {
+      double p0 = 1.0, p1 = t;
+      for (int k = 2; k <= n; ++k) {
+        const double p2 = ((2 * k - 1) * t * p1 - (k - 1) * p0) / k;
+        p0 = p1;
+        p1 = p2;
+      }
+      dp = n * (t * p1 - p0) / (t * t - 1.0);
+      const double step = p1 / dp;
+      t -= step;
+      if (std::fabs(step) < 1e-16) break;
+    }
+    r.x[i] = 0.5 * (t + 1.0);
+    r.w[i] = 1.0 / ((1.0 - t * t) * dp * dp);
+  }
+  return r;
+}
+
+MaxEntLaunch maxent_launch(const StepArgs& a) {
+  static const MaxEntRule rule = gauss_legendre_8();
+  MaxEntLaunch l{};
+  l.fn = reinterpret_cast<void*>(&maxent_source_kernel);
+  const long long ncell = static_cast<long long>(a.g.nx) * a.g.ny;
+  const long long blocks =
+      std::min<long long>(kMeMaxBlocks, (ncell + kMeThreads - 1) / kMeThreads);
+  l.grid = dim3(static_cast<unsigned>(blocks < 1 ? 1 : blocks));
+  l.block = dim3(kMeThreads);
+  l.rule = rule;
+  return l;
+}
+
+hipError_t launch_maxent_source(const StepArgs& a, hipStream_t st) {
+  MaxEntLaunch l = maxent_launch(a);
+  StepArgs copy = a;
+  void* args[] = {&copy, &l.rule};
+  return hipLaunchKernel(l.fn, l.grid, l.block, args, 0, st);
+}
+
+}  // namespace fvm

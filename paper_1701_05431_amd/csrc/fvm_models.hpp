@@ -126,6 +126,8 @@ __device__ __forceinline__ int wave_index() {
 // a linear flux in exact arithmetic).
 struct Adv {
   static constexpr int NV = 1;
+  static constexpr bool kSource = false;  // no pointwise source
+  static constexpr bool kCommit = true;   // the step reduces speeds and sets the next dt
   static constexpr int kPrefetch2 = FVM_PREFETCH2_ADV;
   static constexpr int kPrefetch1 = FVM_PREFETCH1_ADV;
   struct Prim {};
@@ -158,6 +160,8 @@ struct Adv {
 // sigma = max(|u_L.n| + c_L, |u_R.n| + c_R)  (Sec. 2.2.1).
 struct Euler {
   static constexpr int NV = 4;
+  static constexpr bool kSource = false;
+  static constexpr bool kCommit = true;
   static constexpr int kPrefetch2 = FVM_PREFETCH2_EULER;
   static constexpr int kPrefetch1 = FVM_PREFETCH1_EULER;
   struct Prim { double u, v, p, c; };
@@ -218,6 +222,8 @@ struct Euler {
 // (m_0, m_{1/2}, m_{2/2}).
 struct Spray {
   static constexpr int NV = 6;
+  static constexpr bool kSource = true;   // the lognormal-closure source, fused
+  static constexpr bool kCommit = true;
   static constexpr int kPrefetch2 = FVM_PREFETCH2_SPRAY;
   static constexpr int kPrefetch1 = FVM_PREFETCH1_SPRAY;
   struct Prim { double ux, uy; };
@@ -279,6 +285,16 @@ struct Spray {
     w[4] = fma(dt, fma(-Km0, ux, m0 * (ugx - ux) * inv_theta), w[4]);
     w[5] = fma(dt, fma(-Km0, uy, m0 * (ugy - uy) * inv_theta), w[5]);
   }
+};
+
+// The spray transport alone: the step kernel writes W* and neither applies
+// the source nor reduces the speeds; the entropy-maximising source pass
+// (fvm_maxent.hip) then completes the step, reduces the speeds of W^{n+1}
+// and sets the next dt.
+struct SprayTransport : Spray {
+  static constexpr bool kSource = false;
+  static constexpr bool kCommit = false;
+  __device__ explicit SprayTransport(const ModelConsts& m) : Spray(m) {}
 };
 
 }  // namespace fvm

@@ -222,7 +222,7 @@ __device__ __forceinline__ void march_strip1(const M& m, const double* __restric
         Wo[v] = W[c][v] - fma(mux, fe - fw, muy * (G[n][v] - G[c][v]));
       }
       const size_t cell = static_cast<size_t>(j) * g.ld + cx;
-      if constexpr (NV == 6) {
+      if constexpr (M::kSource) {
         // rows past the strip are computed but not stored; keep their
         // gas-velocity reads inside the field
         const size_t uc = ucell(g, min(j, j1 - 1), cx);
@@ -377,7 +377,7 @@ __device__ __forceinline__ void march_strip2(const M& m, const double* __restric
         Ob[v] = B[c][v] - fma(mux, fe - Fab[v], muy * (GB[n][v] - GB[c][v]));
       }
       const size_t row = static_cast<size_t>(j) * g.ld;
-      if constexpr (NV == 6) {
+      if constexpr (M::kSource) {
         double ua[2], ub[2];
         GridGeom gu = g;
         gu.ld = g.uld;

@@ -22,7 +22,8 @@ def params_from(preset=None, **kw) -> _lib.Params:
     """fvm_params from a workload preset (or keyword arguments)."""
     d = dict(model=None, bc=_lib.FVM_PERIODIC, nx=None, ny=None, npart_x=1, npart_y=1,
              ld=None, layout=_lib.FVM_LAYOUT_PLANES, lx=1.0, ly=1.0, gamma=1.4, ax=0.0,
-             ay=0.0, K=1.0, theta=0.1, s_eps=0.01, cfl=0.45, dt_max=0.0)
+             ay=0.0, K=1.0, theta=0.1, s_eps=0.01, cfl=0.45, dt_max=0.0,
+             closure=_lib.FVM_CLOSURE_LOGNORMAL)
     if preset is not None:
         for k in ("model", "bc", "nx", "ny", "npart_x", "npart_y", "lx", "ly", "gamma", "ax",
                   "ay", "K", "theta", "s_eps", "cfl", "dt_max"):

@@ -99,6 +99,8 @@ int main(int argc, char** argv) {
   const int model = atoi(argv[1]), bc = atoi(argv[2]), nx = atoi(argv[3]), ny = atoi(argv[4]);
   const int ld = atoi(argv[5]), layout = atoi(argv[6]), cpl = atoi(argv[7]);
   const int rows = atoi(argv[8]), wpb = atoi(argv[9]);
+  // model 3: the spray's transport-only strip (entropy-maximising closure),
+  // which must not touch the gas velocity: it gets none
   const int nv = model == 0 ? 1 : (model == 1 ? 4 : 6);
   if (cpl == 2 && ((ld % 2) || (static_cast<size_t>(nv) * ny * ld) % 2)) {
     std::fprintf(stderr, "two cells per lane needs an even pitch\n");
@@ -140,16 +142,16 @@ int main(int argc, char** argv) {
         at(win, 2, j, i) = -0.125;
         at(win, 3, j, i) = 2.5;
       }
-  if (model == 2) {
+  if (model >= 2) {
     // moments of one size distribution, velocity 0.5 in x; gas alike
-    ug = exact_buffer(2ull * ny * ld, 0.0, keep);
+    if (model == 2) ug = exact_buffer(2ull * ny * ld, 0.0, keep);
     const double m[4] = {1.0, 0.45, 0.25, 0.15};
     for (int j = 0; j < ny; ++j)
       for (int i = 0; i < nx; ++i) {
         for (int v = 0; v < 4; ++v) at(win, v, j, i) = m[v];
         at(win, 4, j, i) = 0.5 * m[2];
         at(win, 5, j, i) = 0.0;
-        ug[static_cast<size_t>(j) * g.uld + i] = 0.5;
+        if (ug) ug[static_cast<size_t>(j) * g.uld + i] = 0.5;
       }
   }
   ModelConsts mc{};
@@ -181,8 +183,11 @@ int main(int argc, char** argv) {
             run_strip<Adv, B>(Adv(mc), win, wout, ug, g, cpl, xs, j0, j1, mux, muy, dt, gh);
           else if (model == 1)
             run_strip<Euler, B>(Euler(mc), win, wout, ug, g, cpl, xs, j0, j1, mux, muy, dt, gh);
-          else
+          else if (model == 2)
             run_strip<Spray, B>(Spray(mc), win, wout, ug, g, cpl, xs, j0, j1, mux, muy, dt, gh);
+          else
+            run_strip<SprayTransport, B>(SprayTransport(mc), win, wout, ug, g, cpl, xs, j0, j1,
+                                         mux, muy, dt, gh);
         };
         if (bc == 0) go(std::integral_constant<int, 0>());
         else if (bc == 1) go(std::integral_constant<int, 1>());

@@ -41,15 +41,17 @@ def test_binding_constants_match_the_header():
     from paper_1701_05431_amd import _lib
     text = open(HEADER).read()
     defines = dict(re.findall(r"#define (FVM_[A-Z_]+) \(?(-?\d+)\)?", text))
-    assert len(defines) == 15
+    assert len(defines) == 17
     for name, value in defines.items():
         assert getattr(_lib, name) == int(value), name
 
 
 def test_params_struct_layout():
     from paper_1701_05431_amd import _lib
-    # 8 ints followed by 10 doubles, no padding
-    assert C.sizeof(_lib.Params) == 8 * 4 + 10 * 8
+    # 8 ints, 10 doubles, then the closure int and the tail padding of an
+    # 8-byte aligned struct
+    assert _lib.Params.closure.offset == 8 * 4 + 10 * 8
+    assert C.sizeof(_lib.Params) == 8 * 4 + 10 * 8 + 8
 
 
 def test_validation_on_host(L):
@@ -69,6 +71,8 @@ def test_validation_on_host(L):
         dict(cfl=float("nan")),
         dict(lx=-1.0),
         dict(dt_max=-1.0),
+        dict(closure=2),
+        dict(closure=1),            # the entropy closure is the spray's
         dict(layout=2),             # unknown layout
         dict(layout=1, ld=600_000_000, ny=1, npart_y=1),  # nVar * ld overflows int
     ]
@@ -121,6 +125,15 @@ def test_create_destroy_and_unbound_calls(L):
     assert L.fvm_set_boundary_states(h, None) == _lib.FVM_EINVAL
     assert L.fvm_destroy(h) == _lib.FVM_OK
     assert L.fvm_destroy(None) == _lib.FVM_OK
+    # the entropy-maximising spray closure: no Dirichlet boundaries, no halo rows
+    me = params_from(model=2, nx=8, ny=8, closure=_lib.FVM_CLOSURE_MAXENT)
+    assert L.fvm_validate(me) == _lib.FVM_OK
+    me_d = params_from(model=2, nx=8, ny=8, bc=_lib.FVM_DIRICHLET,
+                       closure=_lib.FVM_CLOSURE_MAXENT)
+    assert L.fvm_create(me_d, C.byref(h)) == _lib.FVM_EUNSUPPORTED and not h.value
+    assert L.fvm_create(me, C.byref(h)) == _lib.FVM_OK
+    assert L.fvm_set_halo_rows(h, C.c_void_p(256), None) == _lib.FVM_EUNSUPPORTED
+    assert L.fvm_destroy(h) == _lib.FVM_OK
     assert L.fvm_strerror(-4) == b"non-finite or non-physical state"
     assert L.fvm_nvar(2) == 6 and L.fvm_nvar(7) == 0
 
@@ -137,7 +150,8 @@ def test_batch_create_validation(L):
     # overlapping grids
     assert L.fvm_batch_create(2, arr, (C.c_size_t * 2)(0, 32), C.byref(h)) == _lib.FVM_EINVAL
     # misaligned offset
-    assert L.fvm_batch_create(2, arr, (C.c_size_t * 2)(0, 4 * 64 * 64 + 8), C.byref(h)) == _lib.FVM_EINVAL
+    assert (L.fvm_batch_create(2, arr, (C.c_size_t * 2)(0, 4 * 64 * 64 + 8), C.byref(h))
+            == _lib.FVM_EINVAL)
     sp = (_lib.Params * 1)(params_from(model=2, nx=8, ny=8))
     assert L.fvm_batch_create(1, sp, (C.c_size_t * 1)(0), C.byref(h)) == _lib.FVM_EUNSUPPORTED
     dp = (_lib.Params * 1)(params_from(model=1, nx=8, ny=8, bc=_lib.FVM_DIRICHLET))

@@ -136,6 +136,50 @@ def test_spray_trajectory():
     assert ulps(dt, odt) <= DT_ULP
 
 
+@pytest.mark.parametrize("bc,layout,cpl", [(0, 0, 2), (1, 1, 2), (0, 1, 1)])
+def test_spray_maxent_trajectory(bc, layout, cpl):
+    """The entropy-maximising closure (transport step, then the per-cell
+    Newton source pass) against the oracle's, step after step; the oracle
+    integrates the moments with a different, much finer rule."""
+    nx, ny = 64, 48
+    print(f"spray maxent trajectory bc={bc} layout={layout} cpl={cpl}", flush=True)
+    W, ug = inputs.spray_state(nx, ny, 2)
+    pre = inputs.SPRAY_2048.replace(nx=nx, ny=ny, npart_x=4, npart_y=4, bc=bc)
+    p = params_from(pre, layout=layout, closure=_lib.FVM_CLOSURE_MAXENT)
+    s = Solver(p, ug=ug)
+    s.set_cells_per_lane(cpl)
+    s.set_state(W)
+    P = oparams(p)
+    P.closure = 1
+    ref = W.copy()
+    for k in range(6):
+        dts = s.run(1, record_dt=True).cpu().numpy()
+        ref = orc.run_dts(P, ref, dts, ug=ug)
+        got = gpu_state(s)
+        assert np.all(np.isfinite(got)), k
+        err = rel_linf(got, ref)
+        assert err <= TOL, (k, err)
+    _, _, odt = orc.cfl(P, ref)
+    dt, _, _ = s.cfl_dt()
+    assert ulps(dt, odt) <= DT_ULP
+    assert s.sync() == 0
+
+
+def test_spray_maxent_differs_from_lognormal_only_in_evaporation():
+    """With K = 0 the closure is never used: both closures give the same
+    state bit for bit."""
+    n = 64
+    W, ug = inputs.spray_state(n, n, 4)
+    out = []
+    for closure in (_lib.FVM_CLOSURE_LOGNORMAL, _lib.FVM_CLOSURE_MAXENT):
+        pre = inputs.SPRAY_2048.replace(nx=n, ny=n, npart_x=1, npart_y=1, K=0.0)
+        s = Solver(params_from(pre, closure=closure), ug=ug)
+        s.set_state(W)
+        s.run(3)
+        out.append(gpu_state(s))
+    assert np.array_equal(out[0], out[1])
+
+
 # ---------------------------------------------------------------------------
 # invariance: bit-for-bit across subdomains, tiles and launch forms
 # ---------------------------------------------------------------------------
