@@ -148,6 +148,27 @@ def bench_output(steps, warmup, layout="rows", tuning=TUNING):
             "snapshot_bytes": state_bytes, "path": "null device"}
 
 
+def bench_spray_maxent(steps, warmup, layout="rows", tuning=TUNING):
+    """The spray workload with the entropy-maximising closure: a transport
+    step, then the per-cell Newton source pass (FP64-bound)."""
+    import torch
+    from paper_1701_05431_amd import _lib, inputs
+    from paper_1701_05431_amd.solver import Solver, params_from
+    pre = inputs.SPRAY_2048
+    W, ug = inputs.spray_state(pre.nx, pre.ny, 0)
+    s = Solver(params_from(pre, layout=LAYOUTS[layout], closure=_lib.FVM_CLOSURE_MAXENT), ug=ug)
+    s.set_state(torch.from_numpy(W))
+    tiling = s.autotune(tuning)
+    s.run(warmup)
+    sec = timed(lambda: s.run(steps))
+    st = s.sync()
+    cells = pre.nx * pre.ny
+    return {"workload": pre.name + "_maxent", "steps": steps, "status": st,
+            "gcell_updates_per_s": cells * steps / sec / 1e9, "ms_per_step": sec / steps * 1e3,
+            "tiling": {"rows_per_strip": tiling[0], "waves_per_block": tiling[1],
+                       "cells_per_lane": tiling[2]}}
+
+
 def bench_spray(steps, warmup, autotune=True, layout="rows", tuning=TUNING):
     import torch
     from paper_1701_05431_amd import inputs
@@ -391,7 +412,7 @@ def main():
     ap.add_argument("--wpb", type=int, default=0)
     ap.add_argument("--only-euler", action="store_true")
     ap.add_argument("--only", choices=["spray", "batch", "adjoint", "adjoint4096", "slab",
-                                       "advection", "output"],
+                                       "advection", "output", "spray_maxent"],
                     help="run just this secondary workload (for profiling) and print its record")
     ap.add_argument("--no-autotune", action="store_true")
     ap.add_argument("--tuning", default=TUNING,
@@ -421,7 +442,9 @@ def main():
                "adjoint": lambda: bench_adjoint(1, args.layout, args.tuning),
                "advection": lambda: bench_advection(args.steps),
                "output": lambda: bench_output(args.steps, args.warmup, args.layout,
-                                              args.tuning)}[args.only]
+                                              args.tuning),
+               "spray_maxent": lambda: bench_spray_maxent(min(args.steps, 20), 2, args.layout,
+                                                          args.tuning)}[args.only]
         print(json.dumps(run()), flush=True)
         return
 
