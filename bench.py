@@ -473,6 +473,10 @@ def main():
         work["slab"] = bench_slab(200, 20, args.layout, args.tuning)
         log("advection")
         work["advection"] = bench_advection(100)
+        log("spray, entropy-maximising closure")
+        work["spray_maxent"] = bench_spray_maxent(20, 2, args.layout, args.tuning)
+        log("asynchronous output")
+        work["output"] = bench_output(200, 20, args.layout, args.tuning)
     cpu = None
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle)")
