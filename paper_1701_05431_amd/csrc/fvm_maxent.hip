@@ -35,6 +35,16 @@
 
 namespace fvm {
 
+// Quadrature nodes evaluated per unrolled loop step, and the minimum number
+// of waves per SIMD the source pass is compiled for (0: the compiler's
+// choice).
+#ifndef FVM_MAXENT_UNROLL
+#define FVM_MAXENT_UNROLL 8
+#endif
+#ifndef FVM_MAXENT_WAVES
+#define FVM_MAXENT_WAVES 0
+#endif
+
 constexpr int kMePanels = 16;
 constexpr int kMeThreads = 256;
 constexpr int kMeMaxBlocks = 8192;
@@ -47,7 +57,7 @@ __device__ __forceinline__ void me_moments(const double* l, const MaxEntRule& r,
   for (int j = 0; j < 8; ++j) m[j] = 0.0;
   constexpr double h = 1.0 / kMePanels;
   for (int p = 0; p < kMePanels; ++p) {
-#pragma unroll
+#pragma unroll FVM_MAXENT_UNROLL
     for (int q = 0; q < 8; ++q) {
       const double x = fma(r.x[q], h, p * h);
       const double poly = fma(fma(fma(l[3], x, l[2]), x, l[1]), x, l[0]);
@@ -163,7 +173,14 @@ __device__ bool maxent_closure(const double* w, const MaxEntRule& r, double& mmh
   return false;
 }
 
-__global__ __launch_bounds__(kMeThreads) void maxent_source_kernel(StepArgs a, MaxEntRule r) {
+#if FVM_MAXENT_WAVES > 0
+#define FVM_MAXENT_ATTR __attribute__((amdgpu_waves_per_eu(FVM_MAXENT_WAVES)))
+#else
+#define FVM_MAXENT_ATTR
+#endif
+
+__global__ __launch_bounds__(kMeThreads) FVM_MAXENT_ATTR void maxent_source_kernel(StepArgs a,
+                                                                                 MaxEntRule r) {
   const Spray m(a.m);
   bool cfl_fail;
   const double dt = launch_dt(a, cfl_fail);

@@ -165,6 +165,36 @@ def test_spray_maxent_trajectory(bc, layout, cpl):
     assert s.sync() == 0
 
 
+def test_spray_maxent_fixed_dt_and_cfl_check():
+    """The entropy-closure spray under the paper's fixed-dt policy: explicit
+    steps and a checked fixed-dt run match the oracle's fixed-dt steps; a dt
+    that fails the check leaves the state unchanged (neither the transport
+    nor the source pass moves it) and reports FVM_ECFL."""
+    nx, ny = 48, 40
+    print("spray maxent fixed dt", flush=True)
+    W, ug = inputs.spray_state(nx, ny, 5)
+    pre = inputs.SPRAY_2048.replace(nx=nx, ny=ny, npart_x=2, npart_y=2, bc=1)
+    p = params_from(pre, closure=_lib.FVM_CLOSURE_MAXENT)
+    s = Solver(p, ug=ug)
+    s.set_state(W)
+    P = oparams(p)
+    P.closure = 1
+    dt, sx, sy = s.cfl_dt()
+    lim = min(1.0 / nx, 1.0 / ny) / max(sx, sy)
+    s.step(0.5 * lim)
+    s.run_fixed(3, 0.5 * lim)
+    assert s.sync() == 0
+    ref = W.copy()
+    for _ in range(4):
+        rc, ref = orc.step_fixed(P, ref, 0.5 * lim, ug=ug)
+        assert rc == 0
+    assert rel_linf(gpu_state(s), ref) <= TOL
+    before = gpu_state(s)
+    s.run_fixed(2, 8.0 * lim)
+    assert s.sync() == _lib.FVM_ECFL
+    assert np.array_equal(gpu_state(s), before)
+
+
 def test_spray_maxent_differs_from_lognormal_only_in_evaporation():
     """With K = 0 the closure is never used: both closures give the same
     state bit for bit."""
