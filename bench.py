@@ -23,6 +23,7 @@ import hashlib
 import json
 import math
 import os
+import re
 import sys
 import time
 
@@ -40,11 +41,26 @@ COUNTERS = os.path.join(ROOT, "profiles", "euler_4096_step_counters.json")
 TUNING = os.path.join(ROOT, "paper_1701_05431_amd", "tuning_mi355x.txt")
 
 
-def kernel_hash() -> str:
+def _code_only(text: str) -> str:
+    """Source text without comments and blank space: what the compiler sees
+    (string literals in these files hold no comment markers)."""
+    text = re.sub(r"/\*.*?\*/", " ", text, flags=re.S)
+    text = re.sub(r"//[^\n]*", " ", text)
+    return " ".join(text.split())
+
+
+def kernel_hash(read=None) -> str:
+    """Hash of the step kernel's sources, comments and layout left out, so
+    that counters taken on a kernel stay attached to it until its code
+    changes. read(name) -> text (default: the working tree)."""
     h = hashlib.sha256()
     for f in KERNEL_SOURCES:
-        with open(os.path.join(ROOT, "paper_1701_05431_amd", "csrc", f), "rb") as fh:
-            h.update(fh.read())
+        if read is None:
+            with open(os.path.join(ROOT, "paper_1701_05431_amd", "csrc", f)) as fh:
+                text = fh.read()
+        else:
+            text = read(f)
+        h.update(_code_only(text).encode())
     return h.hexdigest()[:16]
 
 

@@ -273,10 +273,10 @@ int fvm_get_cells_per_lane(const fvm_grid* g);
  * for bit unchanged) on the bound buffers and stream, applies the fastest,
  * and, if cache_path is non-NULL, appends it to that text file; a later call
  * with the same device, model, grid shape and layout reuses the stored
- * choice without timing. For advection and Euler grids without Dirichlet
- * boundaries it then picks the adjoint kernel's tile shape the same way
- * (dry adjoint launches with dt = 0 that write the ping-pong buffer not
- * holding the current state). This is the analogue of the paper's
+ * choice without timing (the spray's closure is part of the key). For
+ * advection and Euler grids without Dirichlet boundaries it then picks the
+ * adjoint kernel's tile shape the same way (dry adjoint launches with
+ * dt = 0 that write the ping-pong buffer not holding the current state). This is the analogue of the paper's
  * per-codelet performance models (Sec. 5.3.2): the task size that runs
  * fastest is chosen by measurement. Synchronises the stream. */
 int fvm_autotune(fvm_grid* g, const char* cache_path);
@@ -293,8 +293,8 @@ int fvm_batch_create(int n, const fvm_params* p, const size_t* offsets,
                      fvm_batch** out);
 int fvm_batch_destroy(fvm_batch* b);
 
-/* Scratch bytes of a batch (per-grid maxima, counters, dt, status, the work
- * list of (grid, tile) items). */
+/* Scratch bytes of a batch (per-grid maxima, counters, dt, status, and the
+ * per-grid records of the work list of (grid, group of strips) items). */
 size_t fvm_batch_scratch_bytes(const fvm_batch* b);
 
 /* Binds the packed state buffers (each holding every grid at its offset),
@@ -320,7 +320,10 @@ int fvm_batch_current(const fvm_batch* b, double** w);
 /* Waits and returns the sticky status of the batch. */
 int fvm_batch_sync(fvm_batch* b);
 
-/* Tile shape of the persistent launch (rows per strip, waves per block). */
+/* Tile shape of the batched step: the tallest row block a strip marches
+ * (each grid's blocks are of near-equal height, at most this) and the waves
+ * per workgroup (1, 2, 4 or 8; a work item is that many strips of one grid);
+ * 0 keeps the current value. Results do not depend on it. */
 int fvm_batch_set_tiling(fvm_batch* b, int rows_per_strip, int waves_per_block);
 
 /* Launch schedule of the batched step: persistent != 0 (the default) runs a

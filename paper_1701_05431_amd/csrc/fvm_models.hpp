@@ -1,4 +1,5 @@
-// fvm_models.hpp -- pointwise physics of the three models, device side.
+// fvm_models.hpp -- pointwise physics of the three models (and the spray's
+// transport-only variant), device side.
 //
 // Each model provides
 //   Prim              per-cell derived quantities reused by both face fluxes;
@@ -8,7 +9,12 @@
 //   shift_next(w,p,wr,pr)   the right neighbour's (W, Prim) from lane+1;
 //   speeds(w, sx, sy) largest |eigenvalue| along x and y of a new state, NaN
 //                     when the state is non-finite or non-physical;
-//   source(w, ugx, ugy, dt) the split source step (spray only).
+//   source(w, ugx, ugy, dt) the split source step (spray only);
+//   kSource           whether the step kernel applies source() (the spray
+//                     with the lognormal closure) or not;
+//   kCommit           whether the step kernel reduces the new state's speeds
+//                     and sets the next dt (all but the spray's transport-only
+//                     step, whose source pass does it).
 #pragma once
 
 #include <hip/hip_runtime.h>
