@@ -256,9 +256,14 @@ int fvm_adjoint_step(fvm_grid* g, const double* w, double dt,
 int fvm_set_tiling(fvm_grid* g, int rows_per_strip, int waves_per_block);
 int fvm_get_tiling(const fvm_grid* g, int* rows_per_strip, int* waves_per_block);
 
-/* Tile shape of the adjoint kernel (rows per strip, waves per block; 0
- * keeps the current value); results do not depend on it. */
-int fvm_set_adjoint_tiling(fvm_grid* g, int rows_per_strip, int waves_per_block);
+/* Tile shape and lane layout of the adjoint kernel: rows per strip, waves
+ * per block, and cells per lane (1, the default: 62-column strips; 2:
+ * 128-column strips with 16-byte accesses, taken only where the pitch is even
+ * and the state and multiplier buffers of a launch are 16-byte aligned, else
+ * 1); 0 keeps the current value. fvm_autotune chooses among all of them.
+ * Results do not depend on any of them. */
+int fvm_set_adjoint_tiling(fvm_grid* g, int rows_per_strip, int waves_per_block,
+                           int cells_per_lane);
 
 /* Lanes of the fused step: 1 = one cell per lane (any pitch), 2 = two
  * adjacent cells per lane with 16-byte accesses (needs an even ld and 16-byte

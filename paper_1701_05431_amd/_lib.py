@@ -61,7 +61,7 @@ SIGNATURES = {
     "fvm_run_dts": (C.c_int, [_V, C.c_int, _V]),
     "fvm_run_fixed": (C.c_int, [_V, C.c_int, C.c_double]),
     "fvm_set_boundary_states": (C.c_int, [_V, _V]),
-    "fvm_set_adjoint_tiling": (C.c_int, [_V, C.c_int, C.c_int]),
+    "fvm_set_adjoint_tiling": (C.c_int, [_V, C.c_int, C.c_int, C.c_int]),
     "fvm_set_halo_rows": (C.c_int, [_V, _V, _V]),
     "fvm_batch_set_schedule": (C.c_int, [_V, C.c_int, C.c_int]),
     "fvm_run_ckpt": (C.c_int, [_V, C.c_int, C.c_int, C.POINTER(_V), _V]),

@@ -1,278 +1,62 @@
-// fvm_adjoint.hip -- discrete adjoint of the transport step (advection, Euler).
-//
-// For W^{n+1} = W^n - mux (F_{i+1/2} - F_{i-1/2}) - muy (G_{j+1/2} - G_{j-1/2})
-// with F_{i+1/2} = F~(W_i, W_{i+1}) (Sec. 2.2.1) and dt held fixed, the
-// transpose of the step's Jacobian applied to lambda = lambda^{n+1} is
-//   lambda^n_i = lambda_i + mux [J_L(i+1/2)^T (lambda_{i+1} - lambda_i)
-//                              + J_R(i-1/2)^T (lambda_i - lambda_{i-1})] + (y),
-// J_L = dF~/dW_L = A(W_L)/2 + sigma/2 I - (W_R - W_L) (dsigma/dW_L)^T / 2,
-// J_R = dF~/dW_R = A(W_R)/2 - sigma/2 I - (W_R - W_L) (dsigma/dW_R)^T / 2,
-// where A = dF.n/dW and sigma = max(s_L, s_R) follows its left argument on
-// ties. On a transmissive boundary the ghost cell equals the boundary cell and
-// has no update of its own: its multiplier is zero and its sensitivity goes to
-// the boundary cell.
-//
-// The kernel has the forward kernel's shape: a wave strip marches up the rows;
-// each face's pair (J_L^T d, J_R^T d), d = lambda_R - lambda_L, is computed
-// once, the left cell keeps J_L^T d and the right cell receives J_R^T d (from
-// the previous row for y-faces, from the lane on its left for x-faces).
-// A^T d is evaluated matrix-free:
-//   T = d1 W1 + d2 W2 + d3 (E + p),  Q = d_{1+D} + d3 u_n,
-//   (A^T d)_0 = -u_n T / rho + (gamma-1) |u|^2/2 Q
-//   (A^T d)_1 = u_n d1 + [D=0] (d0 + T/rho) - (gamma-1) u Q
-//   (A^T d)_2 = u_n d2 + [D=1] (d0 + T/rho) - (gamma-1) v Q
-//   (A^T d)_3 = u_n d3 + (gamma-1) Q
-// and ds/dW for s = |u_n| + c is sign(u_n) du_n/dW + gamma/(2 c rho)
-// (dp/dW - p/rho e_0).
+// fvm_adjoint.hip -- the adjoint kernels (one strip per wave, in either lane
+// layout) and their launch; the device code is in fvm_adjoint.hpp.
 #include <hip/hip_runtime.h>
 
+#include "fvm_adjoint.hpp"
 #include "fvm_internal.hpp"
 #include "fvm_models.hpp"
 
-// Rows of (W, lambda) loads in flight per adjoint strip.
-#ifndef FVM_ADJ_PREFETCH
-#define FVM_ADJ_PREFETCH 2
-#endif
-
 namespace fvm {
 
-struct AdjAdv {
-  static constexpr int NV = 1;
-  struct Prim {};
-  double ax, ay;
-  __device__ explicit AdjAdv(const ModelConsts& m) : ax(m.ax), ay(m.ay) {}
-  __device__ __forceinline__ void prim(const double*, Prim&) const {}
-  template <int D>
-  __device__ __forceinline__ void face(const double*, const Prim&, const double*, const Prim&,
-                                       const double* d, double* a, double* b) const {
-    const double s = D == 0 ? ax : ay;
-    a[0] = (s > 0.0 ? s : 0.0) * d[0];
-    b[0] = (s < 0.0 ? s : 0.0) * d[0];
-  }
-  __device__ __forceinline__ void shift_next(const double* w, const Prim&, double* wr,
-                                             Prim&) const {
-    wr[0] = from_next(w[0]);
-  }
-};
-
-struct AdjEuler {
-  static constexpr int NV = 4;
-  struct Prim { double r, u, v, p, c; };
-  double gamma, gm1;
-  __device__ explicit AdjEuler(const ModelConsts& m) : gamma(m.gamma), gm1(m.gm1) {}
-  // (the forward step's refined reciprocal and square root)
-  __device__ __forceinline__ void prim(const double* w, Prim& q) const {
-    q.r = recip(w[0]);
-    q.u = w[1] * q.r;
-    q.v = w[2] * q.r;
-    q.p = gm1 * fma(-0.5, fma(w[1], q.u, w[2] * q.v), w[3]);
-    q.c = root(gamma * q.p * q.r);
-  }
-  // out = A(W)^T d along axis D
-  template <int D>
-  __device__ __forceinline__ void at_d(const double* w, const Prim& q, const double* d,
-                                       double* out) const {
-    const double un = D == 0 ? q.u : q.v;
-    const double T = d[1] * w[1] + d[2] * w[2] + d[3] * (w[3] + q.p);
-    const double Q = d[1 + D] + d[3] * un;
-    const double Tr = T * q.r;
-    const double hq2 = 0.5 * (q.u * q.u + q.v * q.v);
-    out[0] = -un * Tr + gm1 * hq2 * Q;
-    out[1] = un * d[1] - gm1 * q.u * Q;
-    out[2] = un * d[2] - gm1 * q.v * Q;
-    out[3] = un * d[3] + gm1 * Q;
-    out[1 + D] += d[0] + Tr;
-  }
-  // ds/dW of s = |u_n| + c
-  template <int D>
-  __device__ __forceinline__ void dspeed(const Prim& q, double* gs) const {
-    const double un = D == 0 ? q.u : q.v;
-    const double sg = un >= 0.0 ? 1.0 : -1.0;
-    const double k = 0.5 * gamma * q.r * recip(q.c);
-    const double hq2 = 0.5 * (q.u * q.u + q.v * q.v);
-    gs[0] = -sg * un * q.r + k * (gm1 * hq2 - q.p * q.r);
-    gs[1] = -k * gm1 * q.u;
-    gs[2] = -k * gm1 * q.v;
-    gs[3] = k * gm1;
-    gs[1 + D] += sg * q.r;
-  }
-  template <int D>
-  __device__ __forceinline__ void face(const double* wl, const Prim& pl, const double* wr,
-                                       const Prim& pr, const double* d, double* a,
-                                       double* b) const {
-    const double unl = D == 0 ? pl.u : pl.v;
-    const double unr = D == 0 ? pr.u : pr.v;
-    const double sl = fabs(unl) + pl.c;
-    const double sr = fabs(unr) + pr.c;
-    const bool left = sl >= sr;
-    const double hs = 0.5 * (left ? sl : sr);
-    double al[4], ar[4], gs[4];
-    at_d<D>(wl, pl, d, al);
-    at_d<D>(wr, pr, d, ar);
-    if (left) dspeed<D>(pl, gs); else dspeed<D>(pr, gs);
-    const double dwd = (wr[0] - wl[0]) * d[0] + (wr[1] - wl[1]) * d[1] +
-                       (wr[2] - wl[2]) * d[2] + (wr[3] - wl[3]) * d[3];
-    const double h = 0.5 * dwd;
-    const double hl = left ? h : 0.0, hr = left ? 0.0 : h;
-#pragma unroll
-    for (int k = 0; k < 4; ++k) {
-      a[k] = 0.5 * al[k] + hs * d[k] - hl * gs[k];
-      b[k] = 0.5 * ar[k] - hs * d[k] - hr * gs[k];
-    }
-  }
-  __device__ __forceinline__ void shift_next(const double* w, const Prim& q, double* wr,
-                                             Prim& qr) const {
-#pragma unroll
-    for (int v = 0; v < 4; ++v) wr[v] = from_next(w[v]);
-    qr.r = from_next(q.r);
-    qr.u = from_next(q.u);
-    qr.v = from_next(q.v);
-    qr.p = from_next(q.p);
-    qr.c = from_next(q.c);
-  }
-};
-
-template <int BC>
-__device__ __forceinline__ int adj_col(int i, int nx) {
-  int c;
-  if (BC == 0) c = i < 0 ? i + nx : (i >= nx ? i - nx : i);
-  else c = i;
-  c = c < 0 ? 0 : c;
-  return c >= nx ? nx - 1 : c;
-}
-
-template <int BC>
-__device__ __forceinline__ int adj_row(int r, int ny) {
-  if (BC == 0) return r < 0 ? ny - 1 : (r >= ny ? 0 : r);
-  return r < 0 ? 0 : (r >= ny ? ny - 1 : r);
-}
-
-// State and multiplier of row r; the multiplier of a transmissive ghost row
-// (or ghost column, `ghost_col`) is zero.
-template <int NV, int BC>
-__device__ __forceinline__ void load_adj_row(double* w, double* l, const double* __restrict__ wb,
-                                             const double* __restrict__ lb, const GridGeom& g,
-                                             int r, bool ghost_col) {
-  const size_t off = static_cast<size_t>(adj_row<BC>(r, g.ny)) * g.ld;
-  const bool ghost = ghost_col || (BC == 1 && (r < 0 || r >= g.ny));
-#pragma unroll
-  for (int v = 0; v < NV; ++v) {
-    w[v] = wb[v * g.plane + off];
-    const double x = lb[v * g.plane + off];
-    l[v] = ghost ? 0.0 : x;
-  }
-}
-
-template <class M, int BC, int WPB>
+template <class M, int BC, int WPB, int CPL>
 __global__ __launch_bounds__(WPB * kWave) void adjoint_kernel(AdjointArgs a) {
-  constexpr int NV = M::NV;
-  using Prim = typename M::Prim;
   const M m(a.m);
   const double dt = a.dts ? a.dts[a.k] : a.dt_arg;
   const double mux = dt / a.g.dx, muy = dt / a.g.dy;
   const int tile = blockIdx.x;
   const int tx = tile % a.t.tiles_x, ty = tile / a.t.tiles_x;
   const int wave = wave_index();
-  const int lane = threadIdx.x & (kWave - 1);
-  const int xs = (tx * WPB + wave) * kOutPerWave;
-  if (xs >= a.g.nx) return;
   const int j0 = ty * a.t.rows;
   const int j1 = min(j0 + a.t.rows, a.g.ny);
-  const GridGeom& g = a.g;
-  const int i = xs - 1 + lane;
-  const int ic = adj_col<BC>(i, g.nx);
-  const bool out = (lane >= 1) & (lane <= kOutPerWave) & (i < g.nx);
-  const bool ghost_col = BC == 1 && (i < 0 || i >= g.nx);
-  const bool west = BC == 1 && i == 0;
-  const bool east = BC == 1 && i == g.nx - 1;
-  const double* wb = a.w + ic;
-  const double* lb = a.lam_in + ic;
-
-  // Register ring of R = PF + 2 rows of (W, lambda): row j in slot c, row j+1
-  // in slot n, rows up to j+1+PF loading into the slot row j-1 vacated. The
-  // row loop is unrolled R times so every slot index is static; rows past
-  // the strip are computed from clamped loads and not stored.
-  constexpr int PF = FVM_ADJ_PREFETCH;
-  constexpr int R = PF + 2;
-  double W[R][NV], L[R][NV], Bs[NV], As[NV];
-  Prim P[R];
-  load_adj_row<NV, BC>(W[R - 1], L[R - 1], wb, lb, g, j0 - 1, ghost_col);
-  load_adj_row<NV, BC>(W[0], L[0], wb, lb, g, j0, ghost_col);
-#pragma unroll
-  for (int p = 1; p <= PF; ++p)
-    load_adj_row<NV, BC>(W[p], L[p], wb, lb, g, min(j0 + p, j1), ghost_col);
-  m.prim(W[R - 1], P[R - 1]);
-  m.prim(W[0], P[0]);
-  {
-    double d[NV];
-#pragma unroll
-    for (int v = 0; v < NV; ++v) d[v] = L[0][v] - L[R - 1][v];
-    m.template face<1>(W[R - 1], P[R - 1], W[0], P[0], d, As, Bs);  // As: the row below's share
-  }
-
-  for (int jb = j0; jb < j1; jb += R) {
-#pragma unroll
-    for (int u = 0; u < R; ++u) {
-      const int j = jb + u;
-      const int c = u, n = (u + 1) % R, l = (u + R - 1) % R;
-      load_adj_row<NV, BC>(W[l], L[l], wb, lb, g, min(j + 1 + PF, j1), ghost_col);
-      m.prim(W[n], P[n]);
-      double d[NV], Ay[NV], By[NV], Wr[NV], Lr[NV], Ax[NV], Bx[NV];
-      Prim Pr;
-#pragma unroll
-      for (int v = 0; v < NV; ++v) d[v] = L[n][v] - L[c][v];
-      m.template face<1>(W[c], P[c], W[n], P[n], d, Ay, By);
-      m.shift_next(W[c], P[c], Wr, Pr);
-#pragma unroll
-      for (int v = 0; v < NV; ++v) {
-        Lr[v] = from_next(L[c][v]);
-        d[v] = Lr[v] - L[c][v];
-      }
-      m.template face<0>(W[c], P[c], Wr, Pr, d, Ax, Bx);
-      const bool south = BC == 1 && j == 0;
-      const bool north = BC == 1 && j == g.ny - 1;
-      const size_t cell = static_cast<size_t>(j) * g.ld + ic;
-#pragma unroll
-      for (int v = 0; v < NV; ++v) {
-        const double bw = from_prev(Bx[v]);
-        const double aw = from_prev(Ax[v]);
-        double sx = Ax[v] + bw;
-        if (west) sx += aw;
-        if (east) sx += Bx[v];
-        double sy = Ay[v] + Bs[v];
-        if (south) sy += As[v];
-        if (north) sy += By[v];
-        const double lo = L[c][v] + (mux * sx + muy * sy);
-        if (out && j < j1) a.lam_out[v * g.plane + cell] = lo;
-      }
-#pragma unroll
-      for (int v = 0; v < NV; ++v) {
-        Bs[v] = By[v];
-        As[v] = 0.0;
-      }
-    }
+  if constexpr (CPL == 2) {
+    const int xs = (tx * WPB + wave) * 2 * kWave;
+    if (xs >= a.g.nx) return;  // the whole wave
+    if (xs + 2 * kWave <= a.g.nx)
+      adjoint_strip2<M, BC, false>(m, a, xs, j0, j1, mux, muy);
+    else
+      adjoint_strip2<M, BC, true>(m, a, xs, j0, j1, mux, muy);
+  } else {
+    const int xs = (tx * WPB + wave) * kOutPerWave;
+    if (xs >= a.g.nx) return;
+    adjoint_strip1<M, BC>(m, a, xs, j0, j1, mux, muy);
   }
 }
 
-template <class M, int BC>
+template <class M, int BC, int CPL>
 static void* adj_fn_wpb(int wpb) {
   switch (wpb) {
-    case 1: return reinterpret_cast<void*>(&adjoint_kernel<M, BC, 1>);
-    case 2: return reinterpret_cast<void*>(&adjoint_kernel<M, BC, 2>);
-    case 4: return reinterpret_cast<void*>(&adjoint_kernel<M, BC, 4>);
-    case 8: return reinterpret_cast<void*>(&adjoint_kernel<M, BC, 8>);
+    case 1: return reinterpret_cast<void*>(&adjoint_kernel<M, BC, 1, CPL>);
+    case 2: return reinterpret_cast<void*>(&adjoint_kernel<M, BC, 2, CPL>);
+    case 4: return reinterpret_cast<void*>(&adjoint_kernel<M, BC, 4, CPL>);
+    case 8: return reinterpret_cast<void*>(&adjoint_kernel<M, BC, 8, CPL>);
     default: return nullptr;
   }
 }
 
-void* adjoint_kernel_ptr(int model, int bc, int wpb) {
-  if (model == 0) return bc == 0 ? adj_fn_wpb<AdjAdv, 0>(wpb) : adj_fn_wpb<AdjAdv, 1>(wpb);
-  if (model == 1) return bc == 0 ? adj_fn_wpb<AdjEuler, 0>(wpb) : adj_fn_wpb<AdjEuler, 1>(wpb);
+template <class M, int CPL>
+static void* adj_fn_bc(int bc, int wpb) {
+  return bc == 0 ? adj_fn_wpb<M, 0, CPL>(wpb) : adj_fn_wpb<M, 1, CPL>(wpb);
+}
+
+void* adjoint_kernel_ptr(int model, int bc, int wpb, int cpl) {
+  if (model == 0) return cpl == 2 ? adj_fn_bc<AdjAdv, 2>(bc, wpb) : adj_fn_bc<AdjAdv, 1>(bc, wpb);
+  if (model == 1)
+    return cpl == 2 ? adj_fn_bc<AdjEuler, 2>(bc, wpb) : adj_fn_bc<AdjEuler, 1>(bc, wpb);
   return nullptr;
 }
 
 hipError_t launch_adjoint(const AdjointArgs& a, int model, hipStream_t st) {
-  void* f = adjoint_kernel_ptr(model, a.g.bc, a.t.wpb);
+  void* f = adjoint_kernel_ptr(model, a.g.bc, a.t.wpb, a.t.cpl);
   if (!f) return hipErrorInvalidValue;
   AdjointArgs copy = a;
   void* args[] = {&copy};

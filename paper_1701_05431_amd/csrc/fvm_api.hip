@@ -122,13 +122,15 @@ Tiling tiling(const GridGeom& g, int rows, int wpb, int cpl) {
   return t;
 }
 
-// The adjoint kernel's strips update 62 columns each (lanes 0 and 63 only
-// supply the halo), whatever the forward kernel's lane layout.
-Tiling adjoint_tiling(const GridGeom& g, int rows, int wpb) {
-  Tiling t = tiling(g, rows, wpb, 1);
-  const int w = kOutPerWave * wpb;
-  t.tiles_x = (g.nx + w - 1) / w;
-  t.ntiles = t.tiles_x * t.tiles_y;
+// The adjoint kernel's strips: 128 columns with two cells per lane, or 62
+// columns with one (lanes 0 and 63 only supply the halo).
+Tiling adjoint_tiling(const GridGeom& g, int rows, int wpb, int cpl) {
+  Tiling t = tiling(g, rows, wpb, cpl);
+  if (cpl == 1) {
+    const int w = kOutPerWave * wpb;
+    t.tiles_x = (g.nx + w - 1) / w;
+    t.ntiles = t.tiles_x * t.tiles_y;
+  }
   return t;
 }
 
@@ -196,7 +198,8 @@ struct fvm_grid {
   GridGeom g{};
   ModelConsts m{};
   int rows = kDefaultRows, wpb = kDefaultWpb;
-  int adj_rows = kDefaultRows, adj_wpb = kDefaultWpb;  // adjoint kernel (one cell per lane)
+  int adj_rows = kDefaultRows, adj_wpb = kDefaultWpb;  // adjoint kernel tile shape
+  int adj_cpl = 1;   // adjoint cells per lane (the tuner may pick 2 where allowed)
   int cpl_req = 0;   // requested cells per lane (0: the widest the buffers allow)
   int cpl = 1;       // layout in use
   double* w_a = nullptr;
@@ -298,6 +301,13 @@ int fvm_destroy(fvm_grid* g) {
 static bool wide_layout_ok(const fvm_grid* g) {
   auto al = [](const void* p) { return (reinterpret_cast<uintptr_t>(p) & 15) == 0; };
   return g->p.ld % 2 == 0 && al(g->w_a) && al(g->w_b) && (!g->ug || al(g->ug));
+}
+
+// The adjoint's lane layout for one launch: two cells per lane needs an even
+// pitch and 16-byte aligned state and multiplier buffers.
+static int adjoint_cpl(const fvm_grid* g, const double* w, const double* li, const double* lo) {
+  auto al = [](const void* p) { return (reinterpret_cast<uintptr_t>(p) & 15) == 0; };
+  return g->adj_cpl == 2 && g->p.ld % 2 == 0 && al(w) && al(li) && al(lo) ? 2 : 1;
 }
 
 static void choose_layout(fvm_grid* g) {
@@ -715,7 +725,8 @@ static double time_adjoint_dry(fvm_grid* g, int reps) {
   a.dts = nullptr;
   a.dt_arg = 0.0;
   a.g = g->g;
-  a.t = adjoint_tiling(g->g, g->adj_rows, g->adj_wpb);
+  a.t = adjoint_tiling(g->g, g->adj_rows, g->adj_wpb,
+                       adjoint_cpl(g, a.w, a.lam_in, a.lam_out));
   a.m = g->m;
   hipEvent_t e0, e1;
   if (hipEventCreate(&e0) != hipSuccess) return -1.0;
@@ -739,31 +750,42 @@ static double time_adjoint_dry(fvm_grid* g, int reps) {
 static int tune_adjoint(fvm_grid* g, const char* cache_path, const std::string& key) {
   if (g->p.model == FVM_SPRAY || g->p.bc == FVM_DIRICHLET) return FVM_OK;
   int rows = 0, wpb = 0, cpl = 0;
-  if (cache_lookup(cache_path, key, &rows, &wpb, &cpl) && valid_tiling(rows, wpb)) {
+  if (cache_lookup(cache_path, key, &rows, &wpb, &cpl) && valid_tiling(rows, wpb) &&
+      (cpl == 1 || cpl == 2)) {
     g->adj_rows = rows;
     g->adj_wpb = wpb;
+    g->adj_cpl = cpl;
     return FVM_OK;
   }
   const int wpbs[4] = {1, 2, 4, 8};
   const int rowss[9] = {4, 8, 16, 32, 48, 64, 96, 128, 256};
   double best = 1e300;
-  int br = g->adj_rows, bw = g->adj_wpb;
-  for (int w : wpbs)
-    for (int r : rowss) {
-      if (r > g->p.ny && r != rowss[0]) continue;
-      g->adj_rows = r;
-      g->adj_wpb = w;
-      const double us = time_adjoint_dry(g, 4);
-      if (us < 0) return FVM_EDEVICE;
-      if (us < best) {
-        best = us;
-        br = r;
-        bw = w;
+  int br = g->adj_rows, bw = g->adj_wpb, bc = 1;
+  for (int c : {2, 1}) {
+    for (int w : wpbs)
+      for (int r : rowss) {
+        if (r > g->p.ny && r != rowss[0]) continue;
+        if (c == 2 && w == 8 && g->p.model == FVM_EULER) continue;  // spills at 2 waves/SIMD
+        g->adj_rows = r;
+        g->adj_wpb = w;
+        g->adj_cpl = c;
+        // the dry launches run on the ping-pong buffers, which must allow
+        // the layout
+        if (adjoint_cpl(g, g->cur, g->other(g->cur), g->other(g->cur)) != c) continue;
+        const double us = time_adjoint_dry(g, 4);
+        if (us < 0) return FVM_EDEVICE;
+        if (us < best) {
+          best = us;
+          br = r;
+          bw = w;
+          bc = c;
+        }
       }
-    }
+  }
   g->adj_rows = br;
   g->adj_wpb = bw;
-  cache_store(cache_path, key, br, bw, 1, best);
+  g->adj_cpl = bc;
+  cache_store(cache_path, key, br, bw, bc, best);
   return FVM_OK;
 }
 
@@ -833,13 +855,15 @@ int fvm_set_cells_per_lane(fvm_grid* g, int cpl) {
 
 int fvm_get_cells_per_lane(const fvm_grid* g) { return g ? g->cpl : 0; }
 
-int fvm_set_adjoint_tiling(fvm_grid* g, int rows, int wpb) {
+int fvm_set_adjoint_tiling(fvm_grid* g, int rows, int wpb, int cells_per_lane) {
   if (!g) return FVM_EINVAL;
   const int r = rows ? rows : g->adj_rows;
   const int w = wpb ? wpb : g->adj_wpb;
-  if (!valid_tiling(r, w)) return FVM_EINVAL;
+  const int c = cells_per_lane ? cells_per_lane : g->adj_cpl;
+  if (!valid_tiling(r, w) || (c != 1 && c != 2)) return FVM_EINVAL;
   g->adj_rows = r;
   g->adj_wpb = w;
+  g->adj_cpl = c;
   return FVM_OK;
 }
 
@@ -863,7 +887,8 @@ int fvm_adjoint_step(fvm_grid* g, const double* w, double dt, const double* lam_
   a.dts = nullptr;
   a.dt_arg = dt;
   a.g = g->g;
-  a.t = adjoint_tiling(g->g, g->adj_rows, g->adj_wpb);
+  a.t = adjoint_tiling(g->g, g->adj_rows, g->adj_wpb,
+                       adjoint_cpl(g, a.w, a.lam_in, a.lam_out));
   a.m = g->m;
   return dev_err(launch_adjoint(a, g->p.model, g->stream));
 }
@@ -905,7 +930,8 @@ int fvm_adjoint_run(fvm_grid* g, double* const* ckpts, int ckpt_every, const dou
       a.dts = dts_dev;
       a.k = k;
       a.g = g->g;
-      a.t = adjoint_tiling(g->g, g->adj_rows, g->adj_wpb);
+      a.t = adjoint_tiling(g->g, g->adj_rows, g->adj_wpb,
+                       adjoint_cpl(g, a.w, a.lam_in, a.lam_out));
       a.m = g->m;
       int rc = dev_err(launch_adjoint(a, g->p.model, g->stream));
       if (rc) return rc;

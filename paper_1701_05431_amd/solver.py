@@ -237,9 +237,10 @@ class Solver:
     def set_tiling(self, rows: int = 0, waves_per_block: int = 0) -> None:
         check(lib().fvm_set_tiling(self.h, int(rows), int(waves_per_block)), "fvm_set_tiling")
 
-    def set_adjoint_tiling(self, rows: int = 0, waves_per_block: int = 0) -> None:
-        check(lib().fvm_set_adjoint_tiling(self.h, int(rows), int(waves_per_block)),
-              "fvm_set_adjoint_tiling")
+    def set_adjoint_tiling(self, rows: int = 0, waves_per_block: int = 0,
+                           cells_per_lane: int = 0) -> None:
+        check(lib().fvm_set_adjoint_tiling(self.h, int(rows), int(waves_per_block),
+                                           int(cells_per_lane)), "fvm_set_adjoint_tiling")
 
     def tiling(self):
         r, w = C.c_int(), C.c_int()

@@ -703,25 +703,33 @@ def test_adjoint_step(model, bc):
     assert np.array_equal(got_rows[:, :, :nx].cpu().numpy(), got[:, :, :nx].cpu().numpy())
 
 
-@pytest.mark.parametrize("nx", [1, 62, 63, 64, 124, 130, 500, 1024])
-def test_adjoint_step_covers_every_column(nx):
-    """The adjoint strips (62 columns each) tile the whole width at every
-    default workgroup size."""
+@pytest.mark.parametrize("cpl", [1, 2])
+@pytest.mark.parametrize("bc", [0, 1])
+@pytest.mark.parametrize("nx", [1, 2, 62, 63, 64, 124, 127, 128, 129, 130, 257, 500, 1024])
+def test_adjoint_step_covers_every_column(nx, bc, cpl):
+    """The adjoint strips (62 columns with one cell per lane, 128 with two)
+    tile the whole width at every default workgroup size, ragged last strips
+    and periodic wrap included."""
     ny = 9
-    print(f"adjoint widths nx={nx}", flush=True)
+    print(f"adjoint widths nx={nx} bc={bc} cpl={cpl}", flush=True)
     W = inputs.riemann_state(nx, ny, 8) + 0.01 * np.stack(
         [inputs.gaussian_bumps(nx, ny, 50 + v) for v in range(4)])
-    p = params_from(model=1, bc=1, nx=nx, ny=ny)
+    p = params_from(model=1, bc=bc, nx=nx, ny=ny, ld=nx + nx % 2)
     lam = np.random.default_rng(nx).standard_normal(W.shape)
     P = oparams(p)
     _, _, dt = orc.cfl(P, W)
-    got = Solver(p).adjoint_step(W, dt, lam)
+    s = Solver(p)
+    s.set_adjoint_tiling(0, 0, cpl)
+    got = s.adjoint_step(W, dt, lam)
     torch.cuda.synchronize()
     ref = orc.adjoint_step(P, W, dt, lam)
     assert rel_linf(got[:, :, :nx].cpu().numpy(), ref) <= TOL
 
 
 def test_adjoint_tiling_invariance_bitwise():
+    """Tile shapes and both lane layouts give the same multipliers bit for
+    bit (every face is evaluated once with the same arguments and each cell
+    sums its shares in the same order)."""
     nx, ny = 300, 77
     W = inputs.riemann_state(nx, ny, 13)
     lam = np.random.default_rng(5).standard_normal(W.shape)
@@ -731,8 +739,9 @@ def test_adjoint_tiling_invariance_bitwise():
         s = Solver(p)
         _, _, dt = orc.cfl(oparams(p), W)
         res = []
-        for rows, wpb in ((64, 4), (1, 1), (7, 2), (33, 8), (256, 4)):
-            s.set_adjoint_tiling(rows, wpb)
+        for rows, wpb, cpl in ((64, 4, 1), (1, 1, 1), (7, 2, 1), (33, 8, 1), (256, 4, 1),
+                               (64, 4, 2), (1, 1, 2), (7, 2, 2), (33, 8, 2), (16, 4, 2)):
+            s.set_adjoint_tiling(rows, wpb, cpl)
             res.append(s.adjoint_step(W, dt, lam).cpu().numpy())
         for r in res[1:]:
             assert np.array_equal(r, res[0]), bc
