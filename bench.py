@@ -176,11 +176,19 @@ def bench_spray_maxent(steps, warmup, layout="rows", tuning=TUNING):
     s.set_state(torch.from_numpy(W))
     tiling = s.autotune(tuning)
     s.run(warmup)
-    sec = timed(lambda: s.run(steps))
+    cold = timed(lambda: s.run(steps))  # Newton from the normal start in every cell
     st = s.sync()
+    # the same steps with every cell's multipliers kept between steps
+    s.keep_closure_multipliers()
+    s.set_state(torch.from_numpy(W))
+    s.run(warmup)
+    sec = timed(lambda: s.run(steps))
+    st = st or s.sync()
     cells = pre.nx * pre.ny
     return {"workload": pre.name + "_maxent", "steps": steps, "status": st,
             "gcell_updates_per_s": cells * steps / sec / 1e9, "ms_per_step": sec / steps * 1e3,
+            "newton_start": "previous step's multipliers",
+            "ms_per_step_cold_start": cold / steps * 1e3,
             "tiling": {"rows_per_strip": tiling[0], "waves_per_block": tiling[1],
                        "cells_per_lane": tiling[2]}}
 

@@ -158,6 +158,17 @@ int fvm_set_boundary_states(fvm_grid* g, const double* ghost);
  * this call for a grid with Dirichlet boundaries. */
 int fvm_set_halo_rows(fvm_grid* g, const double* south, const double* north);
 
+/* Entropy-maximising spray closure (FVM_CLOSURE_MAXENT): a caller-owned
+ * device buffer of 4 * ny * nx doubles (contents need not be initialised)
+ * in which the source pass keeps every cell's converged multipliers, so
+ * that the next step's Newton iteration starts from them (it falls back to
+ * the cold start where that fails). Results agree with the cold start within
+ * the convergence tolerance, not bit for bit. NULL (the default) turns it
+ * off; setting a state forgets the kept multipliers. FVM_EUNSUPPORTED for a
+ * non-NULL buffer on any other closure. The buffer must stay valid while
+ * set. */
+int fvm_set_closure_buffer(fvm_grid* g, double* lam);
+
 /* Changes the stream later calls enqueue on. */
 int fvm_set_stream(fvm_grid* g, void* stream);
 

@@ -177,10 +177,12 @@ struct GraphKey {
   int k0;
   int rows, wpb, cpl;
   double dt;             // kind 3
+  const double* me_lam;  // entropy closure: the multiplier buffer, and whether
+  bool me_warm;          // the graph's first step starts from it
   bool operator==(const GraphKey& o) const {
     return kind == o.kind && nsteps == o.nsteps && start == o.start && other == o.other &&
            dts == o.dts && log == o.log && k0 == o.k0 && rows == o.rows && wpb == o.wpb &&
-           cpl == o.cpl && dt == o.dt;
+           cpl == o.cpl && dt == o.dt && me_lam == o.me_lam && me_warm == o.me_warm;
   }
 };
 
@@ -208,6 +210,8 @@ struct fvm_grid {
   const double* ug = nullptr;
   double ghost[4 * kMaxVar] = {};  // Dirichlet states, ghost[side * kMaxVar + v]
   Halo halo{};                     // rows from the caller's buffers
+  double* me_lam = nullptr;        // entropy closure: the caller's multiplier buffer
+  bool me_valid = false;           // it holds the multipliers of the current state's cells
   GridScratch* scr = nullptr;
   hipStream_t stream = nullptr;
   bool bound = false;
@@ -335,6 +339,7 @@ int fvm_bind(fvm_grid* g, double* w_a, double* w_b, const double* ug, void* scra
   g->bound = true;
   choose_layout(g);
   g->speeds_valid = false;
+  g->me_valid = false;
   return dev_err(launch_clear_scratch(g->scr, 1, g->stream));
 }
 
@@ -355,6 +360,16 @@ int fvm_set_halo_rows(fvm_grid* g, const double* south, const double* north) {
   g->halo.s = south;
   g->halo.n = north;
   g->clear_graphs();  // the cached graphs hold the previous pointers
+  return FVM_OK;
+}
+
+int fvm_set_closure_buffer(fvm_grid* g, double* lam) {
+  if (!g) return FVM_EINVAL;
+  if (g->p.closure != FVM_CLOSURE_MAXENT) return lam ? FVM_EUNSUPPORTED : FVM_OK;
+  if (lam && (reinterpret_cast<uintptr_t>(lam) & 7)) return FVM_EINVAL;
+  g->me_lam = lam;
+  g->me_valid = false;
+  g->clear_graphs();  // the cached graphs hold the previous pointer
   return FVM_OK;
 }
 
@@ -394,6 +409,7 @@ int fvm_set_state(fvm_grid* g, const double* src, int src_on_device) {
                                 g->stream);
   if (e == hipSuccess && !src_on_device) e = hipStreamSynchronize(g->stream);
   g->speeds_valid = false;
+  g->me_valid = false;
   return dev_err(e);
 }
 
@@ -405,6 +421,18 @@ int fvm_get_state(fvm_grid* g, double* dst, int dst_on_device) {
                                 g->stream);
   if (e == hipSuccess && !dst_on_device) e = hipStreamSynchronize(g->stream);
   return dev_err(e);
+}
+
+// One step launch outside a graph: the step kernel, and for the entropy
+// closure the source pass that completes it.
+static int enqueue_step(fvm_grid* g, const StepArgs& a) {
+  const int km = kernel_model(g->p);
+  int rc = dev_err(launch_step(a, km, g->stream));
+  if (rc || km != kSprayMaxEnt) return rc;
+  MaxEntWarm wm{g->me_lam, g->me_lam && g->me_valid ? 1 : 0, 0};
+  rc = dev_err(launch_maxent_source(a, wm, g->stream));
+  if (rc == FVM_OK && g->me_lam) g->me_valid = true;
+  return rc;
 }
 
 static int enqueue_cfl(fvm_grid* g, double* dt_dev) {
@@ -475,7 +503,7 @@ int fvm_step(fvm_grid* g, double dt) {
   if (rc) return rc;
   StepArgs a = g->step_args(g->cur, g->other(g->cur), kDtFixedCheck);
   a.dt_arg = dt;
-  rc = dev_err(launch_step(a, kernel_model(g->p), g->stream));
+  rc = enqueue_step(g, a);
   if (rc == FVM_OK) g->cur = a.wout;
   return rc;
 }
@@ -484,7 +512,9 @@ int fvm_step(fvm_grid* g, double dt) {
 // `start`, with step k reading its dt according to `mode`.
 static int graph_for(fvm_grid* g, int kind, int n, double* start, const double* dts, int k0,
                      double* log, int log_cap, hipGraphExec_t* exec, double dt = 0.0) {
-  GraphKey key{kind, n, start, g->other(start), dts, log, k0, g->rows, g->wpb, g->cpl, dt};
+  const bool me_warm = g->me_lam && g->me_valid;
+  GraphKey key{kind,   n,      start,  g->other(start), dts, log, k0,
+               g->rows, g->wpb, g->cpl, dt, g->me_lam, me_warm};
   for (auto it = g->graphs.begin(); it != g->graphs.end(); ++it) {
     if (it->key == key) {
       g->graphs.splice(g->graphs.begin(), g->graphs, it);
@@ -526,7 +556,8 @@ static int graph_for(fvm_grid* g, int kind, int n, double* start, const double* 
     prev = node;
     if (km == kSprayMaxEnt) {  // the source pass completes the step
       MaxEntLaunch ml = maxent_launch(args[s]);
-      void* mp[] = {&args[s], &ml.rule};
+      MaxEntWarm wm{g->me_lam, g->me_lam && (me_warm || s > 0) ? 1 : 0, 0};
+      void* mp[] = {&args[s], &ml.rule, &wm};
       hipKernelNodeParams sp{};
       sp.func = ml.fn;
       sp.gridDim = ml.grid;
@@ -573,6 +604,7 @@ static int run_steps(fvm_grid* g, int kind, int nsteps, const double* dts, doubl
     rc = dev_err(hipGraphLaunch(exec, g->stream));
     if (rc) return rc;
     if (n % 2) g->cur = g->other(g->cur);
+    if (g->me_lam) g->me_valid = true;
     done += n;
   }
   g->speeds_valid = true;
@@ -621,7 +653,7 @@ int fvm_run_ckpt(fvm_grid* g, int nsteps, int ckpt_every, double* const* ckpts,
     StepArgs a = g->step_args(in, out, kDtAdaptive);
     a.dt_log = dts_dev;
     a.dt_log_cap = dts_dev ? nsteps : 0;
-    rc = dev_err(launch_step(a, kernel_model(g->p), g->stream));
+    rc = enqueue_step(g, a);
     if (rc) return rc;
     in = out;
   }
@@ -917,7 +949,7 @@ int fvm_adjoint_run(fvm_grid* g, double* const* ckpts, int ckpt_every, const dou
       StepArgs a = g->step_args(in, out, kDtArray);
       a.dts = dts_dev;
       a.k = k;
-      int rc = dev_err(launch_step(a, kernel_model(g->p), g->stream));
+      int rc = enqueue_step(g, a);
       if (rc) return rc;
       in = out;
     }

@@ -24,7 +24,15 @@ struct MaxEntLaunch {
   dim3 grid, block;
   MaxEntRule rule;
 };
+// Multipliers of the previous source pass, per cell (dense planes
+// lam[(k * ny + j) * nx + i], k = 0..3): Newton starts from them when `warm`
+// is set and writes the converged ones back; lam may be null.
+struct MaxEntWarm {
+  double* lam;
+  int warm;
+  int pad;
+};
 MaxEntLaunch maxent_launch(const StepArgs& a);
-hipError_t launch_maxent_source(const StepArgs& a, hipStream_t st);
+hipError_t launch_maxent_source(const StepArgs& a, const MaxEntWarm& wm, hipStream_t st);
 
 }  // namespace fvm

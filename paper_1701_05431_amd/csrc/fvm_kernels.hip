@@ -30,7 +30,6 @@
 #include <cfloat>
 #include <cstdint>
 
-#include "fvm_host.hpp"
 #include "fvm_internal.hpp"
 #include "fvm_models.hpp"
 #include "fvm_step.hpp"
@@ -182,9 +181,7 @@ hipError_t launch_step(const StepArgs& a, int model, hipStream_t st) {
   if (!f) return hipErrorInvalidValue;
   StepArgs copy = a;
   void* args[] = {&copy};
-  const hipError_t e = hipLaunchKernel(f, dim3(a.t.ntiles), dim3(a.t.wpb * kWave), args, 0, st);
-  if (e != hipSuccess || model != kSprayMaxEnt) return e;
-  return launch_maxent_source(a, st);
+  return hipLaunchKernel(f, dim3(a.t.ntiles), dim3(a.t.wpb * kWave), args, 0, st);
 }
 
 hipError_t launch_cfl(const CflArgs& a, int model, hipStream_t st) {

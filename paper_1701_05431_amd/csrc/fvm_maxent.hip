@@ -9,8 +9,9 @@
 // minimise the convex dual Phi(l) = int n dS - sum_k l_k m_{k/2}, whose
 // gradient is the moment mismatch and whose Hessian is the 4 x 4 matrix of
 // the moments m_{(k+l)/2}. Each cell runs Newton's method on Phi from the
-// normal density in x with the cell's mean and variance of x (steps cut back
-// until Phi decreases while the mismatch is large), with every moment
+// normal density in x with the cell's mean and variance of x, or from the
+// cell's multipliers of the previous pass when the caller keeps them (steps
+// cut back until Phi decreases while the mismatch is large), with every moment
 // integral taken by a composite 8-point Gauss-Legendre rule over 16 panels of
 // x. Then n(S=0) = exp(l0) and m_{-1/2} = int S^{-1/2} n dS.
 //
@@ -108,16 +109,13 @@ __device__ __forceinline__ bool me_direction(const double* mu, const double* g, 
   return true;
 }
 
-// (m_{-1/2}, n(S=0)) of the entropy maximiser with moments w[0..3]; false
-// if the moments cannot be matched.
-__device__ bool maxent_closure(const double* w, const MaxEntRule& r, double& mmh, double& n0) {
-  const double a = w[1] / w[0];
-  const double var = w[2] / w[0] - a * a;
-  if (!(var > 0.0)) return false;
-  double l[4] = {0.0, a / var, -0.5 / var, 0.0}, mu[8];
-  me_moments(l, r, mu);
-  if (!(mu[1] > 0.0)) return false;
-  l[0] = log(w[0] / mu[1]);
+// Newton's method on the dual from the multipliers l (in/out): true with
+// (m_{-1/2}, n(S=0)) once the relative moment mismatch is <= 1e-14, or
+// <= 1e-12 when a step no longer halves it; false if the moments cannot be
+// matched from this start.
+__device__ bool maxent_newton(const double* w, const MaxEntRule& r, double* l, double& mmh,
+                              double& n0) {
+  double mu[8];
   me_moments(l, r, mu);
   double prev = INFINITY;
   for (int it = 0; it < 100; ++it) {
@@ -173,14 +171,42 @@ __device__ bool maxent_closure(const double* w, const MaxEntRule& r, double& mmh
   return false;
 }
 
+// (m_{-1/2}, n(S=0)) of the entropy maximiser with moments w[0..3]. With
+// `warm`, Newton starts from the multipliers in l (the cell's previous
+// ones); otherwise, or if that fails, from the normal density in x with the
+// cell's mean and variance of x. l returns the converged multipliers. False
+// if the moments cannot be matched.
+__device__ bool maxent_closure(const double* w, const MaxEntRule& r, bool warm, double* l,
+                               double& mmh, double& n0) {
+  if (warm && finite(l[0]) && finite(l[1]) && finite(l[2]) && finite(l[3])) {
+    double t[4] = {l[0], l[1], l[2], l[3]};
+    if (maxent_newton(w, r, t, mmh, n0)) {
+#pragma unroll
+      for (int k = 0; k < 4; ++k) l[k] = t[k];
+      return true;
+    }
+  }
+  const double a = w[1] / w[0];
+  const double var = w[2] / w[0] - a * a;
+  if (!(var > 0.0)) return false;
+  double c[4] = {0.0, a / var, -0.5 / var, 0.0}, mu[8];
+  me_moments(c, r, mu);
+  if (!(mu[1] > 0.0)) return false;
+  c[0] = log(w[0] / mu[1]);
+  if (!maxent_newton(w, r, c, mmh, n0)) return false;
+#pragma unroll
+  for (int k = 0; k < 4; ++k) l[k] = c[k];
+  return true;
+}
+
 #if FVM_MAXENT_WAVES > 0
 #define FVM_MAXENT_ATTR __attribute__((amdgpu_waves_per_eu(FVM_MAXENT_WAVES)))
 #else
 #define FVM_MAXENT_ATTR
 #endif
 
-__global__ __launch_bounds__(kMeThreads) FVM_MAXENT_ATTR void maxent_source_kernel(StepArgs a,
-                                                                                 MaxEntRule r) {
+__global__ __launch_bounds__(kMeThreads) FVM_MAXENT_ATTR void maxent_source_kernel(
+    StepArgs a, MaxEntRule r, MaxEntWarm wm) {
   const Spray m(a.m);
   bool cfl_fail;
   const double dt = launch_dt(a, cfl_fail);
@@ -202,7 +228,19 @@ __global__ __launch_bounds__(kMeThreads) FVM_MAXENT_ATTR void maxent_source_kern
       const double ugx = a.ug[uc], ugy = a.ug[a.g.uplane + uc];
       // K = 0: no evaporation, and the closure is not needed
       double mmh = 0.0, n0 = 0.0;
-      if (K == 0.0 || maxent_closure(w, r, mmh, n0)) {
+      const size_t lc = static_cast<size_t>(j) * a.g.nx + i;
+      const size_t lp = static_cast<size_t>(a.g.nx) * a.g.ny;
+      double l[4] = {0.0, 0.0, 0.0, 0.0};
+      if (wm.lam && wm.warm) {
+#pragma unroll
+        for (int k = 0; k < 4; ++k) l[k] = wm.lam[k * lp + lc];
+      }
+      const bool ok = K == 0.0 || maxent_closure(w, r, wm.warm != 0, l, mmh, n0);
+      if (ok && K != 0.0 && wm.lam) {
+#pragma unroll
+        for (int k = 0; k < 4; ++k) wm.lam[k * lp + lc] = l[k];
+      }
+      if (ok) {
         const double r2 = 1.0 / m2;
         const double ux = w[4] * r2, uy = w[5] * r2;
         const double Km0 = K * m0;
@@ -269,10 +307,11 @@ MaxEntLaunch maxent_launch(const StepArgs& a) {
   return l;
 }
 
-hipError_t launch_maxent_source(const StepArgs& a, hipStream_t st) {
+hipError_t launch_maxent_source(const StepArgs& a, const MaxEntWarm& wm, hipStream_t st) {
   MaxEntLaunch l = maxent_launch(a);
   StepArgs copy = a;
-  void* args[] = {&copy, &l.rule};
+  MaxEntWarm w = wm;
+  void* args[] = {&copy, &l.rule, &w};
   return hipLaunchKernel(l.fn, l.grid, l.block, args, 0, st);
 }
 

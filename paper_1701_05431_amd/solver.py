@@ -237,6 +237,14 @@ class Solver:
     def set_tiling(self, rows: int = 0, waves_per_block: int = 0) -> None:
         check(lib().fvm_set_tiling(self.h, int(rows), int(waves_per_block)), "fvm_set_tiling")
 
+    def keep_closure_multipliers(self, enable: bool = True) -> None:
+        """Entropy closure: keep every cell's multipliers between steps (a
+        4 x Ny x Nx device buffer) so that Newton restarts from them."""
+        self._me_lam = (torch.empty(4 * self.p.ny * self.p.nx, dtype=torch.float64,
+                                    device=self.device) if enable else None)
+        check(lib().fvm_set_closure_buffer(self.h, _ptr(self._me_lam)),
+              "fvm_set_closure_buffer")
+
     def set_adjoint_tiling(self, rows: int = 0, waves_per_block: int = 0,
                            cells_per_lane: int = 0) -> None:
         check(lib().fvm_set_adjoint_tiling(self.h, int(rows), int(waves_per_block),

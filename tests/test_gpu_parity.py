@@ -165,6 +165,30 @@ def test_spray_maxent_trajectory(bc, layout, cpl):
     assert s.sync() == 0
 
 
+@pytest.mark.parametrize("chunk", [1, 6])
+def test_spray_maxent_warm_start_matches_oracle(chunk):
+    """Newton restarting from each cell's kept multipliers (one step per
+    call, or six steps in one graph) reaches the oracle's cold-start result
+    within the parity tolerance; setting a new state forgets them."""
+    nx, ny = 64, 48
+    print(f"spray maxent warm start chunk={chunk}", flush=True)
+    W, ug = inputs.spray_state(nx, ny, 7)
+    pre = inputs.SPRAY_2048.replace(nx=nx, ny=ny, npart_x=4, npart_y=4)
+    p = params_from(pre, closure=_lib.FVM_CLOSURE_MAXENT)
+    s = Solver(p, ug=ug)
+    s.keep_closure_multipliers()
+    P = oparams(p)
+    P.closure = 1
+    for rep in range(2):  # the second pass starts over from a new state
+        s.set_state(W)
+        dts = np.concatenate([s.run(chunk, record_dt=True).cpu().numpy()
+                              for _ in range(6 // chunk)])
+        ref = orc.run_dts(P, W, dts, ug=ug)
+        err = rel_linf(gpu_state(s), ref)
+        assert err <= TOL, (rep, err)
+    assert s.sync() == 0
+
+
 def test_spray_maxent_fixed_dt_and_cfl_check():
     """The entropy-closure spray under the paper's fixed-dt policy: explicit
     steps and a checked fixed-dt run match the oracle's fixed-dt steps; a dt
