@@ -30,7 +30,7 @@
 #define FVM_PREFETCH2_EULER 2
 #endif
 #ifndef FVM_PREFETCH2_SPRAY
-#define FVM_PREFETCH2_SPRAY 1
+#define FVM_PREFETCH2_SPRAY 0  // no ring of loads in flight: two waves per SIMD instead
 #endif
 // ... and for the aligned one-cell-per-lane layout
 #ifndef FVM_PREFETCH1_ADV
@@ -298,6 +298,7 @@ struct Spray {
 // (fvm_maxent.hip) then completes the step, reduces the speeds of W^{n+1}
 // and sets the next dt.
 struct SprayTransport : Spray {
+  static constexpr int kPrefetch2 = 1;
   static constexpr bool kSource = false;
   static constexpr bool kCommit = false;
   __device__ explicit SprayTransport(const ModelConsts& m) : Spray(m) {}
