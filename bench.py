@@ -271,6 +271,9 @@ def bench_adjoint(reps, layout="rows", tuning=TUNING):
     Wt = torch.from_numpy(W).cuda()
     s.set_state(Wt)
     s.autotune(tuning)
+    # the adjoint's tiles, timed on multiplier buffers like the backward pass's
+    la = s._as_state(torch.zeros((s.nv, pre.ny, pre.nx), dtype=torch.float64))
+    s.autotune_adjoint(s._as_state(Wt), la, torch.empty_like(la), tuning)
     holder = {}
 
     def fwd():
@@ -313,7 +316,8 @@ def bench_adjoint_step_4096(reps, layout="rows", tuning=TUNING):
     la = s._as_state(torch.randn((s.nv, pre.ny, pre.nx), dtype=torch.float64, generator=g))
     lb = torch.empty_like(la)
     s.set_state(W0)
-    s.autotune(tuning)  # also picks the adjoint kernel's tile shape
+    s.autotune(tuning)
+    s.autotune_adjoint(W, la, lb, tuning)  # the adjoint's tiles, on these buffers
     dt = s.cfl_dt()[0]
     L = lib()
     ptr = lambda t: C.c_void_p(t.data_ptr())

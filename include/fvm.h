@@ -297,6 +297,17 @@ int fvm_get_cells_per_lane(const fvm_grid* g);
  * fastest is chosen by measurement. Synchronises the stream. */
 int fvm_autotune(fvm_grid* g, const char* cache_path);
 
+/* Adjoint tuner on the caller's buffers: times adjoint steps with dt = 0
+ * (lam_out receives lam_in bit for bit) of every tile shape and lane layout
+ * on w and lam_in -> lam_out (distinct buffers of one state each, as
+ * fvm_adjoint_step takes them), applies the fastest and caches it like
+ * fvm_autotune (its own key). Separate multiplier buffers move the traffic
+ * of real adjoint steps, which the in-place dry launches of fvm_autotune
+ * only approximate. FVM_EUNSUPPORTED where fvm_adjoint_step is.
+ * Synchronises the stream. */
+int fvm_autotune_adjoint(fvm_grid* g, const double* w, const double* lam_in, double* lam_out,
+                         const char* cache_path);
+
 /* ---- batches of independent grids -------------------------------------- */
 
 /* Creates a plan for n independent grids solved together, one persistent

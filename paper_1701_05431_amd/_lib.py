@@ -86,6 +86,7 @@ SIGNATURES = {
     "fvm_batch_set_tiling": (C.c_int, [_V, C.c_int, C.c_int]),
     "fvm_batch_autotune": (C.c_int, [_V, C.c_char_p]),
     "fvm_set_closure_buffer": (C.c_int, [_V, _V]),
+    "fvm_autotune_adjoint": (C.c_int, [_V, _V, _V, _V, C.c_char_p]),
     "fvm_output_create": (C.c_int, [_V, _V, _V, _V, C.POINTER(_V)]),
     "fvm_output_snapshot": (C.c_int, [_V, C.c_char_p, C.c_longlong, C.c_double]),
     "fvm_output_wait": (C.c_int, [_V]),

@@ -745,15 +745,16 @@ static double time_dry(fvm_grid* g, int n, int reps) {
   return us;
 }
 
-// Times `reps` dry adjoint launches in the current adjoint tiling: W is the
-// current state, lambda the other ping-pong buffer (which holds no state),
-// read and written in place; with dt = 0 every cell writes back the value it
-// read, so the launches move the real traffic and change nothing.
-static double time_adjoint_dry(fvm_grid* g, int reps) {
+// Times `reps` dry adjoint launches in the current adjoint tiling on
+// (w, lam_in -> lam_out); with dt = 0 every cell writes the value it read,
+// so the launches move the real traffic and change nothing (with
+// lam_in == lam_out they rewrite it in place).
+static double time_adjoint_dry(fvm_grid* g, int reps, const double* w, const double* lam_in,
+                               double* lam_out) {
   AdjointArgs a{};
-  a.w = g->cur;
-  a.lam_in = g->other(g->cur);
-  a.lam_out = g->other(g->cur);
+  a.w = w;
+  a.lam_in = lam_in;
+  a.lam_out = lam_out;
   a.dts = nullptr;
   a.dt_arg = 0.0;
   a.g = g->g;
@@ -778,8 +779,11 @@ static double time_adjoint_dry(fvm_grid* g, int reps) {
   return us;
 }
 
-// The adjoint kernel's tile shape (advection and Euler, not Dirichlet).
-static int tune_adjoint(fvm_grid* g, const char* cache_path, const std::string& key) {
+// The adjoint kernel's tile shape and lane layout (advection and Euler, not
+// Dirichlet), timed on (state, lam_in -> lam_out); fvm_autotune passes the
+// current state and the other ping-pong buffer, read and written in place.
+static int tune_adjoint(fvm_grid* g, const char* cache_path, const std::string& key,
+                        const double* state, const double* lam_in, double* lam_out) {
   if (g->p.model == FVM_SPRAY || g->p.bc == FVM_DIRICHLET) return FVM_OK;
   int rows = 0, wpb = 0, cpl = 0;
   if (cache_lookup(cache_path, key, &rows, &wpb, &cpl) && valid_tiling(rows, wpb) &&
@@ -801,10 +805,9 @@ static int tune_adjoint(fvm_grid* g, const char* cache_path, const std::string& 
         g->adj_rows = r;
         g->adj_wpb = w;
         g->adj_cpl = c;
-        // the dry launches run on the ping-pong buffers, which must allow
-        // the layout
-        if (adjoint_cpl(g, g->cur, g->other(g->cur), g->other(g->cur)) != c) continue;
-        const double us = time_adjoint_dry(g, 4);
+        // the timed buffers must allow the layout
+        if (adjoint_cpl(g, state, lam_in, lam_out) != c) continue;
+        const double us = time_adjoint_dry(g, 4, state, lam_in, lam_out);
         if (us < 0) return FVM_EDEVICE;
         if (us < best) {
           best = us;
@@ -823,6 +826,18 @@ static int tune_adjoint(fvm_grid* g, const char* cache_path, const std::string& 
 
 extern "C" {
 
+int fvm_autotune_adjoint(fvm_grid* g, const double* w, const double* lam_in, double* lam_out,
+                         const char* cache_path) {
+  if (!g || !g->bound || !w || !lam_in || !lam_out || lam_in == lam_out) return FVM_EINVAL;
+  if (g->p.model == FVM_SPRAY || g->p.bc == FVM_DIRICHLET) return FVM_EUNSUPPORTED;
+  char kbuf[256];
+  std::snprintf(kbuf, sizeof kbuf,
+                "%s grid model=%d bc=%d nx=%d ny=%d ld=%d layout=%d adjoint buffers",
+                device_arch().c_str(), g->p.model, g->p.bc, g->p.nx, g->p.ny, g->p.ld,
+                g->p.layout);
+  return tune_adjoint(g, cache_path, kbuf, w, lam_in, lam_out);
+}
+
 int fvm_autotune(fvm_grid* g, const char* cache_path) {
   if (!g || !g->bound) return FVM_EINVAL;
   char kbuf[256];
@@ -838,7 +853,8 @@ int fvm_autotune(fvm_grid* g, const char* cache_path) {
     g->cpl_req = cpl;
     g->clear_graphs();
     choose_layout(g);
-    return tune_adjoint(g, cache_path, key + " adjoint");
+    return tune_adjoint(g, cache_path, key + " adjoint", g->cur, g->other(g->cur),
+                        g->other(g->cur));
   }
   const int cpls[2] = {2, 1};
   const int wpbs[4] = {1, 2, 4, 8};
@@ -875,7 +891,8 @@ int fvm_autotune(fvm_grid* g, const char* cache_path) {
   choose_layout(g);
   g->speeds_valid = true;  // the dry runs recomputed the maxima of the unchanged state
   cache_store(cache_path, key, br, bw, bc, best);
-  return tune_adjoint(g, cache_path, key + " adjoint");
+  return tune_adjoint(g, cache_path, key + " adjoint", g->cur, g->other(g->cur),
+                      g->other(g->cur));
 }
 
 int fvm_set_cells_per_lane(fvm_grid* g, int cpl) {

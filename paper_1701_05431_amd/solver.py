@@ -273,6 +273,15 @@ class Solver:
         check(lib().fvm_autotune(self.h, path), "fvm_autotune")
         return self.tiling() + (self.cells_per_lane(),)
 
+    def autotune_adjoint(self, W: torch.Tensor, lam_in: torch.Tensor, lam_out: torch.Tensor,
+                         cache_path: str | None = None) -> None:
+        """Tiles the adjoint kernel by timing dt = 0 steps on these storage
+        buffers (one state each; lam_out receives lam_in)."""
+        self._bind_stream()
+        path = cache_path.encode() if cache_path else None
+        check(lib().fvm_autotune_adjoint(self.h, _ptr(W), _ptr(lam_in), _ptr(lam_out), path),
+              "fvm_autotune_adjoint")
+
 
 class Batch:
     """Many independent grids packed in one buffer per ping-pong side, each

@@ -103,6 +103,7 @@ def test_create_destroy_and_unbound_calls(L):
     assert L.fvm_create(p, C.byref(h)) == _lib.FVM_OK and h.value
     # nothing is bound: every device call is refused before touching HIP
     assert L.fvm_run(h, 3, None) == _lib.FVM_EINVAL
+    assert L.fvm_autotune_adjoint(h, None, None, None, None) == _lib.FVM_EINVAL
     assert L.fvm_step(h, 0.1) == _lib.FVM_EINVAL
     assert L.fvm_sync(h) == _lib.FVM_EINVAL
     r, w = C.c_int(), C.c_int()

@@ -773,6 +773,30 @@ def test_adjoint_tiling_invariance_bitwise():
     assert not np.array_equal(outs[0], outs[1])
 
 
+def test_adjoint_tuner_on_caller_buffers():
+    """fvm_autotune_adjoint times dt = 0 steps on the given buffers: the
+    output buffer ends up holding the input multipliers bit for bit, the
+    state is untouched, and the chosen tiling still gives the oracle's
+    adjoint step."""
+    nx, ny = 200, 72
+    W = inputs.riemann_state(nx, ny, 21)
+    p = params_from(model=1, bc=1, nx=nx, ny=ny, ld=nx, layout=_lib.FVM_LAYOUT_ROWS)
+    s = Solver(p)
+    Ws = s._as_state(W)
+    lam = np.random.default_rng(21).standard_normal(W.shape)
+    la = s._as_state(lam)
+    lb = torch.full_like(la, 7.0)
+    w_before = Ws.clone()
+    s.autotune_adjoint(Ws, la, lb)
+    torch.cuda.synchronize()
+    assert torch.equal(lb, la) and torch.equal(Ws, w_before)
+    P = oparams(p)
+    _, _, dt = orc.cfl(P, W)
+    got = s.adjoint_step(W, dt, lam)
+    torch.cuda.synchronize()
+    assert rel_linf(got[:, :, :nx].cpu().numpy(), orc.adjoint_step(P, W, dt, lam)) <= TOL
+
+
 def test_fvrun_gradient_matches_oracle_and_fd():
     n = 32
     W0 = inputs.riemann_state(n, n, 0)
