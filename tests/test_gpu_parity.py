@@ -432,6 +432,48 @@ def _random_case(seed):
     return model, bc, nx, ny, ld, layout, cpl, rows, wpb, npx, npy
 
 
+@pytest.mark.parametrize("seed", range(12))
+def test_random_maxent_configurations_match_oracle(seed):
+    """The entropy-closure spray over seeded random sizes, pitches, storage
+    and lane layouts, tile shapes, subdomain counts, boundaries, evaporation
+    rates and Newton starts (cold, or kept multipliers): 3 adaptive steps
+    against the oracle, or the same status where the draw is degenerate."""
+    rng = np.random.default_rng(5000 + seed)
+    bc = int(rng.integers(0, 2))
+    nx = int(rng.choice([1, 2, 3, 17, 64, 65, 128, 129]))
+    ny = int(rng.choice([1, 2, 5, 17, 33]))
+    ld = nx + int(rng.integers(0, 5))
+    layout = int(rng.integers(0, 2))
+    cpl = int(rng.choice([1, 2]))
+    rows = int(rng.choice([1, 3, 8, 32]))
+    wpb = int(rng.choice([1, 2, 4]))
+    npx = int(rng.choice([d for d in (1, 2, 4) if nx % d == 0]))
+    npy = int(rng.choice([d for d in (1, 2, 4) if ny % d == 0]))
+    K = float(rng.choice([0.0, 0.2, 1.0]))
+    warm = bool(rng.integers(0, 2))
+    print(f"random maxent case {seed}: bc={bc} {nx}x{ny} ld={ld} layout={layout} cpl={cpl} "
+          f"tile={rows}x{wpb} parts={npx}x{npy} K={K} warm={warm}", flush=True)
+    W, ug = inputs.spray_state(nx, ny, 300 + seed)
+    pre = inputs.SPRAY_2048.replace(nx=nx, ny=ny, npart_x=npx, npart_y=npy, bc=bc, K=K)
+    p = params_from(pre, ld=ld, layout=layout, closure=_lib.FVM_CLOSURE_MAXENT)
+    s = Solver(p, ug=ug)
+    s.set_cells_per_lane(cpl)
+    s.set_tiling(rows, wpb)
+    if warm:
+        s.keep_closure_multipliers()
+    s.set_state(W)
+    dts = s.run(3, record_dt=True).cpu().numpy()
+    P = oparams(p)
+    P.closure = 1
+    orc_rc, _, _ = orc.run(P, W, 3, ug=ug, return_status=True)
+    if orc_rc != 0:
+        assert s.sync() == orc_rc
+        return
+    assert s.sync() == 0
+    ref = orc.run_dts(P, W, dts, ug=ug)
+    assert rel_linf(gpu_state(s), ref) <= TOL
+
+
 @pytest.mark.parametrize("seed", range(40))
 def test_random_configurations_match_oracle(seed):
     """Seeded random model, boundary, size, pitch, storage and lane layout,
