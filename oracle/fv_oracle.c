@@ -57,7 +57,8 @@
  *      state, one constant state per side of the domain.
  *   R8 the adjoint (not in the paper) is the exact transpose of the
  *      implemented transport step with dt held fixed; max() follows the left
- *      argument on ties and d|x|/dx = +1 at x = 0.
+ *      argument on ties and d|x|/dx = +1 at x = 0; a Dirichlet ghost state
+ *      is a constant, so nothing flows back into it.
  */
 #include <math.h>
 #include <stdlib.h>
@@ -1032,16 +1033,20 @@ static void num_flux_jacobians(const orc_params* P, const double* wl,
 
 /* One adjoint step: lam_out = (dW^{n+1}/dW^n)^T lam_in for the transport
  * step at state W with time step dt. Scatter over faces with explicit
- * Jacobians; on a transmissive boundary the ghost has no update equation
- * (its multiplier is zero) and its sensitivity goes to the boundary cell. */
+ * Jacobians. A ghost cell has no update equation (its multiplier is zero);
+ * on a transmissive boundary it is a copy of the boundary cell, so its
+ * sensitivity goes to that cell; on a Dirichlet boundary it holds the
+ * prescribed state, which does not depend on W, so its sensitivity is
+ * dropped. */
 int orc_adjoint_step(const orc_params* P, const double* W, double dt,
                      const double* lam_in, double* lam_out)
 {
   int rc = orc_validate(P);
   if (rc) return rc;
-  if (P->model == ORC_SPRAY || P->bc == ORC_DIRICHLET) return ORC_EUNSUPPORTED;
+  if (P->model == ORC_SPRAY) return ORC_EUNSUPPORTED;
   int nv = orc_nvar(P->model), nx = P->nx, ny = P->ny;
   size_t plane = (size_t)nx * ny;
+  int dir = P->bc == ORC_DIRICHLET;
   double mu[2] = {dt / (P->lx / nx), dt / (P->ly / ny)};
   int per = P->bc == ORC_PERIODIC;
   memcpy(lam_out, lam_in, sizeof(double) * nv * plane);
@@ -1065,6 +1070,9 @@ int orc_adjoint_step(const orc_params* P, const double* W, double dt,
         for (int v = 0; v < nv; ++v) {
           wl[v] = W[v * plane + cl];
           wr[v] = W[v * plane + cr];
+          /* Dirichlet ghosts: west/east along x, south/north along y */
+          if (dir && !vl) wl[v] = P->ghost[d == 0 ? ORC_WEST : ORC_SOUTH][v];
+          if (dir && !vr) wr[v] = P->ghost[d == 0 ? ORC_EAST : ORC_NORTH][v];
         }
         num_flux_jacobians(P, wl, wr, d, JL, JR);
         for (int v = 0; v < nv; ++v) {
@@ -1078,8 +1086,8 @@ int orc_adjoint_step(const orc_params* P, const double* W, double dt,
             sL = sL + JL[k][l] * dl[k];
             sR = sR + JR[k][l] * dl[k];
           }
-          lam_out[l * plane + cl] = lam_out[l * plane + cl] + mu[d] * sL;
-          lam_out[l * plane + cr] = lam_out[l * plane + cr] + mu[d] * sR;
+          if (vl || !dir) lam_out[l * plane + cl] = lam_out[l * plane + cl] + mu[d] * sL;
+          if (vr || !dir) lam_out[l * plane + cr] = lam_out[l * plane + cr] + mu[d] * sR;
         }
       }
   }
@@ -1095,7 +1103,7 @@ int orc_adjoint_run(const orc_params* P, const double* W0, int nsteps,
 {
   int rc = orc_validate(P);
   if (rc) return rc;
-  if (P->model == ORC_SPRAY || P->bc == ORC_DIRICHLET) return ORC_EUNSUPPORTED;
+  if (P->model == ORC_SPRAY) return ORC_EUNSUPPORTED;
   int nv = orc_nvar(P->model);
   size_t n = (size_t)nv * P->nx * P->ny;
   double* states = (double*)malloc(sizeof(double) * n * (nsteps > 0 ? nsteps : 1));

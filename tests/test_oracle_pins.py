@@ -259,12 +259,47 @@ def test_dirichlet_boundary_flux_balance(orc):
     assert np.all(np.abs(change - flux_in) <= 1e-13 * scale)
 
 
-def test_dirichlet_adjoint_is_unsupported(orc):
+def test_dirichlet_adjoint_is_the_transposed_affine_step(orc):
+    """Advection with Dirichlet ghosts is an affine step W -> A W + b (b from
+    the ghost states): the adjoint step must be A^T, with A brute-forced
+    column by column as step(e_k) - step(0)."""
+    nx, ny = 6, 5
+    ghost = [[0.7], [-0.3], [0.4], [1.1]]
+    P = orc.params(orc.ADV, nx, ny, bc=orc.DIRICHLET, ax=0.8, ay=-0.6, ghost=ghost)
+    dt = 0.05
+    n = nx * ny
+    base = orc.run_dts(P, np.zeros((1, ny, nx)), [dt])
+    A = np.zeros((n, n))
+    for k in range(n):
+        e = np.zeros(n)
+        e[k] = 1.0
+        A[:, k] = (orc.run_dts(P, e.reshape(1, ny, nx), [dt]) - base).reshape(-1)
+    lam = np.random.default_rng(4).standard_normal((1, ny, nx))
+    got = orc.adjoint_step(P, np.zeros((1, ny, nx)), dt, lam).reshape(-1)
+    assert np.max(np.abs(got - A.T @ lam.reshape(-1))) <= 1e-14
+
+
+def test_dirichlet_euler_adjoint_central_differences(orc):
+    """The Euler adjoint with Dirichlet ghost states against central
+    differences of the oracle's own forward steps (dts held fixed)."""
     n = 8
+    W0 = inputs.riemann_state(n, n, 5)
     P = orc.params(orc.EULER, n, n, bc=orc.DIRICHLET, ghost=_euler_ghosts())
-    W = inputs.riemann_state(n, n, 1)
-    with pytest.raises(Exception):
-        orc.adjoint_step(P, W, 1e-3, np.ones_like(W))
+    _, dts = orc.run(P, W0, 8)
+    tgt = inputs.adjoint_target_density(n, n, 5)
+    def loss(W):
+        WN = orc.run_dts(P, W, dts)
+        return 0.5 * np.sum((WN[0] - tgt) ** 2)
+    WN = orc.run_dts(P, W0, dts)
+    lamN = np.zeros_like(W0)
+    lamN[0] = WN[0] - tgt
+    g = orc.adjoint_run(P, W0, dts, lamN)
+    rng = np.random.default_rng(6)
+    for _ in range(8):
+        v = rng.standard_normal(W0.shape)
+        eps = 1e-6
+        fd = (loss(W0 + eps * v) - loss(W0 - eps * v)) / (2 * eps)
+        assert abs(np.sum(g * v) - fd) <= 1e-6 * max(1.0, abs(fd))
 
 
 # --------------------------------------------------------------------------
