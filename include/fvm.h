@@ -234,9 +234,11 @@ int fvm_sync(fvm_grid* g);
 int fvm_get_status(fvm_grid* g, int clear);
 
 /* Gradient of a loss of the final state with respect to the initial state,
- * through nsteps transport steps with frozen time steps (advection and Euler;
- * FVM_EUNSUPPORTED for the spray model and for Dirichlet boundaries). The
- * adjoint of one step is
+ * through nsteps transport steps with frozen time steps (advection and Euler,
+ * every boundary condition; FVM_EUNSUPPORTED for the spray model and with
+ * halo rows). A transmissive ghost is a copy of its boundary cell, so its
+ * sensitivity goes to that cell; a Dirichlet ghost is a constant state and
+ * takes none. The adjoint of one step is
  *   lam^n = lam^{n+1} + dt/dx [J_L(i+1/2)^T (lam_{i+1} - lam_i)
  *                             + J_R(i-1/2)^T (lam_i - lam_{i-1})] + (same in y)
  * with J_L, J_R the Jacobians of the numerical flux with respect to its left
@@ -290,10 +292,10 @@ int fvm_get_cells_per_lane(const fvm_grid* g);
  * and, if cache_path is non-NULL, appends it to that text file; a later call
  * with the same device, model, grid shape and layout reuses the stored
  * choice without timing (the spray's closure is part of the key). For
- * advection and Euler grids without Dirichlet boundaries it then picks the
- * adjoint kernel's tile shape the same way (dry adjoint launches with
- * dt = 0 that write the ping-pong buffer not holding the current state). This is the analogue of the paper's
- * per-codelet performance models (Sec. 5.3.2): the task size that runs
+ * advection and Euler grids it then picks the adjoint kernel's tile shape
+ * the same way (dry adjoint launches with dt = 0 that write the ping-pong
+ * buffer not holding the current state). This is the analogue of the
+ * paper's per-codelet performance models (Sec. 5.3.2): the task size that runs
  * fastest is chosen by measurement. Synchronises the stream. */
 int fvm_autotune(fvm_grid* g, const char* cache_path);
 

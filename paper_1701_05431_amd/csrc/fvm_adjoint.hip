@@ -45,7 +45,12 @@ static void* adj_fn_wpb(int wpb) {
 
 template <class M, int CPL>
 static void* adj_fn_bc(int bc, int wpb) {
-  return bc == 0 ? adj_fn_wpb<M, 0, CPL>(wpb) : adj_fn_wpb<M, 1, CPL>(wpb);
+  switch (bc) {
+    case kPeriodic: return adj_fn_wpb<M, kPeriodic, CPL>(wpb);
+    case kTransmissive: return adj_fn_wpb<M, kTransmissive, CPL>(wpb);
+    case kDirichlet: return adj_fn_wpb<M, kDirichlet, CPL>(wpb);
+    default: return nullptr;
+  }
 }
 
 void* adjoint_kernel_ptr(int model, int bc, int wpb, int cpl) {

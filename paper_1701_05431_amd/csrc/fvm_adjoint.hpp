@@ -154,19 +154,26 @@ __device__ __forceinline__ int adj_row(int r, int ny) {
   return r < 0 ? 0 : (r >= ny ? ny - 1 : r);
 }
 
-// State and multiplier of row r; the multiplier of a transmissive ghost row
-// (or ghost column, `ghost_col`) is zero.
+// State and multiplier of row r; the multiplier of a ghost row (or ghost
+// column, `ghost_col`) is zero. With Dirichlet boundaries (BC 2) a ghost
+// holds the prescribed state of its side (gh: ghost[side * kMaxVar + v];
+// `col_side` is the side of a ghost column); with transmissive ones it is the
+// boundary cell, loaded from the clamped index.
 template <int NV, int BC>
 __device__ __forceinline__ void load_adj_row(double* w, double* l, const double* __restrict__ wb,
                                              const double* __restrict__ lb, const GridGeom& g,
-                                             int r, bool ghost_col) {
+                                             int r, bool ghost_col, const double* gh = nullptr,
+                                             int col_side = 0) {
   const size_t off = static_cast<size_t>(adj_row<BC>(r, g.ny)) * g.ld;
-  const bool ghost = ghost_col || (BC == 1 && (r < 0 || r >= g.ny));
+  const bool ghost_row = BC != 0 && (r < 0 || r >= g.ny);
+  const bool ghost = ghost_col || ghost_row;
+  const int side = ghost_row ? (r < 0 ? kSouth : kNorth) : col_side;
 #pragma unroll
   for (int v = 0; v < NV; ++v) {
-    w[v] = wb[v * g.plane + off];
-    const double x = lb[v * g.plane + off];
-    l[v] = ghost ? 0.0 : x;
+    const double x = wb[v * g.plane + off];
+    w[v] = (BC == kDirichlet && ghost) ? gh[side * kMaxVar + v] : x;
+    const double y = lb[v * g.plane + off];
+    l[v] = ghost ? 0.0 : y;
   }
 }
 
@@ -182,7 +189,9 @@ __device__ __forceinline__ void adjoint_strip1(const M& m, const AdjointArgs& a,
   const int i = xs - 1 + lane;
   const int ic = adj_col<BC>(i, g.nx);
   const bool out = (lane >= 1) & (lane <= kOutPerWave) & (i < g.nx);
-  const bool ghost_col = BC == 1 && (i < 0 || i >= g.nx);
+  const bool ghost_col = BC != 0 && (i < 0 || i >= g.nx);
+  const int col_side = i < 0 ? kWest : kEast;
+  const double* gh = a.ghost;
   const bool west = BC == 1 && i == 0;
   const bool east = BC == 1 && i == g.nx - 1;
   const double* wb = a.w + ic;
@@ -196,11 +205,11 @@ __device__ __forceinline__ void adjoint_strip1(const M& m, const AdjointArgs& a,
   constexpr int R = PF + 2;
   double W[R][NV], L[R][NV], Bs[NV], As[NV];
   Prim P[R];
-  load_adj_row<NV, BC>(W[R - 1], L[R - 1], wb, lb, g, j0 - 1, ghost_col);
-  load_adj_row<NV, BC>(W[0], L[0], wb, lb, g, j0, ghost_col);
+  load_adj_row<NV, BC>(W[R - 1], L[R - 1], wb, lb, g, j0 - 1, ghost_col, gh, col_side);
+  load_adj_row<NV, BC>(W[0], L[0], wb, lb, g, j0, ghost_col, gh, col_side);
 #pragma unroll
   for (int p = 1; p <= PF; ++p)
-    load_adj_row<NV, BC>(W[p], L[p], wb, lb, g, min(j0 + p, j1), ghost_col);
+    load_adj_row<NV, BC>(W[p], L[p], wb, lb, g, min(j0 + p, j1), ghost_col, gh, col_side);
   m.prim(W[R - 1], P[R - 1]);
   m.prim(W[0], P[0]);
   {
@@ -215,7 +224,8 @@ __device__ __forceinline__ void adjoint_strip1(const M& m, const AdjointArgs& a,
     for (int u = 0; u < R; ++u) {
       const int j = jb + u;
       const int c = u, n = (u + 1) % R, l = (u + R - 1) % R;
-      load_adj_row<NV, BC>(W[l], L[l], wb, lb, g, min(j + 1 + PF, j1), ghost_col);
+      load_adj_row<NV, BC>(W[l], L[l], wb, lb, g, min(j + 1 + PF, j1), ghost_col, gh,
+                           col_side);
       m.prim(W[n], P[n]);
       double d[NV], Ay[NV], By[NV], Wr[NV], Lr[NV], Ax[NV], Bx[NV];
       Prim Pr;
@@ -276,18 +286,21 @@ __device__ __forceinline__ void adjoint_strip2(const M& m, const AdjointArgs& a,
   const int ca = EDGE ? adj_col<BC>(xa, g.nx) : xa;
   const int cb = EDGE ? adj_col<BC>(xb, g.nx) : xb;
   const bool oka = !EDGE || xa < g.nx, okb = !EDGE || xb < g.nx;
-  const bool gca = BC == 1 && EDGE && xa >= g.nx;
-  const bool gcb = BC == 1 && EDGE && xb >= g.nx;
+  const bool gca = BC != 0 && EDGE && xa >= g.nx;
+  const bool gcb = BC != 0 && EDGE && xb >= g.nx;
   const int hx = first ? xs - 1 : xs + 2 * kWave;  // halo column of lanes 0 and 63
   const int ch = adj_col<BC>(hx, g.nx);
-  const bool gch = BC == 1 && (hx < 0 || hx >= g.nx);
+  const bool gch = BC != 0 && (hx < 0 || hx >= g.nx);
+  const int h_side = hx < 0 ? kWest : kEast;
+  const double* gh = a.ghost;
   const bool west = BC == 1 && xa == 0;
   const bool east_a = BC == 1 && xa == g.nx - 1;
   const bool east_b = BC == 1 && xb == g.nx - 1;
 
   auto prow = [&](double* wa, double* wbv, double* la, double* lbv, int r) {
     const size_t off = static_cast<size_t>(adj_row<BC>(r, g.ny)) * g.ld;
-    const bool grow = BC == 1 && (r < 0 || r >= g.ny);
+    const bool grow = BC != 0 && (r < 0 || r >= g.ny);
+    const int rs = r < 0 ? kSouth : kNorth;
 #pragma unroll
     for (int v = 0; v < NV; ++v) {
       const size_t base = v * g.plane + off;
@@ -305,16 +318,30 @@ __device__ __forceinline__ void adjoint_strip2(const M& m, const AdjointArgs& a,
         la[v] = (grow || gca) ? 0.0 : x;
         lbv[v] = (grow || gcb) ? 0.0 : y;
       }
+      if constexpr (BC == kDirichlet) {
+        // ghost rows, then ghost columns past the east edge (corners are
+        // never used)
+        if (grow) {
+          wa[v] = gh[rs * kMaxVar + v];
+          wbv[v] = gh[rs * kMaxVar + v];
+        } else {
+          if (gca) wa[v] = gh[kEast * kMaxVar + v];
+          if (gcb) wbv[v] = gh[kEast * kMaxVar + v];
+        }
+      }
     }
   };
   auto hrow = [&](double* wh, double* lh, int r) {
     const size_t off = static_cast<size_t>(adj_row<BC>(r, g.ny)) * g.ld + ch;
-    const bool ghost = gch || (BC == 1 && (r < 0 || r >= g.ny));
+    const bool grow = BC != 0 && (r < 0 || r >= g.ny);
+    const bool ghost = gch || grow;
+    const int side = grow ? (r < 0 ? kSouth : kNorth) : h_side;
 #pragma unroll
     for (int v = 0; v < NV; ++v) {
-      wh[v] = a.w[v * g.plane + off];
-      const double x = a.lam_in[v * g.plane + off];
-      lh[v] = ghost ? 0.0 : x;
+      const double x = a.w[v * g.plane + off];
+      wh[v] = (BC == kDirichlet && ghost) ? gh[side * kMaxVar + v] : x;
+      const double y = a.lam_in[v * g.plane + off];
+      lh[v] = ghost ? 0.0 : y;
     }
   };
 

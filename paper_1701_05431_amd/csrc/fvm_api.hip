@@ -761,6 +761,7 @@ static double time_adjoint_dry(fvm_grid* g, int reps, const double* w, const dou
   a.t = adjoint_tiling(g->g, g->adj_rows, g->adj_wpb,
                        adjoint_cpl(g, a.w, a.lam_in, a.lam_out));
   a.m = g->m;
+  std::memcpy(a.ghost, g->ghost, sizeof a.ghost);
   hipEvent_t e0, e1;
   if (hipEventCreate(&e0) != hipSuccess) return -1.0;
   if (hipEventCreate(&e1) != hipSuccess) {
@@ -779,12 +780,12 @@ static double time_adjoint_dry(fvm_grid* g, int reps, const double* w, const dou
   return us;
 }
 
-// The adjoint kernel's tile shape and lane layout (advection and Euler, not
-// Dirichlet), timed on (state, lam_in -> lam_out); fvm_autotune passes the
+// The adjoint kernel's tile shape and lane layout (advection and Euler),
+// timed on (state, lam_in -> lam_out); fvm_autotune passes the
 // current state and the other ping-pong buffer, read and written in place.
 static int tune_adjoint(fvm_grid* g, const char* cache_path, const std::string& key,
                         const double* state, const double* lam_in, double* lam_out) {
-  if (g->p.model == FVM_SPRAY || g->p.bc == FVM_DIRICHLET) return FVM_OK;
+  if (g->p.model == FVM_SPRAY) return FVM_OK;
   int rows = 0, wpb = 0, cpl = 0;
   if (cache_lookup(cache_path, key, &rows, &wpb, &cpl) && valid_tiling(rows, wpb) &&
       (cpl == 1 || cpl == 2)) {
@@ -829,7 +830,7 @@ extern "C" {
 int fvm_autotune_adjoint(fvm_grid* g, const double* w, const double* lam_in, double* lam_out,
                          const char* cache_path) {
   if (!g || !g->bound || !w || !lam_in || !lam_out || lam_in == lam_out) return FVM_EINVAL;
-  if (g->p.model == FVM_SPRAY || g->p.bc == FVM_DIRICHLET) return FVM_EUNSUPPORTED;
+  if (g->p.model == FVM_SPRAY) return FVM_EUNSUPPORTED;
   char kbuf[256];
   std::snprintf(kbuf, sizeof kbuf,
                 "%s grid model=%d bc=%d nx=%d ny=%d ld=%d layout=%d adjoint buffers",
@@ -926,7 +927,7 @@ int fvm_get_tiling(const fvm_grid* g, int* rows, int* wpb) {
 int fvm_adjoint_step(fvm_grid* g, const double* w, double dt, const double* lam_in,
                      double* lam_out) {
   if (!g || !g->bound || !w || !lam_in || !lam_out || lam_in == lam_out) return FVM_EINVAL;
-  if (g->p.model == FVM_SPRAY || g->p.bc == FVM_DIRICHLET) return FVM_EUNSUPPORTED;
+  if (g->p.model == FVM_SPRAY) return FVM_EUNSUPPORTED;
   if (g->halo.s || g->halo.n) return FVM_EUNSUPPORTED;
   if (!(dt >= 0.0) || !std::isfinite(dt)) return FVM_EINVAL;
   AdjointArgs a{};
@@ -939,6 +940,7 @@ int fvm_adjoint_step(fvm_grid* g, const double* w, double dt, const double* lam_
   a.t = adjoint_tiling(g->g, g->adj_rows, g->adj_wpb,
                        adjoint_cpl(g, a.w, a.lam_in, a.lam_out));
   a.m = g->m;
+  std::memcpy(a.ghost, g->ghost, sizeof a.ghost);
   return dev_err(launch_adjoint(a, g->p.model, g->stream));
 }
 
@@ -948,7 +950,7 @@ int fvm_adjoint_run(fvm_grid* g, double* const* ckpts, int ckpt_every, const dou
       !lam_tmp || lam == lam_tmp)
     return FVM_EINVAL;
   if (ckpt_every > 1 && !seg_buf) return FVM_EINVAL;
-  if (g->p.model == FVM_SPRAY || g->p.bc == FVM_DIRICHLET) return FVM_EUNSUPPORTED;
+  if (g->p.model == FVM_SPRAY) return FVM_EUNSUPPORTED;
   if (g->halo.s || g->halo.n) return FVM_EUNSUPPORTED;
   const int nck = (nsteps + ckpt_every - 1) / ckpt_every;
   for (int s = 0; s < nck; ++s)
@@ -980,8 +982,9 @@ int fvm_adjoint_run(fvm_grid* g, double* const* ckpts, int ckpt_every, const dou
       a.k = k;
       a.g = g->g;
       a.t = adjoint_tiling(g->g, g->adj_rows, g->adj_wpb,
-                       adjoint_cpl(g, a.w, a.lam_in, a.lam_out));
+                           adjoint_cpl(g, a.w, a.lam_in, a.lam_out));
       a.m = g->m;
+      std::memcpy(a.ghost, g->ghost, sizeof a.ghost);
       int rc = dev_err(launch_adjoint(a, g->p.model, g->stream));
       if (rc) return rc;
       std::swap(lin, lout);

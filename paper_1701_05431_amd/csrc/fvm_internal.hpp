@@ -139,6 +139,7 @@ struct AdjointArgs {
   GridGeom g;
   Tiling t;
   ModelConsts m;
+  double ghost[4 * kMaxVar];  // Dirichlet states: ghost[side * kMaxVar + v]
 };
 
 // ---- batches ---------------------------------------------------------------

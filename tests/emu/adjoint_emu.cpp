@@ -132,6 +132,10 @@ int main(int argc, char** argv) {
       }
       for (int vv = 0; vv < nv; ++vv) at(lin, vv, j, i) = rnd();
     }
+  // Dirichlet (bc 2): ghost states a little off the interior values
+  double ghost[4 * kMaxVar] = {};
+  for (int side = 0; side < 4; ++side)
+    for (int v = 0; v < nv; ++v) ghost[side * kMaxVar + v] = (1.05 + 0.1 * side) * at(w, v, 0, 0);
   ModelConsts mc{};
   mc.gamma = 1.4;
   mc.gm1 = 0.4;
@@ -145,6 +149,7 @@ int main(int argc, char** argv) {
     a.lam_out = cpl == 1 ? out1 : out2;
     a.dt_arg = dt;
     a.g = g;
+    for (int k = 0; k < 4 * kMaxVar; ++k) a.ghost[k] = ghost[k];
     const int sw = cpl == 1 ? kOutPerWave : 2 * kWave;
     const int nstrip = (nx + sw - 1) / sw, tiles_y = (ny + rows - 1) / rows;
     for (int ty = 0; ty < tiles_y; ++ty)
@@ -158,7 +163,8 @@ int main(int argc, char** argv) {
             run_strip<AdjEuler, B>(AdjEuler(mc), a, cpl, xs, j0, j1, mux, muy);
         };
         if (bc == 0) go(std::integral_constant<int, 0>());
-        else go(std::integral_constant<int, 1>());
+        else if (bc == 1) go(std::integral_constant<int, 1>());
+        else go(std::integral_constant<int, 2>());
       }
   }
   long missing = 0, stray = 0, differ = 0;

@@ -3,12 +3,12 @@
 tests/emu/adjoint_emu.cpp compiles the device code of both adjoint strip
 layouts (62 columns with one cell per lane; 128 with two) as plain C++, 64
 host threads in lockstep per wave, under AddressSanitizer, with every buffer
-exactly as large as the C ABI's contract. For advection and Euler, periodic
-and transmissive boundaries, both storage layouts and a set of widths,
-heights and row blocks (exact fits, ragged last strips, grids narrower than a
-strip), it checks that no access leaves the buffers, that every cell is
-written and no padding column touched, and that the two layouts give the
-same multipliers bit for bit.
+exactly as large as the C ABI's contract. For advection and Euler, periodic,
+transmissive and Dirichlet boundaries, both storage layouts and a set of
+widths, heights and row blocks (exact fits, ragged last strips, grids
+narrower than a strip), it checks that no access leaves the buffers, that
+every cell is written and no padding column touched, and that the two
+layouts give the same multipliers bit for bit.
 """
 import itertools
 import os
@@ -41,7 +41,7 @@ def emu(tmp_path_factory):
 
 def test_adjoint_strips_in_bounds_and_layouts_agree(emu):
     cases = [(model, bc, nx, ny, ld, layout, rows)
-             for model, bc, layout in itertools.product((0, 1), (0, 1), (0, 1))
+             for model, bc, layout in itertools.product((0, 1), (0, 1, 2), (0, 1))
              for nx, ny, ld, rows in SHAPES]
     env = dict(os.environ, ASAN_OPTIONS="detect_leaks=0:abort_on_error=0")
 

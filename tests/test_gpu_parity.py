@@ -343,7 +343,7 @@ def test_dirichlet_matches_oracle_in_every_layout(model, nx):
 
 def test_dirichlet_ghost_states_change_between_runs():
     """New ghost states apply to the next run (cached launch graphs are
-    rebuilt); the adjoint refuses Dirichlet boundaries."""
+    rebuilt) and to the adjoint step."""
     n = 96
     W, _, _, ghost = _dirichlet_case(1, n, n, 5)
     p = params_from(model=1, bc=_lib.FVM_DIRICHLET, nx=n, ny=n, npart_x=2, npart_y=3)
@@ -360,8 +360,11 @@ def test_dirichlet_ghost_states_change_between_runs():
     assert rel_linf(mid, ref) <= TOL
     ref = orc.run_dts(oparams(p, ghost2), ref, d2)
     assert rel_linf(got, ref) <= TOL
-    with pytest.raises(_lib.FvmError):
-        s.adjoint_step(W, 1e-4, np.ones_like(W))
+    lam = np.random.default_rng(3).standard_normal(W.shape)
+    adj = s.adjoint_step(W, 1e-4, lam)
+    torch.cuda.synchronize()
+    oref = orc.adjoint_step(oparams(p, ghost2), W, 1e-4, lam)
+    assert rel_linf(adj[:, :, :n].cpu().numpy(), oref) <= TOL
 
 
 @pytest.mark.parametrize("model", [1, 2])
@@ -743,20 +746,20 @@ def test_batch_workload_sample_parity():
 # adjoint
 # ---------------------------------------------------------------------------
 
-@pytest.mark.parametrize("bc", [0, 1])
+@pytest.mark.parametrize("bc", [0, 1, 2])
 @pytest.mark.parametrize("model", [0, 1])
 def test_adjoint_step(model, bc):
     nx, ny = 133, 70
+    W, _, kw, ghost = _dirichlet_case(model, nx, ny, 6)
     if model == 1:
-        W = inputs.riemann_state(nx, ny, 6) + 0.01 * np.stack(
-            [inputs.gaussian_bumps(nx, ny, 40 + v) for v in range(4)])
-        p = params_from(model=1, bc=bc, nx=nx, ny=ny)
-    else:
-        W = inputs.advection_state(nx, ny, 6)
-        p = params_from(model=0, bc=bc, nx=nx, ny=ny, ax=0.7, ay=-0.4)
+        W = W + 0.01 * np.stack([inputs.gaussian_bumps(nx, ny, 40 + v) for v in range(4)])
+    p = params_from(model=model, bc=bc, nx=nx, ny=ny, **kw)
+    gh = ghost if bc == _lib.FVM_DIRICHLET else None
     lam = np.random.default_rng(7).standard_normal(W.shape)
     s = Solver(p)
-    P = oparams(p)
+    if gh is not None:
+        s.set_boundary_states(gh)
+    P = oparams(p, gh)
     _, _, dt = orc.cfl(P, W)
     got = s.adjoint_step(W, dt, lam)
     torch.cuda.synchronize()
@@ -764,13 +767,19 @@ def test_adjoint_step(model, bc):
     assert rel_linf(got[:, :, :nx].cpu().numpy(), ref) <= TOL
     p.layout = _lib.FVM_LAYOUT_ROWS
     p.ld = nx + 3
-    got_rows = Solver(p).adjoint_step(W, dt, lam)
-    torch.cuda.synchronize()
-    assert np.array_equal(got_rows[:, :, :nx].cpu().numpy(), got[:, :, :nx].cpu().numpy())
+    for cpl in (1, 2):
+        sr = Solver(p)
+        if gh is not None:
+            sr.set_boundary_states(gh)
+        sr.set_adjoint_tiling(0, 0, cpl)
+        got_rows = sr.adjoint_step(W, dt, lam)
+        torch.cuda.synchronize()
+        assert np.array_equal(got_rows[:, :, :nx].cpu().numpy(),
+                              got[:, :, :nx].cpu().numpy()), cpl
 
 
 @pytest.mark.parametrize("cpl", [1, 2])
-@pytest.mark.parametrize("bc", [0, 1])
+@pytest.mark.parametrize("bc", [0, 1, 2])
 @pytest.mark.parametrize("nx", [1, 2, 62, 63, 64, 124, 127, 128, 129, 130, 257, 500, 1024])
 def test_adjoint_step_covers_every_column(nx, bc, cpl):
     """The adjoint strips (62 columns with one cell per lane, 128 with two)
@@ -782,9 +791,12 @@ def test_adjoint_step_covers_every_column(nx, bc, cpl):
         [inputs.gaussian_bumps(nx, ny, 50 + v) for v in range(4)])
     p = params_from(model=1, bc=bc, nx=nx, ny=ny, ld=nx + nx % 2)
     lam = np.random.default_rng(nx).standard_normal(W.shape)
-    P = oparams(p)
+    gh = _dirichlet_case(1, 1, 1, 0)[3] if bc == _lib.FVM_DIRICHLET else None
+    P = oparams(p, gh)
     _, _, dt = orc.cfl(P, W)
     s = Solver(p)
+    if gh is not None:
+        s.set_boundary_states(gh)
     s.set_adjoint_tiling(0, 0, cpl)
     got = s.adjoint_step(W, dt, lam)
     torch.cuda.synchronize()
@@ -872,6 +884,26 @@ def test_fvrun_gradient_matches_oracle_and_fd():
         eps = 1e-6
         fd = (L(W0 + eps * v) - L(W0 - eps * v)) / (2 * eps)
         assert abs(float(np.sum(g * v)) - fd) <= 1e-6 * max(1.0, abs(fd))
+
+
+def test_fvrun_gradient_with_dirichlet_boundaries():
+    """The differentiable run with prescribed ghost states: the gradient the
+    checkpointed GPU adjoint returns equals the oracle's adjoint run."""
+    n = 40
+    W0, _, _, ghost = _dirichlet_case(1, n, n, 9)
+    tgt = torch.tensor(inputs.adjoint_target_density(n, n, 9), device="cuda")
+    p = params_from(model=1, bc=_lib.FVM_DIRICHLET, nx=n, ny=n)
+    s = Solver(p)
+    s.set_boundary_states(ghost)
+    X = torch.tensor(W0, device="cuda", requires_grad=True)
+    Y = fvrun(X, s, 20, 4)
+    (0.5 * ((Y[0] - tgt) ** 2).sum()).backward()
+    g = X.grad.cpu().numpy()
+    P = oparams(p, ghost)
+    WN, odts = orc.run(P, W0, 20)
+    lamN = np.zeros_like(W0)
+    lamN[0] = WN[0] - inputs.adjoint_target_density(n, n, 9)
+    assert rel_linf(g, orc.adjoint_run(P, W0, odts, lamN)) <= 1e-10
 
 
 # ---------------------------------------------------------------------------
