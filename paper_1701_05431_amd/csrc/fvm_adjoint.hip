@@ -5,6 +5,7 @@
 #include "fvm_adjoint.hpp"
 #include "fvm_internal.hpp"
 #include "fvm_models.hpp"
+#include "fvm_step.hpp"
 
 namespace fvm {
 
@@ -13,7 +14,9 @@ __global__ __launch_bounds__(WPB * kWave) void adjoint_kernel(AdjointArgs a) {
   const M m(a.m);
   const double dt = a.dts ? a.dts[a.k] : a.dt_arg;
   const double mux = dt / a.g.dx, muy = dt / a.g.dy;
-  const int tile = blockIdx.x;
+  // each XCD walks a contiguous range of tiles, as in the forward step, so
+  // vertically adjacent tiles share its L2 for their halo rows
+  const int tile = xcd_tile(blockIdx.x, a.t.ntiles);
   const int tx = tile % a.t.tiles_x, ty = tile / a.t.tiles_x;
   const int wave = wave_index();
   const int j0 = ty * a.t.rows;
