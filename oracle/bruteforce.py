@@ -146,8 +146,10 @@ def cfl_dt(model, W, cfl, *, lx=1.0, ly=1.0, gamma=1.4, a=(0.0, 0.0)):
 # --------------------------------------------------------------------------
 
 def torch_step(model, W, dt, *, bc=PERIODIC, lx=1.0, ly=1.0, gamma=1.4,
-               a=(0.0, 0.0)):
-    """Differentiable whole-grid transport step (advection or Euler)."""
+               a=(0.0, 0.0), ug=None, K=1.0, theta=0.1, s_eps=0.01):
+    """Differentiable whole-grid step: the transport (advection, Euler or the
+    spray's kinetic upwind flux) and, for the spray, the lognormal-closure
+    source at W* (ug: the gas velocity, 2 planes)."""
     import torch
 
     def nb(X, axis):
@@ -171,11 +173,21 @@ def torch_step(model, W, dt, *, bc=PERIODIC, lx=1.0, ly=1.0, gamma=1.4,
         f2 = rv * un + (p if d == 1 else 0.0)
         return torch.stack([r * un, f1, f2, (e + p) * un]), torch.abs(un) + c
 
+    def vel(X, d):
+        ok = X[2] > TINY
+        return torch.where(ok, X[4 + d] / torch.where(ok, X[2], torch.ones_like(X[2])),
+                           torch.zeros_like(X[2]))
+
     def nflux(XL, XR, d):
         if model == ADV:
             ap = a[d] if a[d] > 0.0 else 0.0
             am = a[d] if a[d] < 0.0 else 0.0
             return ap * XL + am * XR
+        if model == SPRAY:
+            ul, ur = vel(XL, d), vel(XR, d)
+            up = torch.where(ul > 0.0, ul, torch.zeros_like(ul))
+            um = torch.where(ur < 0.0, ur, torch.zeros_like(ur))
+            return XL * up + XR * um
         FL, sl = pflux(XL, d)
         FR, sr = pflux(XR, d)
         sigma = torch.where(sl >= sr, sl, sr)
@@ -187,4 +199,25 @@ def torch_step(model, W, dt, *, bc=PERIODIC, lx=1.0, ly=1.0, gamma=1.4,
     Wl, Wr = nb(W, 2)
     Ws, Wn = nb(W, 1)
     t = mux * (nflux(W, Wr, 0) - nflux(Wl, W, 0)) + muy * (nflux(W, Wn, 1) - nflux(Ws, W, 1))
-    return W - t
+    Wstar = W - t
+    if model != SPRAY:
+        return Wstar
+    ug = torch.as_tensor(ug, dtype=W.dtype)
+    m0, m1, m2 = Wstar[0], Wstar[1], Wstar[2]
+    ok = (m0 > TINY) & (m1 > TINY) & (m2 > TINY)
+    one = torch.ones_like(m0)
+    m0s, m1s, m2s = torch.where(ok, m0, one), torch.where(ok, m1, one), torch.where(ok, m2, one)
+    ux, uy = Wstar[4] / m2s, Wstar[5] / m2s
+    L1 = torch.log(m1s / m0s)
+    L2 = torch.log(m2s / m0s)
+    s2 = 4.0 * (L2 - 2.0 * L1)
+    s2 = torch.where(s2 < 1e-8, torch.full_like(s2, 1e-8), s2)
+    mu = 2.0 * L1 - s2 / 4.0
+    mmh = m0s * torch.exp(-mu / 2.0 + s2 / 8.0)
+    z = math.log(s_eps) - mu
+    n0 = m0s / (s_eps * torch.sqrt(2.0 * math.pi * s2)) * torch.exp(-(z * z) / (2.0 * s2))
+    it = 0.0 if math.isinf(theta) else 1.0 / theta
+    S = torch.stack([-K * n0, -(K / 2.0) * mmh, -K * m0s, -(1.5 * K) * m1s,
+                     -K * m0s * ux + m0s * (ug[0] - ux) * it,
+                     -K * m0s * uy + m0s * (ug[1] - uy) * it])
+    return Wstar + dt * torch.where(ok[None], S, torch.zeros_like(S))

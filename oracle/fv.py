@@ -94,8 +94,8 @@ def lib():
             "orc_run": (C.c_int, [P, _D, _D, C.c_int, _D]),
             "orc_run_dts": (C.c_int, [P, _D, _D, C.c_int, _D]),
             "orc_step_fixed": (C.c_int, [P, _D, _D, C.c_double]),
-            "orc_adjoint_step": (C.c_int, [P, _D, C.c_double, _D, _D]),
-            "orc_adjoint_run": (C.c_int, [P, _D, C.c_int, _D, _D]),
+            "orc_adjoint_step": (C.c_int, [P, _D, _D, C.c_double, _D, _D]),
+            "orc_adjoint_run": (C.c_int, [P, _D, _D, C.c_int, _D, _D]),
         }
         for name, (res, args) in sig.items():
             f = getattr(L, name)
@@ -227,22 +227,27 @@ def step_fixed(P: Params, W, dt: float, ug=None):
     return int(rc), W
 
 
-def adjoint_step(P: Params, W, dt: float, lam) -> np.ndarray:
+def adjoint_step(P: Params, W, dt: float, lam, ug=None) -> np.ndarray:
+    """(dW^{n+1}/dW^n)^T lam at state W (ug: the spray's gas velocity)."""
     W = _check_state(P, W)
     lam = _check_state(P, lam)
     out = np.empty_like(lam)
-    rc = lib().orc_adjoint_step(C.byref(P), _ptr(W), float(dt), _ptr(lam), _ptr(out))
+    ugp = None if ug is None else _f64(ug)
+    rc = lib().orc_adjoint_step(C.byref(P), _ptr(W), _ptr(ugp), float(dt), _ptr(lam),
+                                _ptr(out))
     if rc:
         raise OracleError(rc, "adjoint_step")
     return out
 
 
-def adjoint_run(P: Params, W0, dts, lamN) -> np.ndarray:
-    """dL/dW^0 from dL/dW^N for len(dts) transport steps with frozen dts."""
+def adjoint_run(P: Params, W0, dts, lamN, ug=None) -> np.ndarray:
+    """dL/dW^0 from dL/dW^N for len(dts) steps with frozen dts."""
     W0 = _check_state(P, W0)
     lam = _check_state(P, lamN).copy()
     dts = _f64(dts).reshape(-1)
-    rc = lib().orc_adjoint_run(C.byref(P), _ptr(W0), int(dts.size), _ptr(dts), _ptr(lam))
+    ugp = None if ug is None else _f64(ug)
+    rc = lib().orc_adjoint_run(C.byref(P), _ptr(W0), _ptr(ugp), int(dts.size), _ptr(dts),
+                               _ptr(lam))
     if rc:
         raise OracleError(rc, "adjoint_run")
     return lam

@@ -56,9 +56,12 @@
  *      subdomain at the domain's edge): the ghost cell holds a prescribed
  *      state, one constant state per side of the domain.
  *   R8 the adjoint (not in the paper) is the exact transpose of the
- *      implemented transport step with dt held fixed; max() follows the left
- *      argument on ties and d|x|/dx = +1 at x = 0; a Dirichlet ghost state
- *      is a constant, so nothing flows back into it.
+ *      implemented step with dt held fixed: the transport, and for the spray
+ *      (lognormal closure only) the source at W* as well; max() follows the
+ *      left argument on ties, d|x|/dx = +1 at x = 0, a clipped lognormal
+ *      width is a constant, and every other branch is differentiated on the
+ *      side it takes; a Dirichlet ghost state is a constant, so nothing
+ *      flows back into it.
  */
 #include <math.h>
 #include <stdlib.h>
@@ -1002,15 +1005,50 @@ static void euler_speed_gradient(const orc_params* P, const double* w, int d,
   }
 }
 
+/* Jacobians of the kinetic upwind flux (reading R5) with respect to its left
+ * and right states: F = W_L up + W_R um with up = max(u_L.n, 0),
+ * um = min(u_R.n, 0) and u.n = W[4+d] / W[2]. The branch taken decides the
+ * derivative (at u.n = 0 both are the zero branch); below the vacuum
+ * threshold u.n is the constant 0. */
+static void spray_flux_jacobians(const double* wl, const double* wr, int d,
+                                 double JL[ORC_MAXV][ORC_MAXV],
+                                 double JR[ORC_MAXV][ORC_MAXV])
+{
+  double ul = 0.0, ur = 0.0, gl[6] = {0}, gr[6] = {0};
+  if (wl[2] > ORC_TINY) {
+    ul = wl[4 + d] / wl[2];
+    gl[2] = -ul / wl[2];
+    gl[4 + d] = 1.0 / wl[2];
+  }
+  if (wr[2] > ORC_TINY) {
+    ur = wr[4 + d] / wr[2];
+    gr[2] = -ur / wr[2];
+    gr[4 + d] = 1.0 / wr[2];
+  }
+  int pos = ul > 0.0, neg = ur < 0.0;
+  double up = pos ? ul : 0.0, um = neg ? ur : 0.0;
+  for (int k = 0; k < 6; ++k)
+    for (int l = 0; l < 6; ++l) {
+      double id = (k == l) ? 1.0 : 0.0;
+      JL[k][l] = id * up + (pos ? wl[k] * gl[l] : 0.0);
+      JR[k][l] = id * um + (neg ? wr[k] * gr[l] : 0.0);
+    }
+}
+
 /* Jacobians of the numerical flux with respect to its left and right states. */
 static void num_flux_jacobians(const orc_params* P, const double* wl,
-                               const double* wr, int d, double JL[4][4],
-                               double JR[4][4])
+                               const double* wr, int d,
+                               double JL[ORC_MAXV][ORC_MAXV],
+                               double JR[ORC_MAXV][ORC_MAXV])
 {
   if (P->model == ORC_ADV) {
     double a = (d == 0) ? P->ax : P->ay;
     JL[0][0] = a > 0.0 ? a : 0.0;
     JR[0][0] = a < 0.0 ? a : 0.0;
+    return;
+  }
+  if (P->model == ORC_SPRAY) {
+    spray_flux_jacobians(wl, wr, d, JL, JR);
     return;
   }
   double AL[4][4], AR[4][4], gl[4], gr[4], f[4], sl, sr;
@@ -1031,25 +1069,138 @@ static void num_flux_jacobians(const orc_params* P, const double* wl,
     }
 }
 
-/* One adjoint step: lam_out = (dW^{n+1}/dW^n)^T lam_in for the transport
- * step at state W with time step dt. Scatter over faces with explicit
- * Jacobians. A ghost cell has no update equation (its multiplier is zero);
- * on a transmissive boundary it is a copy of the boundary cell, so its
+/* J = dS/dW of the spray source (Sec. 6.1 eq. Essadki) with the lognormal
+ * closure (reading R6), differentiated by hand: with
+ * L1 = ln(m_{1/2}/m_0), L2 = ln(m_{2/2}/m_0), s^2 = 4 (L2 - 2 L1) (a constant
+ * where it is clipped at 1e-8), mu = 2 L1 - s^2/4,
+ *   d ln m_{-1/2} = dm_0/m_0 - dmu/2 + ds^2/8,
+ *   d ln n(S_eps) = dm_0/m_0 - ds^2/(2 s^2) + z dmu/s^2 + z^2 ds^2/(2 s^4),
+ * z = ln S_eps - mu; the momentum rows follow from u = q/m_{2/2}. Zero where
+ * the source is switched off (a moment at or below the vacuum threshold). */
+static void spray_source_jacobian(const orc_params* P, const double* w,
+                                  const double* ug, double J[6][6])
+{
+  for (int k = 0; k < 6; ++k)
+    for (int l = 0; l < 6; ++l) J[k][l] = 0.0;
+  double m0 = w[0], m1 = w[1], m2 = w[2];
+  if (!(m0 > ORC_TINY) || !(m1 > ORC_TINY) || !(m2 > ORC_TINY)) return;
+  double K = P->K, it = 1.0 / P->theta;
+  double u[2] = {w[4] / m2, w[5] / m2};
+  for (int d = 0; d < 2; ++d) {
+    /* S_{4+d} = m_0 (-K u + (ug - u)/theta) */
+    J[4 + d][0] = -K * u[d] + (ug[d] - u[d]) * it;
+    J[4 + d][2] = m0 * (K + it) * u[d] / m2;
+    J[4 + d][4 + d] = -m0 * (K + it) / m2;
+  }
+  J[2][0] = -K;
+  J[3][1] = -1.5 * K;
+  if (K == 0.0) return;
+  double mmh, n0;
+  lognormal_closure(P, w, &mmh, &n0);
+  double L1 = log(m1 / m0), L2 = log(m2 / m0);
+  double s2 = 4.0 * (L2 - 2.0 * L1);
+  int clipped = s2 < 1e-8;
+  if (clipped) s2 = 1e-8;
+  double mu = 2.0 * L1 - s2 / 4.0;
+  double z = log(P->s_eps) - mu;
+  double dL1[3] = {-1.0 / m0, 1.0 / m1, 0.0};
+  double dL2[3] = {-1.0 / m0, 0.0, 1.0 / m2};
+  for (int l = 0; l < 3; ++l) {
+    double ds2 = clipped ? 0.0 : 4.0 * (dL2[l] - 2.0 * dL1[l]);
+    double dmu = 2.0 * dL1[l] - ds2 / 4.0;
+    double dm0 = (l == 0) ? 1.0 / m0 : 0.0;
+    double dlmmh = dm0 - dmu / 2.0 + ds2 / 8.0;
+    double dln0 = dm0 - ds2 / (2.0 * s2) + z * dmu / s2 + z * z * ds2 / (2.0 * s2 * s2);
+    J[1][l] = -(K / 2.0) * mmh * dlmmh;
+    J[0][l] = -K * n0 * dln0;
+  }
+}
+
+/* W* = W - [mux (F_E - F_W) + muy (G_N - G_S)] over the whole grid (the
+ * transport half of the step, eq. VF_scheme with reading R1), neighbours
+ * by the boundary rule. */
+static void transport_star(const orc_params* P, const double* W, double dt,
+                           double* Ws)
+{
+  int nv = orc_nvar(P->model), nx = P->nx, ny = P->ny;
+  size_t plane = (size_t)nx * ny;
+  double mux = dt / (P->lx / nx), muy = dt / (P->ly / ny);
+  for (int j = 0; j < ny; ++j)
+    for (int i = 0; i < nx; ++i) {
+      double c[ORC_MAXV], nb[4][ORC_MAXV];
+      int di[4] = {-1, 1, 0, 0}, dj[4] = {0, 0, -1, 1};
+      for (int v = 0; v < nv; ++v) c[v] = W[v * plane + (size_t)j * nx + i];
+      for (int s = 0; s < 4; ++s) {
+        int ii = i + di[s], jj = j + dj[s];
+        int out = ii < 0 || ii >= nx || jj < 0 || jj >= ny;
+        if (P->bc == ORC_PERIODIC) {
+          ii = (ii + nx) % nx;
+          jj = (jj + ny) % ny;
+        } else if (out && P->bc == ORC_TRANSMISSIVE) {
+          ii = i;
+          jj = j;
+        }
+        for (int v = 0; v < nv; ++v)
+          nb[s][v] = (out && P->bc == ORC_DIRICHLET)
+                         ? P->ghost[s][v]
+                         : W[v * plane + (size_t)jj * nx + ii];
+      }
+      double FE[ORC_MAXV], FW[ORC_MAXV], GN[ORC_MAXV], GS[ORC_MAXV];
+      num_flux(P, c, nb[ORC_EAST], 0, FE);
+      num_flux(P, nb[ORC_WEST], c, 0, FW);
+      num_flux(P, c, nb[ORC_NORTH], 1, GN);
+      num_flux(P, nb[ORC_SOUTH], c, 1, GS);
+      for (int v = 0; v < nv; ++v) {
+        double t = mux * (FE[v] - FW[v]) + muy * (GN[v] - GS[v]);
+        Ws[v * plane + (size_t)j * nx + i] = c[v] - t;
+      }
+    }
+}
+
+/* One adjoint step: lam_out = (dW^{n+1}/dW^n)^T lam_in at state W with time
+ * step dt. For the spray, W^{n+1} = W* + dt S(W*) with W* the transport
+ * step, so lam_in is first taken back through the source,
+ * mu = lam_in + dt J_S(W*)^T lam_in, cell by cell, and then through the
+ * transport. The transport part scatters over faces with explicit Jacobians.
+ * A ghost cell has no update equation (its multiplier is zero); on a
+ * transmissive boundary it is a copy of the boundary cell, so its
  * sensitivity goes to that cell; on a Dirichlet boundary it holds the
  * prescribed state, which does not depend on W, so its sensitivity is
- * dropped. */
-int orc_adjoint_step(const orc_params* P, const double* W, double dt,
-                     const double* lam_in, double* lam_out)
+ * dropped. ug: the spray's gas velocity (2 planes), unused otherwise. */
+int orc_adjoint_step(const orc_params* P, const double* W, const double* ug,
+                     double dt, const double* lam_in, double* lam_out)
 {
   int rc = orc_validate(P);
   if (rc) return rc;
-  if (P->model == ORC_SPRAY) return ORC_EUNSUPPORTED;
+  int spray = P->model == ORC_SPRAY;
+  if (spray && P->closure != 0) return ORC_EUNSUPPORTED;
+  if (spray && !ug) return ORC_EINVAL;
   int nv = orc_nvar(P->model), nx = P->nx, ny = P->ny;
   size_t plane = (size_t)nx * ny;
   int dir = P->bc == ORC_DIRICHLET;
   double mu[2] = {dt / (P->lx / nx), dt / (P->ly / ny)};
   int per = P->bc == ORC_PERIODIC;
-  memcpy(lam_out, lam_in, sizeof(double) * nv * plane);
+  double* lam_src = NULL;
+  const double* lm = lam_in; /* the multiplier of W* */
+  if (spray) {
+    double* Ws = (double*)malloc(sizeof(double) * nv * plane);
+    lam_src = (double*)malloc(sizeof(double) * nv * plane);
+    if (!Ws || !lam_src) { free(Ws); free(lam_src); return ORC_EINVAL; }
+    transport_star(P, W, dt, Ws);
+    for (size_t c = 0; c < plane; ++c) {
+      double w[6], J[6][6], u2[2] = {ug[c], ug[plane + c]};
+      for (int v = 0; v < 6; ++v) w[v] = Ws[v * plane + c];
+      spray_source_jacobian(P, w, u2, J);
+      for (int l = 0; l < 6; ++l) {
+        double s = 0.0;
+        for (int k = 0; k < 6; ++k) s = s + J[k][l] * lam_in[k * plane + c];
+        lam_src[l * plane + c] = lam_in[l * plane + c] + dt * s;
+      }
+    }
+    free(Ws);
+    lm = lam_src;
+  }
+  memcpy(lam_out, lm, sizeof(double) * nv * plane);
   for (int d = 0; d < 2; ++d) {
     int n_along = d == 0 ? nx : ny, n_across = d == 0 ? ny : nx;
     int first = per ? 0 : -1;
@@ -1066,7 +1217,8 @@ int orc_adjoint_step(const orc_params* P, const double* W, double dt,
         }
         size_t cl = d == 0 ? (size_t)a * nx + il : (size_t)il * nx + a;
         size_t cr = d == 0 ? (size_t)a * nx + ir : (size_t)ir * nx + a;
-        double wl[4], wr[4], JL[4][4], JR[4][4], dl[4];
+        double wl[ORC_MAXV], wr[ORC_MAXV], dl[ORC_MAXV];
+        double JL[ORC_MAXV][ORC_MAXV], JR[ORC_MAXV][ORC_MAXV];
         for (int v = 0; v < nv; ++v) {
           wl[v] = W[v * plane + cl];
           wr[v] = W[v * plane + cr];
@@ -1076,8 +1228,8 @@ int orc_adjoint_step(const orc_params* P, const double* W, double dt,
         }
         num_flux_jacobians(P, wl, wr, d, JL, JR);
         for (int v = 0; v < nv; ++v) {
-          double lr = vr ? lam_in[v * plane + cr] : 0.0;
-          double ll = vl ? lam_in[v * plane + cl] : 0.0;
+          double lr = vr ? lm[v * plane + cr] : 0.0;
+          double ll = vl ? lm[v * plane + cl] : 0.0;
           dl[v] = lr - ll;
         }
         for (int l = 0; l < nv; ++l) {
@@ -1091,6 +1243,7 @@ int orc_adjoint_step(const orc_params* P, const double* W, double dt,
         }
       }
   }
+  free(lam_src);
   return ORC_OK;
 }
 
@@ -1098,12 +1251,13 @@ int orc_adjoint_step(const orc_params* P, const double* W, double dt,
  * for nsteps transport steps with the given dts (held fixed): the forward
  * states are all stored, then the adjoint steps run in reverse.
  * lam: in = dL/dW^N, out = dL/dW^0. */
-int orc_adjoint_run(const orc_params* P, const double* W0, int nsteps,
-                    const double* dts, double* lam)
+int orc_adjoint_run(const orc_params* P, const double* W0, const double* ug,
+                    int nsteps, const double* dts, double* lam)
 {
   int rc = orc_validate(P);
   if (rc) return rc;
-  if (P->model == ORC_SPRAY) return ORC_EUNSUPPORTED;
+  if (P->model == ORC_SPRAY && P->closure != 0) return ORC_EUNSUPPORTED;
+  if (P->model == ORC_SPRAY && !ug) return ORC_EINVAL;
   int nv = orc_nvar(P->model);
   size_t n = (size_t)nv * P->nx * P->ny;
   double* states = (double*)malloc(sizeof(double) * n * (nsteps > 0 ? nsteps : 1));
@@ -1112,11 +1266,11 @@ int orc_adjoint_run(const orc_params* P, const double* W0, int nsteps,
   memcpy(states, W0, sizeof(double) * n);
   for (int k = 1; k < nsteps; ++k) {
     memcpy(states + (size_t)k * n, states + (size_t)(k - 1) * n, sizeof(double) * n);
-    rc = orc_run_dts(P, states + (size_t)k * n, NULL, 1, dts + (k - 1));
+    rc = orc_run_dts(P, states + (size_t)k * n, ug, 1, dts + (k - 1));
     if (rc) break;
   }
   for (int k = nsteps - 1; k >= 0 && rc == ORC_OK; --k) {
-    rc = orc_adjoint_step(P, states + (size_t)k * n, dts[k], lam, tmp);
+    rc = orc_adjoint_step(P, states + (size_t)k * n, ug, dts[k], lam, tmp);
     memcpy(lam, tmp, sizeof(double) * n);
   }
   free(states);

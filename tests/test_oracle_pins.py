@@ -710,6 +710,102 @@ def test_euler_adjoint_matches_autograd(orc, bc):
     assert _rel_linf(g, X.grad.numpy()) < 1e-12
 
 
+def _spray_adjoint_case(n, seed):
+    """A spray state whose velocity differs from the gas velocity (so the drag
+    acts) and whose moments are not exactly lognormal."""
+    W, ug = inputs.spray_state(n, n, seed)
+    rng = np.random.default_rng(seed + 100)
+    W = W.copy()
+    W[:4] *= 1.0 + 0.02 * rng.standard_normal((4, n, n))
+    W[4:] += 0.1 * W[2] * rng.standard_normal((2, n, n))
+    return W, ug
+
+
+def _spray_ghosts():
+    g = []
+    for k, (u, v) in enumerate([(0.3, -0.2), (-0.4, 0.1), (0.2, 0.35), (-0.1, -0.3)]):
+        m = inputs.lognormal_moments(1.0 + 0.1 * k, math.log(0.2), 0.3)
+        g.append([m[0], m[1], m[2], m[3], m[2] * u, m[2] * v])
+    return np.array(g)
+
+
+@pytest.mark.parametrize("bc", [0, 1])
+def test_spray_adjoint_matches_autograd(orc, bc):
+    """The spray adjoint (kinetic upwind transport, then the lognormal-closure
+    source at W*) equals torch.autograd through a whole-grid torch version of
+    the step, over three steps with frozen dts."""
+    import torch
+    n = 10
+    W0, ug = _spray_adjoint_case(n, 11)
+    P = orc.params(orc.SPRAY, n, n, bc=bc, npx=2, npy=2, cfl=0.9)
+    _, dts = orc.run(P, W0, 3, ug)
+    lam = np.random.default_rng(2).standard_normal(W0.shape)
+    g = orc.adjoint_run(P, W0, dts, lam, ug)
+    X = torch.tensor(W0, requires_grad=True)
+    Y = X
+    for dt in dts:
+        Y = bf.torch_step(bf.SPRAY, Y, float(dt), bc=bc, ug=ug)
+    assert _rel_linf(Y.detach().numpy(), orc.run_dts(P, W0, dts, ug)) < 1e-13
+    (Y * torch.tensor(lam)).sum().backward()
+    assert _rel_linf(g, X.grad.numpy()) < 1e-12
+
+
+@pytest.mark.parametrize("bc", [1, 2])
+def test_spray_adjoint_central_differences(orc, bc):
+    """The spray adjoint against central differences of the oracle's own
+    forward steps (dts held fixed), transmissive and Dirichlet ghosts, with
+    drag and without (theta = inf)."""
+    n = 8
+    W0, ug = _spray_adjoint_case(n, 4)
+    for theta in (0.1, math.inf):
+        P = orc.params(orc.SPRAY, n, n, bc=bc, cfl=0.3, K=0.5, theta=theta,
+                       ghost=_spray_ghosts() if bc == 2 else None)
+        _, dts = orc.run(P, W0, 4, ug)
+        tgt = W0[0] * 0.9
+        def loss(W):
+            WN = orc.run_dts(P, W, dts, ug)
+            return 0.5 * np.sum((WN[0] - tgt) ** 2) + np.sum(WN[4] * WN[1])
+        WN = orc.run_dts(P, W0, dts, ug)
+        lamN = np.zeros_like(W0)
+        lamN[0] = WN[0] - tgt
+        lamN[4] = WN[1]
+        lamN[1] = WN[4]
+        g = orc.adjoint_run(P, W0, dts, lamN, ug)
+        rng = np.random.default_rng(8)
+        for _ in range(6):
+            v = rng.standard_normal(W0.shape) * np.abs(W0)
+            eps = 1e-6
+            fd = (loss(W0 + eps * v) - loss(W0 - eps * v)) / (2 * eps)
+            assert abs(np.sum(g * v) - fd) <= 1e-6 * max(1.0, abs(fd))
+
+
+def test_spray_adjoint_source_jacobian_by_columns(orc):
+    """On a 1 x 1 periodic grid the transport cancels (each face sees the same
+    state on both sides), so one step is W + dt S(W) and its adjoint is
+    (I + dt J_S)^T: compared column by column with central differences of the
+    oracle's step, including a state whose lognormal width is clipped."""
+    ug = np.array([0.3, -0.2]).reshape(2, 1, 1)
+    P = orc.params(orc.SPRAY, 1, 1, bc=orc.PERIODIC)
+    m = inputs.lognormal_moments(1.2, math.log(0.2), 0.25)
+    states = [[m[0], m[1], m[2], m[3], 0.1 * m[2], 0.4 * m[2]],
+              [1.0, 0.55, 0.25, 0.125, 0.05, -0.02]]  # m1^2 > m0 m2: width clipped
+    dt = 0.05
+    for w in states:
+        W = np.array(w, dtype=np.float64).reshape(6, 1, 1)
+        A = np.zeros((6, 6))
+        for k in range(6):
+            h = 1e-6 * max(1.0, abs(w[k]))
+            e = np.zeros((6, 1, 1))
+            e[k] = h
+            A[:, k] = ((orc.run_dts(P, W + e, [dt], ug) - orc.run_dts(P, W - e, [dt], ug))
+                       / (2 * h)).reshape(-1)
+        for k in range(6):
+            lam = np.zeros((6, 1, 1))
+            lam[k] = 1.0
+            row = orc.adjoint_step(P, W, dt, lam, ug).reshape(-1)
+            assert np.max(np.abs(row - A[k])) <= 1e-7 * max(1.0, np.max(np.abs(A[k])))
+
+
 def test_euler_adjoint_central_differences(orc):
     n = 8
     W0 = inputs.riemann_state(n, n, 2)
