@@ -337,6 +337,63 @@ def bench_adjoint_step_4096(reps, layout="rows", tuning=TUNING):
             "gcell_updates_per_s": cells / sec / 1e9}
 
 
+def bench_spray_adjoint(reps, steps=20, layout="rows", tuning=TUNING):
+    """The spray's discrete adjoint on the 2048^2 spray workload (lognormal
+    closure): one adjoint step timed per launch (reads W^n, lam^{n+1} and the
+    gas velocity, writes lam^n: 160 algorithmic bytes per cell), and a
+    checkpointed differentiable run of `steps` steps against its forward."""
+    import ctypes as C
+    import torch
+    from paper_1701_05431_amd import inputs
+    from paper_1701_05431_amd._lib import check, lib
+    from paper_1701_05431_amd.solver import Solver, params_from
+    pre = inputs.SPRAY_2048
+    W0, ug = inputs.spray_state(pre.nx, pre.ny, 0)
+    s = Solver(params_from(pre, layout=LAYOUTS[layout]), ug=ug)
+    W0 = torch.from_numpy(W0)
+    W = s._as_state(W0)
+    g = torch.Generator().manual_seed(0)
+    la = s._as_state(torch.randn((s.nv, pre.ny, pre.nx), dtype=torch.float64, generator=g))
+    lb = torch.empty_like(la)
+    s.set_state(W0)
+    s.autotune(tuning)
+    dt = s.cfl_dt()[0]
+    L = lib()
+    ptr = lambda t: C.c_void_p(t.data_ptr())
+    s._bind_stream()
+
+    def two():
+        check(L.fvm_adjoint_step(s.h, ptr(W), dt, ptr(la), ptr(lb)), "fvm_adjoint_step")
+        check(L.fvm_adjoint_step(s.h, ptr(W), dt, ptr(lb), ptr(la)), "fvm_adjoint_step")
+
+    two()
+    sec = timed(two, reps) / 2
+    assert bool(torch.isfinite(la).all())
+    cells = pre.nx * pre.ny
+    gbs = 160.0 * cells / sec / 1e9
+    every = 5
+    holder = {}
+
+    def fwd():
+        s.set_state(W0)
+        holder["ck"], holder["dts"] = s.run_ckpt(steps, every)
+
+    def bwd():
+        lam = s.current()[:, :, :pre.nx].clone()
+        holder["g"] = s.adjoint(holder["ck"], every, holder["dts"], lam)
+
+    fwd()
+    bwd()
+    tf = min(timed(fwd) for _ in range(3))
+    fwd()
+    tb = min(timed(bwd) for _ in range(3))
+    return {"workload": "spray_adjoint_2048x2048", "us_per_step": sec * 1e6,
+            "bytes_per_cell": 160, "hbm_gbs": gbs, "hbm_frac": gbs / HBM_PEAK_GBS,
+            "gcell_updates_per_s": cells / sec / 1e9, "run_steps": steps,
+            "ckpt_every": every, "forward_ms": tf * 1e3, "backward_ms": tb * 1e3,
+            "adjoint_over_forward": tb / tf, "status": s.sync()}
+
+
 def bench_slab(steps, warmup, layout="rows", tuning=TUNING):
     """One GPU's share of the 4096^2 Euler grid cut into 8 slabs of 512 rows:
     the slab steps with its south and north halo rows read from neighbour
@@ -448,7 +505,8 @@ def main():
     ap.add_argument("--wpb", type=int, default=0)
     ap.add_argument("--only-euler", action="store_true")
     ap.add_argument("--only", choices=["spray", "batch", "adjoint", "adjoint4096", "slab",
-                                       "advection", "output", "spray_maxent"],
+                                       "advection", "output", "spray_maxent",
+                                       "spray_adjoint"],
                     help="run just this secondary workload (for profiling) and print its record")
     ap.add_argument("--no-autotune", action="store_true")
     ap.add_argument("--tuning", default=TUNING,
@@ -480,7 +538,9 @@ def main():
                "output": lambda: bench_output(args.steps, args.warmup, args.layout,
                                               args.tuning),
                "spray_maxent": lambda: bench_spray_maxent(min(args.steps, 20), 2, args.layout,
-                                                          args.tuning)}[args.only]
+                                                          args.tuning),
+               "spray_adjoint": lambda: bench_spray_adjoint(20, 20, args.layout,
+                                                            args.tuning)}[args.only]
         print(json.dumps(run()), flush=True)
         return
 
@@ -505,6 +565,8 @@ def main():
         work["adjoint"] = bench_adjoint(3, args.layout, args.tuning)
         log("adjoint step 4096")
         work["adjoint_step_4096"] = bench_adjoint_step_4096(50, args.layout, args.tuning)
+        log("spray adjoint")
+        work["spray_adjoint"] = bench_spray_adjoint(20, 20, args.layout, args.tuning)
         log("slab with halo rows")
         work["slab"] = bench_slab(200, 20, args.layout, args.tuning)
         log("advection")

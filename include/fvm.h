@@ -234,16 +234,21 @@ int fvm_sync(fvm_grid* g);
 int fvm_get_status(fvm_grid* g, int clear);
 
 /* Gradient of a loss of the final state with respect to the initial state,
- * through nsteps transport steps with frozen time steps (advection and Euler,
- * every boundary condition; FVM_EUNSUPPORTED for the spray model and with
- * halo rows). A transmissive ghost is a copy of its boundary cell, so its
- * sensitivity goes to that cell; a Dirichlet ghost is a constant state and
- * takes none. The adjoint of one step is
+ * through nsteps steps with frozen time steps (advection, Euler and the spray
+ * with the lognormal closure, every boundary condition; FVM_EUNSUPPORTED for
+ * the entropy-maximising closure and with halo rows). A transmissive ghost is
+ * a copy of its boundary cell, so its sensitivity goes to that cell; a
+ * Dirichlet ghost is a constant state and takes none. The adjoint of one
+ * transport step is
  *   lam^n = lam^{n+1} + dt/dx [J_L(i+1/2)^T (lam_{i+1} - lam_i)
  *                             + J_R(i-1/2)^T (lam_i - lam_{i-1})] + (same in y)
  * with J_L, J_R the Jacobians of the numerical flux with respect to its left
  * and right states (derived from Sec. 2.2.1; max() follows its left argument
- * on ties). Inputs (all device memory, the grid's ld and layout):
+ * on ties). For the spray the split source of Sec. 2.2.2 comes first:
+ * lam^{n+1} is replaced by lam^{n+1} + dt J_S(W*)^T lam^{n+1}, with J_S the
+ * Jacobian of the source of Sec. 6.1 at the transported state W* (a clipped
+ * lognormal width counts as a constant), before the transport's adjoint.
+ * Inputs (all device memory, the grid's ld and layout):
  *   ckpts[s]   : host array of device pointers, W^{s * ckpt_every}, as
  *                written by fvm_run_ckpt;
  *   dts_dev    : the nsteps forward time steps;
@@ -259,7 +264,9 @@ int fvm_adjoint_run(fvm_grid* g, double* const* ckpts, int ckpt_every,
                     double* lam_tmp, double* seg_buf);
 
 /* One adjoint step at state w with time step dt: lam_out = (dW^{n+1}/dW^n)^T
- * lam_in (device pointers, the grid's ld and layout). Asynchronous. */
+ * lam_in (device pointers, the grid's ld and layout; lam_out must not alias
+ * w or lam_in). The spray's step reads the bound gas velocity. Same model
+ * and boundary restrictions as fvm_adjoint_run. Asynchronous. */
 int fvm_adjoint_step(fvm_grid* g, const double* w, double dt,
                      const double* lam_in, double* lam_out);
 
@@ -274,7 +281,8 @@ int fvm_get_tiling(const fvm_grid* g, int* rows_per_strip, int* waves_per_block)
  * 128-column strips with 16-byte accesses, taken only where the pitch is even
  * and the state and multiplier buffers of a launch are 16-byte aligned, else
  * 1); 0 keeps the current value. fvm_autotune chooses among all of them.
- * Results do not depend on any of them. */
+ * Results do not depend on any of them. The spray's adjoint kernel ignores
+ * them (one cell per thread). */
 int fvm_set_adjoint_tiling(fvm_grid* g, int rows_per_strip, int waves_per_block,
                            int cells_per_lane);
 
@@ -305,7 +313,8 @@ int fvm_autotune(fvm_grid* g, const char* cache_path);
  * fvm_adjoint_step takes them), applies the fastest and caches it like
  * fvm_autotune (its own key). Separate multiplier buffers move the traffic
  * of real adjoint steps, which the in-place dry launches of fvm_autotune
- * only approximate. FVM_EUNSUPPORTED where fvm_adjoint_step is.
+ * only approximate. FVM_EUNSUPPORTED for the spray (its adjoint kernel has a
+ * single shape: one cell per thread) and where fvm_adjoint_step is.
  * Synchronises the stream. */
 int fvm_autotune_adjoint(fvm_grid* g, const double* w, const double* lam_in, double* lam_out,
                          const char* cache_path);

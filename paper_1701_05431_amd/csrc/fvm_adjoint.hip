@@ -1,7 +1,9 @@
-// fvm_adjoint.hip -- the adjoint kernels (one strip per wave, in either lane
-// layout) and their launch; the device code is in fvm_adjoint.hpp.
+// fvm_adjoint.hip -- the adjoint kernels of advection and Euler (one strip
+// per wave, in either lane layout) and the launch of every model's adjoint;
+// the device code is in fvm_adjoint.hpp (the spray's in fvm_adjoint_spray.hpp).
 #include <hip/hip_runtime.h>
 
+#include "../../include/fvm.h"
 #include "fvm_adjoint.hpp"
 #include "fvm_internal.hpp"
 #include "fvm_models.hpp"
@@ -63,7 +65,10 @@ void* adjoint_kernel_ptr(int model, int bc, int wpb, int cpl) {
   return nullptr;
 }
 
-hipError_t launch_adjoint(const AdjointArgs& a, int model, hipStream_t st) {
+hipError_t launch_spray_adjoint(const AdjointArgs& a, const double* ug, hipStream_t st);
+
+hipError_t launch_adjoint(const AdjointArgs& a, int model, const double* ug, hipStream_t st) {
+  if (model == FVM_SPRAY) return launch_spray_adjoint(a, ug, st);
   void* f = adjoint_kernel_ptr(model, a.g.bc, a.t.wpb, a.t.cpl);
   if (!f) return hipErrorInvalidValue;
   AdjointArgs copy = a;

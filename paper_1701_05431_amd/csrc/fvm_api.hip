@@ -25,7 +25,7 @@ hipError_t launch_step(const StepArgs& a, int model, hipStream_t st);
 hipError_t launch_cfl(const CflArgs& a, int model, hipStream_t st);
 hipError_t launch_clear_scratch(GridScratch* s, int n, hipStream_t st);
 hipError_t launch_clear_log_cursor(GridScratch* s, hipStream_t st);
-hipError_t launch_adjoint(const AdjointArgs& a, int model, hipStream_t st);
+hipError_t launch_adjoint(const AdjointArgs& a, int model, const double* ug, hipStream_t st);
 
 GridGeom grid_geometry(const fvm_params& p) {
   GridGeom g{};
@@ -305,6 +305,13 @@ int fvm_destroy(fvm_grid* g) {
 static bool wide_layout_ok(const fvm_grid* g) {
   auto al = [](const void* p) { return (reinterpret_cast<uintptr_t>(p) & 15) == 0; };
   return g->p.ld % 2 == 0 && al(g->w_a) && al(g->w_b) && (!g->ug || al(g->ug));
+}
+
+// The adjoint covers advection, Euler and the spray with the lognormal
+// closure, without halo rows.
+static bool adjoint_supported(const fvm_grid* g) {
+  if (g->halo.s || g->halo.n) return false;
+  return g->p.model != FVM_SPRAY || g->p.closure == FVM_CLOSURE_LOGNORMAL;
 }
 
 // The adjoint's lane layout for one launch: two cells per lane needs an even
@@ -769,9 +776,10 @@ static double time_adjoint_dry(fvm_grid* g, int reps, const double* w, const dou
     return -1.0;
   }
   double us = -1.0;
-  bool ok = launch_adjoint(a, g->p.model, g->stream) == hipSuccess;  // warm-up
+  bool ok = launch_adjoint(a, g->p.model, g->ug, g->stream) == hipSuccess;  // warm-up
   ok = ok && hipEventRecord(e0, g->stream) == hipSuccess;
-  for (int r = 0; r < reps && ok; ++r) ok = launch_adjoint(a, g->p.model, g->stream) == hipSuccess;
+  for (int r = 0; r < reps && ok; ++r)
+    ok = launch_adjoint(a, g->p.model, g->ug, g->stream) == hipSuccess;
   ok = ok && hipEventRecord(e1, g->stream) == hipSuccess && hipEventSynchronize(e1) == hipSuccess;
   float ms = 0.0f;
   if (ok && hipEventElapsedTime(&ms, e0, e1) == hipSuccess) us = 1e3 * ms / reps;
@@ -926,9 +934,9 @@ int fvm_get_tiling(const fvm_grid* g, int* rows, int* wpb) {
 
 int fvm_adjoint_step(fvm_grid* g, const double* w, double dt, const double* lam_in,
                      double* lam_out) {
-  if (!g || !g->bound || !w || !lam_in || !lam_out || lam_in == lam_out) return FVM_EINVAL;
-  if (g->p.model == FVM_SPRAY) return FVM_EUNSUPPORTED;
-  if (g->halo.s || g->halo.n) return FVM_EUNSUPPORTED;
+  if (!g || !g->bound || !w || !lam_in || !lam_out || lam_in == lam_out || w == lam_out)
+    return FVM_EINVAL;
+  if (!adjoint_supported(g)) return FVM_EUNSUPPORTED;
   if (!(dt >= 0.0) || !std::isfinite(dt)) return FVM_EINVAL;
   AdjointArgs a{};
   a.w = w;
@@ -941,7 +949,7 @@ int fvm_adjoint_step(fvm_grid* g, const double* w, double dt, const double* lam_
                        adjoint_cpl(g, a.w, a.lam_in, a.lam_out));
   a.m = g->m;
   std::memcpy(a.ghost, g->ghost, sizeof a.ghost);
-  return dev_err(launch_adjoint(a, g->p.model, g->stream));
+  return dev_err(launch_adjoint(a, g->p.model, g->ug, g->stream));
 }
 
 int fvm_adjoint_run(fvm_grid* g, double* const* ckpts, int ckpt_every, const double* dts_dev,
@@ -950,8 +958,7 @@ int fvm_adjoint_run(fvm_grid* g, double* const* ckpts, int ckpt_every, const dou
       !lam_tmp || lam == lam_tmp)
     return FVM_EINVAL;
   if (ckpt_every > 1 && !seg_buf) return FVM_EINVAL;
-  if (g->p.model == FVM_SPRAY) return FVM_EUNSUPPORTED;
-  if (g->halo.s || g->halo.n) return FVM_EUNSUPPORTED;
+  if (!adjoint_supported(g)) return FVM_EUNSUPPORTED;
   const int nck = (nsteps + ckpt_every - 1) / ckpt_every;
   for (int s = 0; s < nck; ++s)
     if (!ckpts[s]) return FVM_EINVAL;
@@ -985,7 +992,7 @@ int fvm_adjoint_run(fvm_grid* g, double* const* ckpts, int ckpt_every, const dou
                            adjoint_cpl(g, a.w, a.lam_in, a.lam_out));
       a.m = g->m;
       std::memcpy(a.ghost, g->ghost, sizeof a.ghost);
-      int rc = dev_err(launch_adjoint(a, g->p.model, g->stream));
+      int rc = dev_err(launch_adjoint(a, g->p.model, g->ug, g->stream));
       if (rc) return rc;
       std::swap(lin, lout);
     }

@@ -906,6 +906,131 @@ def test_fvrun_gradient_with_dirichlet_boundaries():
     assert rel_linf(g, orc.adjoint_run(P, W0, odts, lamN)) <= 1e-10
 
 
+def _spray_adjoint_case(nx, ny, seed):
+    """A spray state whose velocity differs from the gas velocity (the drag
+    acts) and whose moments are not exactly lognormal."""
+    W, ug = inputs.spray_state(nx, ny, seed)
+    rng = np.random.default_rng(seed + 50)
+    W = W.copy()
+    W[:4] *= 1.0 + 0.02 * rng.standard_normal((4, ny, nx))
+    W[4:] += 0.1 * W[2] * rng.standard_normal((2, ny, nx))
+    return W, ug
+
+
+def _spray_ghosts():
+    g = []
+    for k, (u, v) in enumerate([(0.3, -0.2), (-0.4, 0.1), (0.2, 0.35), (-0.1, -0.3)]):
+        m = inputs.lognormal_moments(1.0 + 0.1 * k, math.log(0.2), 0.3)
+        g.append([m[0], m[1], m[2], m[3], m[2] * u, m[2] * v])
+    return np.array(g)
+
+
+@pytest.mark.parametrize("theta", [0.1, math.inf])
+@pytest.mark.parametrize("bc", [0, 1, 2])
+def test_spray_adjoint_step(bc, theta):
+    """One spray adjoint step (transport and lognormal-closure source) against
+    the oracle; the row-interleaved layout with a padded pitch gives the same
+    multipliers bit for bit."""
+    nx, ny = 133, 70
+    print(f"spray adjoint bc={bc} theta={theta}", flush=True)
+    W, ug = _spray_adjoint_case(nx, ny, 3)
+    gh = _spray_ghosts() if bc == _lib.FVM_DIRICHLET else None
+    p = params_from(model=2, bc=bc, nx=nx, ny=ny, K=0.7, theta=theta, cfl=0.9)
+    lam = np.random.default_rng(9).standard_normal(W.shape)
+    P = oparams(p, gh)
+    _, _, dt = orc.cfl(P, W)
+    s = Solver(p, ug=ug)
+    if gh is not None:
+        s.set_boundary_states(gh)
+    got = s.adjoint_step(W, dt, lam)
+    torch.cuda.synchronize()
+    ref = orc.adjoint_step(P, W, dt, lam, ug)
+    assert rel_linf(got[:, :, :nx].cpu().numpy(), ref) <= TOL
+    p.layout = _lib.FVM_LAYOUT_ROWS
+    p.ld = nx + 3
+    sr = Solver(p, ug=ug)
+    if gh is not None:
+        sr.set_boundary_states(gh)
+    got_rows = sr.adjoint_step(W, dt, lam)
+    torch.cuda.synchronize()
+    assert np.array_equal(got_rows[:, :, :nx].cpu().numpy(), got[:, :, :nx].cpu().numpy())
+
+
+@pytest.mark.parametrize("bc", [0, 1, 2])
+@pytest.mark.parametrize("nx,ny", [(1, 1), (1, 6), (2, 5), (63, 3), (64, 4), (65, 9),
+                                   (129, 7), (300, 2)])
+def test_spray_adjoint_covers_every_cell(nx, ny, bc):
+    """The spray adjoint's 64 x 4 cell tiles cover every cell of ragged grids,
+    periodic wrap onto the cell itself (nx = 1) included."""
+    print(f"spray adjoint cells nx={nx} ny={ny} bc={bc}", flush=True)
+    W, ug = _spray_adjoint_case(nx, ny, nx + ny)
+    gh = _spray_ghosts() if bc == _lib.FVM_DIRICHLET else None
+    p = params_from(model=2, bc=bc, nx=nx, ny=ny, ld=nx + 1, K=0.7, cfl=0.9)
+    lam = np.random.default_rng(nx).standard_normal(W.shape)
+    P = oparams(p, gh)
+    dt = 0.3 / max(nx, ny)
+    s = Solver(p, ug=ug)
+    if gh is not None:
+        s.set_boundary_states(gh)
+    got = s.adjoint_step(W, dt, lam)
+    torch.cuda.synchronize()
+    ref = orc.adjoint_step(P, W, dt, lam, ug)
+    assert rel_linf(got[:, :, :nx].cpu().numpy(), ref) <= TOL
+
+
+@pytest.mark.parametrize("bc", [0, 2])
+def test_fvrun_spray_gradient(bc):
+    """The differentiable spray run: the checkpointed GPU adjoint (forward
+    recomputation with the fused source, then the spray adjoint steps)
+    equals the oracle's adjoint run, and central differences of the oracle's
+    forward steps agree with it."""
+    n = 40
+    W0, ug = _spray_adjoint_case(n, n, 12)
+    gh = _spray_ghosts() if bc == _lib.FVM_DIRICHLET else None
+    p = params_from(model=2, bc=bc, nx=n, ny=n, K=0.5, cfl=0.5)
+    s = Solver(p, ug=ug)
+    if gh is not None:
+        s.set_boundary_states(gh)
+    tgt_np = 0.9 * W0[0]
+    tgt = torch.tensor(tgt_np, device="cuda")
+    X = torch.tensor(W0, device="cuda", requires_grad=True)
+    Y = fvrun(X, s, 12, 4)
+    (0.5 * ((Y[0] - tgt) ** 2).sum()).backward()
+    g = X.grad.cpu().numpy()
+    P = oparams(p, gh)
+    WN, odts = orc.run(P, W0, 12, ug)
+    assert rel_linf(Y.detach().cpu().numpy(), WN) <= 1e-11
+    lamN = np.zeros_like(W0)
+    lamN[0] = WN[0] - tgt_np
+    assert rel_linf(g, orc.adjoint_run(P, W0, odts, lamN, ug)) <= 1e-10
+    def L(W):
+        out = orc.run_dts(P, W, odts, ug)
+        return 0.5 * np.sum((out[0] - tgt_np) ** 2)
+    rng = np.random.default_rng(13)
+    for _ in range(4):
+        v = rng.standard_normal(W0.shape) * np.abs(W0)
+        eps = 1e-6
+        fd = (L(W0 + eps * v) - L(W0 - eps * v)) / (2 * eps)
+        assert abs(float(np.sum(g * v)) - fd) <= 1e-6 * max(1.0, abs(fd))
+
+
+def test_spray_adjoint_2048_full_size_step():
+    """One spray adjoint step on the 2048^2 spray workload's state (lognormal
+    closure, K = 1, theta = 0.1) against the oracle, whole grid."""
+    pre = inputs.SPRAY_2048
+    W, ug = inputs.spray_state(pre.nx, pre.ny, 0)
+    p = params_from(pre)
+    lam = np.random.default_rng(5).standard_normal(W.shape)
+    P = oparams(p)
+    orc.set_threads(16)
+    _, _, dt = orc.cfl(P, W)
+    print("spray adjoint 2048^2", flush=True)
+    got = Solver(p, ug=ug).adjoint_step(W, dt, lam)
+    torch.cuda.synchronize()
+    ref = orc.adjoint_step(P, W, dt, lam, ug)
+    assert rel_linf(got[:, :, :pre.nx].cpu().numpy(), ref) <= TOL
+
+
 # ---------------------------------------------------------------------------
 # the full-size Euler workload in the benchmark's launch configuration
 # ---------------------------------------------------------------------------
