@@ -373,9 +373,10 @@ def bench_spray_adjoint(reps, steps=20, layout="rows", tuning=TUNING):
     gbs = 160.0 * cells / sec / 1e9
     every = 5
     holder = {}
+    W0d = W0.cuda()
 
     def fwd():
-        s.set_state(W0)
+        s.set_state(W0d)
         holder["ck"], holder["dts"] = s.run_ckpt(steps, every)
 
     def bwd():

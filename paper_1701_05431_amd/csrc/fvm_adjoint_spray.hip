@@ -1,6 +1,6 @@
 // fvm_adjoint_spray.hip -- launch of the spray adjoint (the device code and
-// its derivation are in fvm_adjoint_spray.hpp): one thread per cell, rows of
-// 64 cells per wave, four rows per workgroup.
+// its derivation are in fvm_adjoint_spray.hpp): one workgroup per tile of
+// 64 x 8 cells, mu of the tile and its ring in LDS, one barrier.
 #include <hip/hip_runtime.h>
 
 #include "fvm_adjoint_spray.hpp"
@@ -10,18 +10,17 @@ namespace fvm {
 
 namespace {
 
-constexpr int kSaThreads = 256;
-constexpr int kSaX = 64;  // cells of one row per wave
-constexpr int kSaY = kSaThreads / kSaX;
-
-__global__ __launch_bounds__(kSaThreads) void spray_adjoint_kernel(AdjointArgs a,
-                                                                  const double* ug,
-                                                                  int tiles_x) {
+__global__ __launch_bounds__(sadj::kTileThreads) void spray_adjoint_kernel(AdjointArgs a,
+                                                                          const double* ug,
+                                                                          int tiles_x) {
+  __shared__ double mu_s[6 * sadj::kRing];
   const int b = static_cast<int>(blockIdx.x);
-  const int i = (b % tiles_x) * kSaX + static_cast<int>(threadIdx.x) % kSaX;
-  const int j = (b / tiles_x) * kSaY + static_cast<int>(threadIdx.x) / kSaX;
-  if (i >= a.g.nx || j >= a.g.ny) return;
-  sadj::spray_adjoint_cell(a, ug, j, i);
+  const int i0 = (b % tiles_x) * sadj::kTX, j0 = (b / tiles_x) * sadj::kTY;
+  const sadj::SprayAdj s = sadj::make_adj(a, ug);
+  const int tid = static_cast<int>(threadIdx.x);
+  sadj::tile_mu(s, j0, i0, tid, mu_s);
+  __syncthreads();
+  sadj::tile_out(s, j0, i0, tid, mu_s);
 }
 
 }  // namespace
@@ -29,11 +28,11 @@ __global__ __launch_bounds__(kSaThreads) void spray_adjoint_kernel(AdjointArgs a
 hipError_t launch_spray_adjoint(const AdjointArgs& a, const double* ug, hipStream_t st) {
   if (!a.w || !a.lam_in || !a.lam_out || !ug || a.g.nx < 1 || a.g.ny < 1)
     return hipErrorInvalidValue;
-  const long long tx = (a.g.nx + kSaX - 1) / kSaX;
-  const long long ty = (a.g.ny + kSaY - 1) / kSaY;
+  const long long tx = (a.g.nx + sadj::kTX - 1) / sadj::kTX;
+  const long long ty = (a.g.ny + sadj::kTY - 1) / sadj::kTY;
   if (tx * ty > 0x7fffffffLL) return hipErrorInvalidValue;
   hipLaunchKernelGGL(spray_adjoint_kernel, dim3(static_cast<unsigned>(tx * ty)),
-                     dim3(kSaThreads), 0, st, a, ug, static_cast<int>(tx));
+                     dim3(sadj::kTileThreads), 0, st, a, ug, static_cast<int>(tx));
   return hipGetLastError();
 }
 

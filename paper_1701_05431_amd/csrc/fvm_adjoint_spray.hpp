@@ -1,6 +1,7 @@
-// fvm_adjoint_spray.hpp -- device code of the spray adjoint, one cell per
-// thread (fvm_adjoint_spray.hip launches it). Plain per-thread code with no
-// cross-lane operations, so a host build can run it cell by cell.
+// fvm_adjoint_spray.hpp -- device code of the spray adjoint
+// (fvm_adjoint_spray.hip launches it). No cross-lane operations: the two
+// phases of a tile are plain per-thread code around one barrier, so a host
+// build can run them thread by thread.
 //
 // The discrete adjoint of one spray step (Sec. 6.1 eq. Essadki with the
 // splitting of Sec. 2.2.2 eq. SourceTerm), with the lognormal closure of the
@@ -15,8 +16,8 @@
 //   lam^n_c = mu_c + mux [J_L(c, E)^T (mu_E - mu_c) + J_R(W, c)^T (mu_c - mu_W)]
 //                  + muy [same with N and S].
 // mu of a neighbour needs that neighbour's W*, so one cell's adjoint reads
-// the state two cells away. One thread owns one cell and recomputes W* and
-// mu for itself and its four neighbours. Boundary rules as in the forward
+// the state two cells away. A workgroup computes mu once per cell of its
+// tile and the ring around it, in LDS, then gathers. Boundary rules as in the forward
 // step: a transmissive ghost is a copy of its boundary cell (its share goes
 // to that cell), a Dirichlet ghost a constant state (no share flows back).
 //
@@ -205,9 +206,12 @@ struct SprayAdj {
   }
 
   // lam^n of the real cell (j, i)
-  __device__ __forceinline__ void cell(int j, int i, double* out) const {
-    double mc[6], c[6];
-    mu_at(j, i, mc);
+  // lam^n of the real cell (j, i) from its own mu (mc) and its neighbours'
+  // (nb_mu(side, m) fills mu of the neighbour cell on that side)
+  template <class NbMu>
+  __device__ __forceinline__ void gather(int j, int i, const double* mc, NbMu&& nb_mu,
+                                         double* out) const {
+    double c[6];
     load6(a.w, a.g, j, i, c);
 #pragma unroll
     for (int v = 0; v < 6; ++v) out[v] = mc[v];
@@ -216,7 +220,7 @@ struct SprayAdj {
     // x faces: east (c left of it), west (c right of it)
     int k = neighbour(a.g, j, i, 1, jj, ii);
     if (k == kCell) {
-      mu_at(jj, ii, m);
+      nb_mu(1, m);
 #pragma unroll
       for (int v = 0; v < 6; ++v) d[v] = m[v] - mc[v];
       add_jl<0>(c, d, mux, out);
@@ -228,7 +232,7 @@ struct SprayAdj {
     }
     k = neighbour(a.g, j, i, 0, jj, ii);
     if (k == kCell) {
-      mu_at(jj, ii, m);
+      nb_mu(0, m);
 #pragma unroll
       for (int v = 0; v < 6; ++v) d[v] = mc[v] - m[v];
       add_jr<0>(c, d, mux, out);
@@ -239,7 +243,7 @@ struct SprayAdj {
     // y faces: north, south
     k = neighbour(a.g, j, i, 3, jj, ii);
     if (k == kCell) {
-      mu_at(jj, ii, m);
+      nb_mu(3, m);
 #pragma unroll
       for (int v = 0; v < 6; ++v) d[v] = m[v] - mc[v];
       add_jl<1>(c, d, muy, out);
@@ -251,7 +255,7 @@ struct SprayAdj {
     }
     k = neighbour(a.g, j, i, 2, jj, ii);
     if (k == kCell) {
-      mu_at(jj, ii, m);
+      nb_mu(2, m);
 #pragma unroll
       for (int v = 0; v < 6; ++v) d[v] = mc[v] - m[v];
       add_jr<1>(c, d, muy, out);
@@ -262,18 +266,71 @@ struct SprayAdj {
   }
 };
 
-// lam^n of the real cell (j, i), written to a.lam_out
-__device__ __forceinline__ void spray_adjoint_cell(const AdjointArgs& a, const double* ug,
-                                                   int j, int i) {
+// ---- tiles ------------------------------------------------------------------
+//
+// A workgroup of kTileThreads threads owns kTX x kTY cells. It first computes
+// mu once for every cell of the tile and of the one-cell ring around it (the
+// ring wraps on periodic grids; outside other grids it is not needed: those
+// faces use the ghost rules) into LDS, then each thread gathers the faces of
+// its cells from there. Every mu is computed as the per-cell formula does,
+// so the result does not depend on the tiling.
+
+constexpr int kTileThreads = 256;
+constexpr int kTX = 64;                      // one wave across
+constexpr int kTY = 8;
+constexpr int kRX = kTX + 2, kRY = kTY + 2;  // with the ring
+constexpr int kRing = kRX * kRY;             // mu values per variable in LDS
+
+__device__ __forceinline__ SprayAdj make_adj(const AdjointArgs& a, const double* ug) {
   SprayAdj s{a, ug, 0.0, 0.0, 0.0};
   s.dt = a.dts ? a.dts[a.k] : a.dt_arg;
   s.mux = s.dt / a.g.dx;
   s.muy = s.dt / a.g.dy;
-  double out[6];
-  s.cell(j, i, out);
-  double* p = a.lam_out + static_cast<size_t>(j) * a.g.ld + i;
+  return s;
+}
+
+// phase 1: mu of the tile and its ring into mu_s[v * kRing + r * kRX + c]
+__device__ __forceinline__ void tile_mu(const SprayAdj& s, int j0, int i0, int tid,
+                                        double* mu_s) {
+  const GridGeom& g = s.a.g;
+  for (int idx = tid; idx < kRing; idx += kTileThreads) {
+    const int r = idx / kRX, c = idx % kRX;
+    int j = j0 - 1 + r, i = i0 - 1 + c;
+    bool need = j >= -1 && j <= g.ny && i >= -1 && i <= g.nx;
+    if (j < 0 || j >= g.ny || i < 0 || i >= g.nx) {
+      need = need && g.bc == FVM_PERIODIC;
+      j = j < 0 ? g.ny - 1 : (j >= g.ny ? 0 : j);
+      i = i < 0 ? g.nx - 1 : (i >= g.nx ? 0 : i);
+    }
+    double m[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+    if (need) s.mu_at(j, i, m);
 #pragma unroll
-  for (int v = 0; v < 6; ++v) p[v * a.g.plane] = out[v];
+    for (int v = 0; v < 6; ++v) mu_s[v * kRing + idx] = m[v];
+  }
+}
+
+// phase 2: lam^n of the tile's cells from mu_s
+__device__ __forceinline__ void tile_out(const SprayAdj& s, int j0, int i0, int tid,
+                                         const double* mu_s) {
+  const GridGeom& g = s.a.g;
+  const int c = tid % kTX;
+  for (int rr = tid / kTX; rr < kTY; rr += kTileThreads / kTX) {
+    const int j = j0 + rr, i = i0 + c;
+    if (j >= g.ny || i >= g.nx) continue;
+    const int at = (rr + 1) * kRX + c + 1;
+    double mc[6], out[6];
+#pragma unroll
+    for (int v = 0; v < 6; ++v) mc[v] = mu_s[v * kRing + at];
+    auto nb_mu = [mu_s, at](int side, double* m) {
+      const int o = side == 0 ? -1 : (side == 1 ? 1 : (side == 2 ? -kRX : kRX));
+#pragma unroll
+      for (int v = 0; v < 6; ++v) m[v] = mu_s[v * kRing + at + o];
+    };
+    s.gather(j, i, mc, nb_mu, out);
+    double* p = s.a.lam_out + static_cast<size_t>(j) * g.ld + i;
+#pragma unroll
+    for (int v = 0; v < 6; ++v) p[v * g.plane] = out[v];
+  }
 }
 
 }  // namespace sadj

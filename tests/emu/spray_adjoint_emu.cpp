@@ -1,6 +1,6 @@
-// spray_adjoint_emu.cpp -- runs the spray adjoint's per-cell device code on
-// the CPU, cell by cell, to check its memory accesses and its values without
-// a GPU.
+// spray_adjoint_emu.cpp -- runs the spray adjoint's device code on the CPU,
+// tile by tile and thread by thread, to check its memory accesses (global
+// and LDS) and its values without a GPU.
 //
 // Usage: spray_adjoint_emu bc nx ny pitch layout lx ly dt K inv_theta s_eps in out
 //
@@ -96,8 +96,18 @@ int main(int argc, char** argv) {
   for (int s = 0; s < 4; ++s)
     for (int v = 0; v < 6; ++v) a.ghost[s * kMaxVar + v] = raw[14 * n + s * 6 + v];
 
-  for (int j = 0; j < ny; ++j)
-    for (int i = 0; i < nx; ++i) sadj::spray_adjoint_cell(a, ug, j, i);
+  // every tile's two phases, thread by thread, with a heap LDS stand-in of
+  // exactly the kernel's size (the barrier sits between the phases)
+  const sadj::SprayAdj sa = sadj::make_adj(a, ug);
+  const int tx = (nx + sadj::kTX - 1) / sadj::kTX, ty = (ny + sadj::kTY - 1) / sadj::kTY;
+  for (int b = 0; b < tx * ty; ++b) {
+    const int i0 = (b % tx) * sadj::kTX, j0 = (b / tx) * sadj::kTY;
+    double* lds = new double[6 * sadj::kRing];
+    for (int k = 0; k < 6 * sadj::kRing; ++k) lds[k] = NAN;
+    for (int t = 0; t < sadj::kTileThreads; ++t) sadj::tile_mu(sa, j0, i0, t, lds);
+    for (int t = 0; t < sadj::kTileThreads; ++t) sadj::tile_out(sa, j0, i0, t, lds);
+    delete[] lds;
+  }
 
   // every cell written, no padding touched
   std::vector<double> res(6 * n);

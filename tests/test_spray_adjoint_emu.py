@@ -1,8 +1,9 @@
 """The spray adjoint's device code, built for the host (tests/emu/
-spray_adjoint_emu.cpp) and run cell by cell under AddressSanitizer on
-buffers exactly as large as the ABI contract: no access outside them, no
-padding column written, and the values equal the oracle's adjoint step
-(relative L-inf 1e-12) for every boundary condition and both layouts."""
+spray_adjoint_emu.cpp) and run tile by tile under AddressSanitizer on
+buffers exactly as large as the ABI contract (LDS included): no access
+outside them, no padding column written, and the values equal the oracle's
+adjoint step (relative L-inf 1e-12) for every boundary condition and both
+layouts, on grids with ragged tiles in both directions."""
 import math
 import os
 import shutil
@@ -51,7 +52,8 @@ def _case(nx, ny, seed):
 
 
 # (nx, ny, pitch)
-SHAPES = [(1, 1, 1), (1, 5, 2), (2, 3, 2), (7, 4, 8), (65, 6, 72), (130, 5, 130)]
+SHAPES = [(1, 1, 1), (1, 5, 2), (2, 3, 2), (7, 4, 8), (65, 9, 72), (130, 17, 130),
+          (64, 8, 64)]
 
 
 def test_spray_adjoint_cells_in_bounds_and_equal_the_oracle(emu, tmp_path):
