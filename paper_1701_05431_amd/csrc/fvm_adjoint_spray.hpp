@@ -275,11 +275,18 @@ struct SprayAdj {
 // its cells from there. Every mu is computed as the per-cell formula does,
 // so the result does not depend on the tiling.
 
-constexpr int kTileThreads = 256;
-constexpr int kTX = 64;                      // one wave across
-constexpr int kTY = 8;
+#ifndef FVM_SADJ_THREADS
+#define FVM_SADJ_THREADS 512
+#endif
+#ifndef FVM_SADJ_ROWS
+#define FVM_SADJ_ROWS 16
+#endif
+constexpr int kTileThreads = FVM_SADJ_THREADS;  // a multiple of kTX
+constexpr int kTX = 64;                         // one wave across
+constexpr int kTY = FVM_SADJ_ROWS;
 constexpr int kRX = kTX + 2, kRY = kTY + 2;  // with the ring
 constexpr int kRing = kRX * kRY;             // mu values per variable in LDS
+static_assert(kTileThreads % kTX == 0, "whole waves across the tile");
 
 __device__ __forceinline__ SprayAdj make_adj(const AdjointArgs& a, const double* ug) {
   SprayAdj s{a, ug, 0.0, 0.0, 0.0};
