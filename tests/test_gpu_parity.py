@@ -1016,10 +1016,11 @@ def test_fvrun_spray_gradient(bc):
 
 def test_spray_adjoint_2048_full_size_step():
     """One spray adjoint step on the 2048^2 spray workload's state (lognormal
-    closure, K = 1, theta = 0.1) against the oracle, whole grid."""
+    closure, K = 1, theta = 0.1) in the benchmark's storage layout against
+    the oracle, whole grid."""
     pre = inputs.SPRAY_2048
     W, ug = inputs.spray_state(pre.nx, pre.ny, 0)
-    p = params_from(pre)
+    p = params_from(pre, layout=_lib.FVM_LAYOUT_ROWS)
     lam = np.random.default_rng(5).standard_normal(W.shape)
     P = oparams(p)
     orc.set_threads(16)
