@@ -1014,6 +1014,33 @@ def test_fvrun_spray_gradient(bc):
         assert abs(float(np.sum(g * v)) - fd) <= 1e-6 * max(1.0, abs(fd))
 
 
+@pytest.mark.parametrize("bc", [0, 1, 2])
+def test_spray_adjoint_degenerate_cases(bc):
+    """dt = 0 leaves the multipliers bit for bit unchanged; vacuum cells (all
+    moments zero: no velocity, no source) next to droplets, with and without
+    evaporation, match the oracle."""
+    nx, ny = 70, 21
+    W, ug = _spray_adjoint_case(nx, ny, 17)
+    W[:, 5:12, 20:41] = 0.0   # a vacuum block
+    W[:, :, 60] = 0.0         # and a vacuum column
+    gh = _spray_ghosts() if bc == _lib.FVM_DIRICHLET else None
+    lam = np.random.default_rng(19).standard_normal(W.shape)
+    for K in (0.7, 0.0):
+        print(f"spray adjoint degenerate bc={bc} K={K}", flush=True)
+        p = params_from(model=2, bc=bc, nx=nx, ny=ny, K=K, cfl=0.9)
+        s = Solver(p, ug=ug)
+        if gh is not None:
+            s.set_boundary_states(gh)
+        same = s.adjoint_step(W, 0.0, lam)
+        torch.cuda.synchronize()
+        assert np.array_equal(same[:, :, :nx].cpu().numpy(), lam)
+        dt = 0.3 / nx
+        got = s.adjoint_step(W, dt, lam)
+        torch.cuda.synchronize()
+        ref = orc.adjoint_step(oparams(p, gh), W, dt, lam, ug)
+        assert rel_linf(got[:, :, :nx].cpu().numpy(), ref) <= TOL
+
+
 def test_spray_adjoint_2048_full_size_step():
     """One spray adjoint step on the 2048^2 spray workload's state (lognormal
     closure, K = 1, theta = 0.1) in the benchmark's storage layout against

@@ -47,6 +47,8 @@ def _case(nx, ny, seed):
     W = W.copy()
     W[:4] *= 1.0 + 0.02 * rng.standard_normal((4, ny, nx))
     W[4:] += 0.1 * W[2] * rng.standard_normal((2, ny, nx))
+    if nx >= 7 and ny >= 4:
+        W[:, 1:3, 2:5] = 0.0   # vacuum cells next to droplets
     lam = rng.standard_normal((6, ny, nx))
     return W, ug, lam
 
