@@ -282,7 +282,7 @@ int fvm_get_tiling(const fvm_grid* g, int* rows_per_strip, int* waves_per_block)
  * and the state and multiplier buffers of a launch are 16-byte aligned, else
  * 1); 0 keeps the current value. fvm_autotune chooses among all of them.
  * Results do not depend on any of them. The spray's adjoint kernel ignores
- * them (one cell per thread). */
+ * them (it has one fixed tile shape). */
 int fvm_set_adjoint_tiling(fvm_grid* g, int rows_per_strip, int waves_per_block,
                            int cells_per_lane);
 
@@ -313,8 +313,8 @@ int fvm_autotune(fvm_grid* g, const char* cache_path);
  * fvm_adjoint_step takes them), applies the fastest and caches it like
  * fvm_autotune (its own key). Separate multiplier buffers move the traffic
  * of real adjoint steps, which the in-place dry launches of fvm_autotune
- * only approximate. FVM_EUNSUPPORTED for the spray (its adjoint kernel has a
- * single shape: one cell per thread) and where fvm_adjoint_step is.
+ * only approximate. FVM_EUNSUPPORTED for the spray (its adjoint kernel has
+ * one fixed tile shape) and where fvm_adjoint_step is.
  * Synchronises the stream. */
 int fvm_autotune_adjoint(fvm_grid* g, const double* w, const double* lam_in, double* lam_out,
                          const char* cache_path);
