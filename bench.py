@@ -441,6 +441,7 @@ def bench_advection(steps):
 def cpu_baseline(target_s: float = 12.0):
     """The oracle as it is, on the host cores, on a bounded sample of the
     headline workload: a few steps of the 4096^2 Euler grid."""
+    import numpy as np
     from oracle import fv as orc
     from paper_1701_05431_amd import inputs
     pre = inputs.EULER_4096
@@ -466,10 +467,26 @@ def cpu_baseline(target_s: float = 12.0):
     t0 = time.perf_counter()
     orc.run(P, W, k)
     t = time.perf_counter() - t0
+    # the oracle's adjoint (one thread) on the adjoint workload's kind of
+    # state at 256^2: forward states kept, then the adjoint steps
+    adj = inputs.ADJOINT_1024
+    n, steps = 256, 10
+    Pa = orc.from_preset(adj, nx=n, ny=n, npx=1, npy=1)
+    Wa = inputs.riemann_state(n, n, 0)
+    _, dts = orc.run(Pa, Wa, steps)
+    lam = np.zeros_like(Wa)
+    lam[0] = 1.0
+    t0 = time.perf_counter()
+    orc.adjoint_run(Pa, Wa, dts, lam)
+    ta = time.perf_counter() - t0
     return {"value": pre.nx * pre.ny * k / t / 1e9, "unit": "Gcell-updates/s",
             "cores": orc.get_threads(), "kind": "oracle",
             "sample": f"{pre.name}: {k} adaptive steps in one call after 5 untimed steps, "
-                      f"{t:.1f} s"}
+                      f"{t:.1f} s",
+            "adjoint": {"workload": f"euler_adjoint_{n}x{n}", "steps": steps, "cores": 1,
+                        "ms_per_step": ta / steps * 1e3,
+                        "sample": "forward states recomputed and kept, then the adjoint "
+                                  "steps, one call"}}
 
 
 def traffic_from_counters(tiling: dict, layout: str):
