@@ -997,6 +997,16 @@ def test_fvrun_spray_gradient(bc):
     Y = fvrun(X, s, 12, 4)
     (0.5 * ((Y[0] - tgt) ** 2).sum()).backward()
     g = X.grad.cpu().numpy()
+    # the same gradient, bit for bit, from row-interleaved storage with a padded pitch
+    pr = params_from(model=2, bc=bc, nx=n, ny=n, K=0.5, cfl=0.5, ld=n + 2,
+                     layout=_lib.FVM_LAYOUT_ROWS)
+    sr = Solver(pr, ug=ug)
+    if gh is not None:
+        sr.set_boundary_states(gh)
+    Xr = torch.tensor(W0, device="cuda", requires_grad=True)
+    Yr = fvrun(Xr, sr, 12, 4)
+    (0.5 * ((Yr[0] - tgt) ** 2).sum()).backward()
+    assert torch.equal(Yr, Y) and np.array_equal(Xr.grad.cpu().numpy(), g)
     P = oparams(p, gh)
     WN, odts = orc.run(P, W0, 12, ug)
     assert rel_linf(Y.detach().cpu().numpy(), WN) <= 1e-11
