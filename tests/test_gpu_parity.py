@@ -985,6 +985,7 @@ def test_fvrun_spray_gradient(bc):
     equals the oracle's adjoint run, and central differences of the oracle's
     forward steps agree with it."""
     n = 40
+    print(f"spray fvrun gradient bc={bc}", flush=True)
     W0, ug = _spray_adjoint_case(n, n, 12)
     gh = _spray_ghosts() if bc == _lib.FVM_DIRICHLET else None
     p = params_from(model=2, bc=bc, nx=n, ny=n, K=0.5, cfl=0.5)
