@@ -1,6 +1,8 @@
-// Host stand-in for <hip/hip_runtime.h>, used only by strip_emu.cpp: it lets
-// the device headers of the fused step compile as plain C++ so that the 64
-// lanes of a wave run as 64 host threads in lockstep. Cross-lane moves (DPP
+// Host stand-in for <hip/hip_runtime.h>, used only by the CPU emulators in
+// tests/emu (strip_emu.cpp, adjoint_emu.cpp, spray_adjoint_emu.cpp): it lets
+// the device headers compile as plain C++ so that the 64 lanes of a wave run
+// as 64 host threads in lockstep (or, for the spray adjoint's per-thread
+// code, one thread after another). Cross-lane moves (DPP
 // row shifts, xor shuffles) go through a shared slot array between two
 // barriers; the hardware reciprocal / rsqrt estimates become exact host
 // arithmetic. The reduction atomics are single-threaded stand-ins: the
