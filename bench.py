@@ -83,6 +83,60 @@ def timed(fn, reps: int = 1):
     return s.elapsed_time(e) / 1e3 / reps
 
 
+def median_windows(fn, steps: int, reps: int = 5):
+    """Times `reps` windows of fn() (one window = `steps` steps) with HIP
+    events; returns (median ms per step, all ms per step)."""
+    ms = sorted(timed(fn) / steps * 1e3 for _ in range(reps))
+    return ms[len(ms) // 2], ms
+
+
+def euler_protocol(s, steps: int, warmup: int, reps: int = 5, seeds=(0, 1, 2)):
+    """The headline step timed as the median of `reps` windows of `steps`
+    steps per seed of the Riemann data (each seed after `warmup` untimed
+    steps)."""
+    import torch
+    from paper_1701_05431_amd import inputs
+    pre = inputs.EULER_4096
+    per_seed = {}
+    for seed in seeds:
+        s.set_state(torch.from_numpy(inputs.riemann_state(pre.nx, pre.ny, seed)))
+        s.run(warmup)
+        med, allv = median_windows(lambda: s.run(steps), steps, reps)
+        per_seed[str(seed)] = {"median_ms_per_step": med, "ms_per_step": allv}
+    meds = sorted(v["median_ms_per_step"] for v in per_seed.values())
+    med = meds[len(meds) // 2]
+    return {"windows_per_seed": reps, "steps_per_window": steps, "warmup_per_seed": warmup,
+            "seeds": list(seeds), "per_seed": per_seed, "median_ms_per_step": med,
+            "median_gcell_updates_per_s": pre.nx * pre.ny / (med * 1e-3) / 1e9,
+            "median_hbm_frac": 64.0 * pre.nx * pre.ny / (med * 1e-3) / 1e9 / HBM_PEAK_GBS}
+
+
+def clock_state():
+    """The GPU's engine and memory clock tables and performance level from
+    sysfs, when this process may read them (None otherwise)."""
+    import glob
+    import torch
+    try:
+        props = torch.cuda.get_device_properties(0)
+        bus = getattr(props, "pci_bus_id", None)
+        dom = getattr(props, "pci_domain_id", 0)
+        dev = getattr(props, "pci_device_id", 0)
+    except Exception:
+        return None
+    if bus is None:
+        return None
+    base = f"/sys/bus/pci/devices/{dom:04x}:{bus:02x}:{dev:02x}.0"
+    out = {"pci": base.rsplit("/", 1)[-1]}
+    for name in ("pp_dpm_sclk", "pp_dpm_mclk", "power_dpm_force_performance_level"):
+        paths = glob.glob(os.path.join(base, name))
+        try:
+            with open(paths[0]) as fh:
+                out[name] = fh.read().strip().splitlines()
+        except (IndexError, OSError):
+            out[name] = None
+    return out
+
+
 def bench_euler(args):
     import torch
     from paper_1701_05431_amd import inputs
@@ -438,35 +492,99 @@ def bench_advection(steps):
             "status": s.sync()}
 
 
-def cpu_baseline(target_s: float = 12.0):
-    """The oracle as it is, on the host cores, on a bounded sample of the
-    headline workload: a few steps of the 4096^2 Euler grid."""
+def cpu_share() -> tuple[int, int]:
+    """(threads the CPU baseline uses, host cores visible to this process):
+    one GPU's share of a shared host is 16 cores, whatever the affinity
+    mask shows."""
+    try:
+        visible = len(os.sched_getaffinity(0))
+    except AttributeError:
+        visible = os.cpu_count() or 1
+    return min(visible, 16), visible
+
+
+def _oracle_step_cost(run, k_target_s: float):
+    """Per-step seconds of an oracle run(n) call, from a one-step and a
+    three-step call (a call has a fixed cost, the subdomain copies in and
+    out, besides its steps); returns (per_step, t1, t3)."""
+    t0 = time.perf_counter()
+    run(1)
+    t1 = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    run(3)
+    t3 = time.perf_counter() - t0
+    return max((t3 - t1) / 2.0, 1e-4), t1, t3
+
+
+def cpu_baseline(target_s: float = 10.0):
+    """The oracle as it is, on the host: the headline Euler workload on the
+    CPU share (value) and on one core, bounded samples of the spray and
+    batch workloads, and the oracle's adjoint at 256^2; per-step times are
+    extrapolated to each workload's step count."""
     import numpy as np
+    from concurrent.futures import ThreadPoolExecutor
     from oracle import fv as orc
     from paper_1701_05431_amd import inputs
+    cores, visible = cpu_share()
     pre = inputs.EULER_4096
-    try:
-        cores = len(os.sched_getaffinity(0))
-    except AttributeError:
-        cores = os.cpu_count() or 1
-    cores = min(cores, 16)
+    cells = pre.nx * pre.ny
     orc.set_threads(cores)
     P = orc.from_preset(pre)
     W = inputs.riemann_state(pre.nx, pre.ny, 0)
     W, _ = orc.run(P, W, 1)  # warm-up: thread start-up, first touch of the arrays
-    # a call has a fixed cost (the subdomain copies in and out) besides its
-    # steps: size the sample from one- and three-step calls
-    t0 = time.perf_counter()
-    W, _ = orc.run(P, W, 1)
-    t1 = time.perf_counter() - t0
-    t0 = time.perf_counter()
-    W, _ = orc.run(P, W, 3)
-    t3 = time.perf_counter() - t0
-    per = max((t3 - t1) / 2.0, 1e-3)
+    per, t1, _ = _oracle_step_cost(lambda n: orc.run(P, W, n), target_s)
     k = max(1, min(1000, int((target_s - max(t1 - per, 0.0)) / per)))
     t0 = time.perf_counter()
     orc.run(P, W, k)
     t = time.perf_counter() - t0
+    value = cells * k / t / 1e9
+    # one core: the per-step cost from a one- and a three-step call
+    orc.set_threads(1)
+    per1, _, _ = _oracle_step_cost(lambda n: orc.run(P, W, n), target_s)
+    one_core = {"cores": 1, "gcell_updates_per_s": cells / per1 / 1e9, "s_per_step": per1,
+                "extrapolated_s_200_steps": 200 * per1,
+                "sample": f"{pre.name}: (three-step call - one-step call) / 2, one thread"}
+    # spray workload
+    sp = inputs.SPRAY_2048
+    Ps = orc.from_preset(sp)
+    Ws, ug = inputs.spray_state(sp.nx, sp.ny, 0)
+    spray = {}
+    for nthr in (cores, 1):
+        orc.set_threads(nthr)
+        ps, _, _ = _oracle_step_cost(lambda n: orc.run(Ps, Ws, n, ug), target_s)
+        spray[str(nthr)] = {"cores": nthr, "gcell_updates_per_s": sp.nx * sp.ny / ps / 1e9,
+                            "s_per_step": ps, "extrapolated_s_200_steps": 200 * ps}
+    # batch workload: every grid, one call per grid, grids spread over the
+    # share's threads (one thread per call: the grids have one subdomain)
+    sizes = inputs.batch_sizes(inputs.BATCH_COUNT, 0)
+    bcells = sum(n * n for n in sizes)
+    bstates = [inputs.riemann_state(n, n, g) for g, n in enumerate(sizes)]
+
+    def grid_cost(gn):
+        g, n = gn
+        orc.set_threads(1)
+        Pg = orc.from_preset(inputs.BATCH_256, nx=n, ny=n, npx=1, npy=1)
+        t0 = time.perf_counter()
+        orc.run(Pg, bstates[g], 1)
+        a = time.perf_counter() - t0
+        t0 = time.perf_counter()
+        orc.run(Pg, bstates[g], 3)
+        return (time.perf_counter() - t0 - a) / 2.0
+
+    t0 = time.perf_counter()
+    with ThreadPoolExecutor(max_workers=cores) as ex:
+        costs = list(ex.map(grid_cost, list(enumerate(sizes))))
+    wall = time.perf_counter() - t0
+    step_1core = sum(costs)
+    batch = {"grids": len(sizes), "cells": bcells, "threads": cores,
+             "s_per_step_one_core": step_1core,
+             "gcell_updates_per_s_one_core": bcells / step_1core / 1e9,
+             "s_per_step_share": step_1core / cores,
+             "gcell_updates_per_s_share": bcells / (step_1core / cores) / 1e9,
+             "extrapolated_s_100_steps_share": 100 * step_1core / cores,
+             "sample": "each grid's (three-step call - one-step call) / 2 on one thread, "
+                       f"grids spread over {cores} threads ({wall:.1f} s wall); the share's rate "
+                       "assumes the grids divide evenly over its threads"}
     # the oracle's adjoint (one thread) on the adjoint workload's kind of
     # state at 256^2: forward states kept, then the adjoint steps
     adj = inputs.ADJOINT_1024
@@ -479,10 +597,13 @@ def cpu_baseline(target_s: float = 12.0):
     t0 = time.perf_counter()
     orc.adjoint_run(Pa, Wa, dts, lam)
     ta = time.perf_counter() - t0
-    return {"value": pre.nx * pre.ny * k / t / 1e9, "unit": "Gcell-updates/s",
-            "cores": orc.get_threads(), "kind": "oracle",
-            "sample": f"{pre.name}: {k} adaptive steps in one call after 5 untimed steps, "
-                      f"{t:.1f} s",
+    orc.set_threads(cores)
+    return {"value": value, "unit": "Gcell-updates/s", "cores": cores, "kind": "oracle",
+            "host_cores_visible": visible,
+            "sample": f"{pre.name}: {k} adaptive steps in one call ({t:.1f} s) after 5 "
+                      f"untimed steps, {cores} threads (one GPU's share of the host)",
+            "extrapolated_s_200_steps": 200 * t / k,
+            "one_core": one_core, "spray": spray, "batch": batch,
             "adjoint": {"workload": f"euler_adjoint_{n}x{n}", "steps": steps, "cores": 1,
                         "ms_per_step": ta / steps * 1e3,
                         "sample": "forward states recomputed and kept, then the adjoint "
@@ -564,6 +685,9 @@ def main():
 
     e = bench_euler(args)
     value = e["cells"] * args.steps / e["sec"] / 1e9
+    log("euler: median of 5 windows for seeds 0, 1, 2")
+    protocol = euler_protocol(e["solver"], args.steps, args.warmup)
+    protocol["clock_state"] = clock_state()
     tiling = {"rows_per_strip": e["tiling"][0], "waves_per_block": e["tiling"][1],
               "cells_per_lane": e["cpl"]}
     traffic = traffic_from_counters(tiling, args.layout)
@@ -615,6 +739,7 @@ def main():
                    "init": "four-quadrant Riemann, seed 0", "layout": args.layout,
                    "tiling": tiling},
         "roofline": roof,
+        "timing_protocol": protocol,
         "cpu_baseline": cpu,
         "workloads": work,
     }

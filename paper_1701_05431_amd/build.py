@@ -11,6 +11,7 @@ import os
 import subprocess
 import sys
 import tempfile
+from concurrent.futures import ThreadPoolExecutor
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
@@ -30,17 +31,32 @@ def flags(extra=()):
             "-I", os.path.join(HERE, "..", "include"), *extra]
 
 
+def _jobs() -> int:
+    """Parallel compiles: MAX_JOBS if set, else the usable cores, at most 16."""
+    env = os.environ.get("MAX_JOBS")
+    if env and env.isdigit() and int(env) > 0:
+        return min(int(env), 16)
+    try:
+        n = len(os.sched_getaffinity(0))
+    except AttributeError:
+        n = os.cpu_count() or 1
+    return max(1, min(n, 16))
+
+
 def build(verbose: bool = False, extra=(), out: str = LIB) -> str:
     """Compiles every source (extra: additional hipcc flags) and links `out`."""
     with tempfile.TemporaryDirectory(prefix="fvm_build_") as tmpdir:
-        objs = []
+        objs, cmds = [], []
         for src in SOURCES:
             obj = os.path.join(tmpdir, src.replace(".hip", ".o"))
-            cmd = [HIPCC, *flags(extra), "-c", os.path.join(CSRC, src), "-o", obj]
-            if verbose:
-                print(" ".join(cmd), flush=True)
-            subprocess.run(cmd, check=True)
+            cmds.append([HIPCC, *flags(extra), "-c", os.path.join(CSRC, src), "-o", obj])
             objs.append(obj)
+        if verbose:
+            for cmd in cmds:
+                print(" ".join(cmd), flush=True)
+        with ThreadPoolExecutor(max_workers=_jobs()) as ex:
+            for r in ex.map(lambda c: subprocess.run(c, check=True), cmds):
+                pass
         tmp = out + ".tmp"
         cmd = [HIPCC, "--offload-arch=" + ARCH, "-shared", "-fPIC", "-o", tmp, *objs]
         if verbose:

@@ -24,7 +24,8 @@ void* step_kernel_ptr(int model, int bc, int wpb, int cpl, bool halo);
 hipError_t launch_step(const StepArgs& a, int model, hipStream_t st);
 hipError_t launch_cfl(const CflArgs& a, int model, hipStream_t st);
 hipError_t launch_clear_scratch(GridScratch* s, int n, hipStream_t st);
-hipError_t launch_clear_log_cursor(GridScratch* s, hipStream_t st);
+hipError_t launch_set_log(GridScratch* s, int n, double* base, int cap, int stride,
+                          hipStream_t st);
 hipError_t launch_adjoint(const AdjointArgs& a, int model, const double* ug, hipStream_t st);
 
 GridGeom grid_geometry(const fvm_params& p) {
@@ -60,8 +61,13 @@ namespace {
 
 constexpr int kDefaultRows = 64;
 constexpr int kDefaultWpb = 4;
-constexpr int kGraphChunk = 32;   // steps per cached graph
-constexpr size_t kGraphCacheMax = 16;
+// Runs are cut into graphs of 32, 16, 8, 4, 2 and 1 steps; the first run of
+// a kind builds every chunk from both ping-pong buffers, so later runs of any
+// length only replay cached graphs (no graph is built between the caller's
+// launches).
+constexpr int kGraphChunk = 32;
+constexpr int kChunkSizes[6] = {32, 16, 8, 4, 2, 1};
+constexpr size_t kGraphCacheMax = 40;
 
 bool valid_params(const fvm_params* p) {
   if (!p) return false;
@@ -173,7 +179,6 @@ struct GraphKey {
   const double* start;   // input buffer of the first step
   const double* other;
   const double* dts;
-  const double* log;
   int k0;
   int rows, wpb, cpl;
   double dt;             // kind 3
@@ -181,7 +186,7 @@ struct GraphKey {
   bool me_warm;          // the graph's first step starts from it
   bool operator==(const GraphKey& o) const {
     return kind == o.kind && nsteps == o.nsteps && start == o.start && other == o.other &&
-           dts == o.dts && log == o.log && k0 == o.k0 && rows == o.rows && wpb == o.wpb &&
+           dts == o.dts && k0 == o.k0 && rows == o.rows && wpb == o.wpb &&
            cpl == o.cpl && dt == o.dt && me_lam == o.me_lam && me_warm == o.me_warm;
   }
 };
@@ -213,6 +218,7 @@ struct fvm_grid {
   double* me_lam = nullptr;        // entropy closure: the caller's multiplier buffer
   bool me_valid = false;           // it holds the multipliers of the current state's cells
   GridScratch* scr = nullptr;
+  const double* log_armed = nullptr;  // dt log the scratch currently points to
   hipStream_t stream = nullptr;
   bool bound = false;
   bool speeds_valid = false;
@@ -238,7 +244,6 @@ struct fvm_grid {
     a.ug = ug;
     a.scr = scr;
     a.mode = mode;
-    a.dt_log_stride = 1;
     a.g = g;
     a.t = tiling(g, rows, wpb, cpl);
     a.m = m;
@@ -347,6 +352,7 @@ int fvm_bind(fvm_grid* g, double* w_a, double* w_b, const double* ug, void* scra
   choose_layout(g);
   g->speeds_valid = false;
   g->me_valid = false;
+  g->log_armed = nullptr;
   return dev_err(launch_clear_scratch(g->scr, 1, g->stream));
 }
 
@@ -430,6 +436,17 @@ int fvm_get_state(fvm_grid* g, double* dst, int dst_on_device) {
   return dev_err(e);
 }
 
+// Points the scratch's dt log at `log` (cap entries, cursor rewound) for the
+// steps enqueued next; log == null turns logging off. Every path that
+// enqueues steps calls it first, so no step logs into a buffer of an earlier
+// run.
+static int arm_log(fvm_grid* g, double* log, int cap) {
+  if (!log && !g->log_armed) return FVM_OK;
+  const int rc = dev_err(launch_set_log(g->scr, 1, log, cap, 1, g->stream));
+  if (rc == FVM_OK) g->log_armed = log;
+  return rc;
+}
+
 // One step launch outside a graph: the step kernel, and for the entropy
 // closure the source pass that completes it.
 static int enqueue_step(fvm_grid* g, const StepArgs& a) {
@@ -507,6 +524,7 @@ int fvm_step(fvm_grid* g, double dt) {
   if (!(dt > 0.0) || !std::isfinite(dt)) return FVM_EINVAL;
   int rc = FVM_OK;
   if (!g->speeds_valid) rc = enqueue_cfl(g, nullptr);
+  if (rc == FVM_OK) rc = arm_log(g, nullptr, 0);
   if (rc) return rc;
   StepArgs a = g->step_args(g->cur, g->other(g->cur), kDtFixedCheck);
   a.dt_arg = dt;
@@ -515,20 +533,32 @@ int fvm_step(fvm_grid* g, double dt) {
   return rc;
 }
 
-// Builds (or finds) the graph of `n` consecutive steps starting from buffer
-// `start`, with step k reading its dt according to `mode`.
-static int graph_for(fvm_grid* g, int kind, int n, double* start, const double* dts, int k0,
-                     double* log, int log_cap, hipGraphExec_t* exec, double dt = 0.0) {
+static GraphKey graph_key(const fvm_grid* g, int kind, int n, const double* start,
+                          const double* dts, int k0, double dt) {
   const bool me_warm = g->me_lam && g->me_valid;
-  GraphKey key{kind,   n,      start,  g->other(start), dts, log, k0,
-               g->rows, g->wpb, g->cpl, dt, g->me_lam, me_warm};
+  return GraphKey{kind,   n,      start,  g->other(start), dts, k0,
+                  g->rows, g->wpb, g->cpl, dt, g->me_lam, me_warm};
+}
+
+// The cached graph of `key`, moved to the front of the cache, or null.
+static CachedGraph* find_graph(fvm_grid* g, const GraphKey& key) {
   for (auto it = g->graphs.begin(); it != g->graphs.end(); ++it) {
     if (it->key == key) {
       g->graphs.splice(g->graphs.begin(), g->graphs, it);
-      *exec = g->graphs.front().exec;
-      return FVM_OK;
+      return &g->graphs.front();
     }
   }
+  return nullptr;
+}
+
+// Builds the graph of `key`: n consecutive steps starting from buffer
+// key.start, with step k reading its dt according to the kind.
+static int build_graph(fvm_grid* g, const GraphKey& key, hipGraphExec_t* exec) {
+  const int kind = key.kind, n = key.nsteps, k0 = key.k0;
+  const double* start = key.start;
+  const double* dts = key.dts;
+  const double dt = key.dt;
+  const bool me_warm = key.me_warm;
   CachedGraph c;
   c.key = key;
   if (hipGraphCreate(&c.graph, 0) != hipSuccess) return FVM_EDEVICE;
@@ -544,8 +574,6 @@ static int graph_for(fvm_grid* g, int kind, int n, double* start, const double* 
     args[s].dts = dts;
     args[s].dt_arg = dt;
     args[s].k = kind == 2 ? 0 : k0 + s;  // kind 2: dry run, dts = the scratch's zero
-    args[s].dt_log = log;
-    args[s].dt_log_cap = log_cap;
     void* kp[] = {&args[s]};
     hipKernelNodeParams np{};
     np.func = fn;
@@ -593,20 +621,63 @@ static int graph_for(fvm_grid* g, int kind, int n, double* start, const double* 
   return FVM_OK;
 }
 
+// Finds or builds the graph of `n` consecutive steps starting from buffer
+// `start`, with step k reading its dt according to `kind`.
+static int graph_for(fvm_grid* g, int kind, int n, double* start, const double* dts, int k0,
+                     hipGraphExec_t* exec, double dt = 0.0) {
+  const GraphKey key = graph_key(g, kind, n, start, dts, k0, dt);
+  if (CachedGraph* c = find_graph(g, key)) {
+    *exec = c->exec;
+    return FVM_OK;
+  }
+  return build_graph(g, key, exec);
+}
+
+// Adaptive and fixed-dt runs: on a miss, builds the graph of every chunk size
+// from both ping-pong buffers, so that any later run of this kind and
+// configuration only replays.
+static int chunk_graph(fvm_grid* g, int kind, int n, double dt, hipGraphExec_t* exec) {
+  const GraphKey key = graph_key(g, kind, n, g->cur, nullptr, 0, dt);
+  if (CachedGraph* c = find_graph(g, key)) {
+    *exec = c->exec;
+    return FVM_OK;
+  }
+  for (double* start : {g->other(g->cur), g->cur}) {
+    for (int m : kChunkSizes) {
+      if (start == g->cur && m == n) continue;  // built last: it heads the cache
+      const GraphKey k = graph_key(g, kind, m, start, nullptr, 0, dt);
+      hipGraphExec_t e;
+      if (!find_graph(g, k) && build_graph(g, k, &e) != FVM_OK) return FVM_EDEVICE;
+    }
+  }
+  return build_graph(g, key, exec);
+}
+
+// The largest chunk size not above `left`.
+static int chunk_size(int left) {
+  for (int m : kChunkSizes)
+    if (m <= left) return m;
+  return 1;
+}
+
 static int run_steps(fvm_grid* g, int kind, int nsteps, const double* dts, double* log,
                      double dt = 0.0) {
   int rc = FVM_OK;
   // adaptive steps and checked fixed steps read the current state's maxima
   if ((kind == 0 || kind == 3) && !g->speeds_valid) rc = enqueue_cfl(g, nullptr);
-  if (rc) return rc;
-  if (log) rc = dev_err(launch_clear_log_cursor(g->scr, g->stream));
+  if (rc == FVM_OK) rc = arm_log(g, log, nsteps);
   if (rc) return rc;
   int done = 0;
   while (done < nsteps) {
-    const int n = std::min(kGraphChunk, nsteps - done);
     hipGraphExec_t exec;
-    rc = graph_for(g, kind, n, g->cur, dts, kind == 1 ? done : 0, log, log ? nsteps : 0, &exec,
-                   dt);
+    int n;
+    if (kind == 0 || kind == 3) {
+      n = chunk_size(nsteps - done);
+      rc = chunk_graph(g, kind, n, dt, &exec);
+    } else {
+      n = std::min(kGraphChunk, nsteps - done);
+      rc = graph_for(g, kind, n, g->cur, dts, kind == 1 ? done : 0, &exec, dt);
+    }
     if (rc) return rc;
     rc = dev_err(hipGraphLaunch(exec, g->stream));
     if (rc) return rc;
@@ -642,8 +713,7 @@ int fvm_run_ckpt(fvm_grid* g, int nsteps, int ckpt_every, double* const* ckpts,
     if (!ckpts[s] || ckpts[s] == g->w_a || ckpts[s] == g->w_b) return FVM_EINVAL;
   int rc = FVM_OK;
   if (!g->speeds_valid) rc = enqueue_cfl(g, nullptr);
-  if (rc) return rc;
-  if (dts_dev) rc = dev_err(launch_clear_log_cursor(g->scr, g->stream));
+  if (rc == FVM_OK) rc = arm_log(g, dts_dev, nsteps);
   if (rc) return rc;
   const size_t bytes = sizeof(double) * g->elems();
   if (nck > 0) {
@@ -658,8 +728,6 @@ int fvm_run_ckpt(fvm_grid* g, int nsteps, int ckpt_every, double* const* ckpts,
     else
       out = (in == g->w_a) ? g->w_b : g->w_a;
     StepArgs a = g->step_args(in, out, kDtAdaptive);
-    a.dt_log = dts_dev;
-    a.dt_log_cap = dts_dev ? nsteps : 0;
     rc = enqueue_step(g, a);
     if (rc) return rc;
     in = out;
@@ -733,7 +801,8 @@ void cache_store(const char* path, const std::string& key, int rows, int wpb, in
 // tiling; returns microseconds per step, or a negative value on error.
 static double time_dry(fvm_grid* g, int n, int reps) {
   hipGraphExec_t exec;
-  if (graph_for(g, 2, n, g->cur, &g->scr->zero, 0, nullptr, 0, &exec) != FVM_OK) return -1.0;
+  if (arm_log(g, nullptr, 0) != FVM_OK) return -1.0;
+  if (graph_for(g, 2, n, g->cur, &g->scr->zero, 0, &exec) != FVM_OK) return -1.0;
   hipEvent_t e0, e1;
   if (hipEventCreate(&e0) != hipSuccess) return -1.0;
   if (hipEventCreate(&e1) != hipSuccess) {
@@ -963,6 +1032,7 @@ int fvm_adjoint_run(fvm_grid* g, double* const* ckpts, int ckpt_every, const dou
   for (int s = 0; s < nck; ++s)
     if (!ckpts[s]) return FVM_EINVAL;
   const size_t state = g->elems();
+  if (const int rc = arm_log(g, nullptr, 0)) return rc;  // the recomputed steps log nothing
   double* lin = lam;
   double* lout = lam_tmp;
   for (int s = nck - 1; s >= 0; --s) {

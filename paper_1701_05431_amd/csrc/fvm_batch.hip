@@ -41,6 +41,8 @@ namespace fvm {
 void* step_kernel_ptr(int model, int bc, int wpb, int cpl, bool halo);
 hipError_t launch_cfl(const CflArgs& a, int model, hipStream_t st);
 hipError_t launch_clear_scratch(GridScratch* s, int n, hipStream_t st);
+hipError_t launch_set_log(GridScratch* s, int n, double* base, int cap, int stride,
+                          hipStream_t st);
 
 __global__ void batch_clear_kernel(BatchScratch* b, GridScratch* g, int n) {
   const int k = blockIdx.x * blockDim.x + threadIdx.x;
@@ -52,11 +54,6 @@ __global__ void batch_clear_kernel(BatchScratch* b, GridScratch* g, int n) {
     GridScratch z = {};
     g[k] = z;
   }
-}
-
-__global__ void batch_log_rewind_kernel(GridScratch* g, int n) {
-  const int k = blockIdx.x * blockDim.x + threadIdx.x;
-  if (k < n) g[k].nstep = 0;
 }
 
 // PERSIST: a resident set of workgroups takes items from the queue until it
@@ -118,8 +115,7 @@ __global__ FVM_STEP_BOUNDS(WPB) void batch_kernel(BatchArgs a) {
                                        by);
     }
     if (block_commit<WPB>(bx, by, s, static_cast<unsigned int>(G.nitems)) && threadIdx.x == 0)
-      finalize_grid(s, G.g, dt, a.dt_log ? a.dt_log + G.user : nullptr, a.dt_log_cap, a.ngrids,
-                    nullptr);
+      finalize_grid(s, G.g, dt, true, nullptr);
     if constexpr (!PERSIST) break;
   }
   if (PERSIST && threadIdx.x == 0) {
@@ -164,11 +160,13 @@ namespace {
 
 int berr(hipError_t e) { return e == hipSuccess ? FVM_OK : FVM_EDEVICE; }
 
+constexpr int kBatchChunks[6] = {32, 16, 8, 4, 2, 1};  // steps per persistent-run graph
+constexpr size_t kBatchGraphCacheMax = 16;
+
 struct BatchGraph {
   int kind;  // 0 persistent, 1 per grid
   int nsteps;
   const double* start;
-  const double* log;
   int rows, wpb;
   bool persist, fit;
   hipGraph_t graph = nullptr;
@@ -191,6 +189,7 @@ struct fvm_batch {
   double* w_b = nullptr;
   double* cur = nullptr;
   unsigned char* scratch = nullptr;
+  const double* log_armed = nullptr;  // dt log the per-grid scratch currently points to
   hipStream_t stream = nullptr;
   bool bound = false, speeds_valid = false;
   int nitems = 0;
@@ -357,6 +356,7 @@ int fvm_batch_bind(fvm_batch* b, double* w_a, double* w_b, void* scratch, void* 
   b->stream = static_cast<hipStream_t>(stream);
   b->bound = true;
   b->speeds_valid = false;
+  b->log_armed = nullptr;
   int dev = 0, cus = 0, per_cu = 0;
   if (hipGetDevice(&dev) != hipSuccess) return FVM_EDEVICE;
   if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
@@ -409,29 +409,43 @@ int fvm_batch_cfl(fvm_batch* b) {
   return FVM_OK;
 }
 
-static int batch_graph(fvm_batch* b, int kind, int nsteps, double* log, int log_cap,
-                       hipGraphExec_t* exec) {
+// Points every grid's dt log at log + k (stride n, cap entries, cursors
+// rewound) for the steps enqueued next; null turns logging off.
+static int arm_batch_log(fvm_batch* b, double* log, int cap) {
+  if (!log && !b->log_armed) return FVM_OK;
+  if (launch_set_log(b->gscr(), b->n, log, cap, b->n, b->stream) != hipSuccess)
+    return FVM_EDEVICE;
+  b->log_armed = log;
+  return FVM_OK;
+}
+
+// The cached graph of `nsteps` steps of `kind` from buffer `start` in the
+// current tiling and schedule, moved to the front of the cache, or null.
+static BatchGraph* find_batch_graph(fvm_batch* b, int kind, int nsteps, const double* start) {
   for (auto it = b->graphs.begin(); it != b->graphs.end(); ++it) {
-    if (it->kind == kind && it->nsteps == nsteps && it->start == b->cur && it->log == log &&
+    if (it->kind == kind && it->nsteps == nsteps && it->start == start &&
         it->rows == b->rows && it->wpb == b->wpb && it->persist == b->persist &&
         it->fit == b->fit) {
       b->graphs.splice(b->graphs.begin(), b->graphs, it);
-      *exec = b->graphs.front().exec;
-      return FVM_OK;
+      return &b->graphs.front();
     }
   }
+  return nullptr;
+}
+
+static int build_batch_graph(fvm_batch* b, int kind, int nsteps, const double* start,
+                             hipGraphExec_t* exec) {
   BatchGraph c;
   c.kind = kind;
   c.nsteps = nsteps;
-  c.start = b->cur;
-  c.log = log;
+  c.start = start;
   c.rows = b->rows;
   c.wpb = b->wpb;
   c.persist = b->persist;
   c.fit = b->fit;
   if (hipGraphCreate(&c.graph, 0) != hipSuccess) return FVM_EDEVICE;
   hipGraphNode_t prev = nullptr;
-  const double* in = b->cur;
+  const double* in = start;
   auto add = [&](void* fn, dim3 grid, dim3 block, void* arg) -> bool {
     void* kp[] = {arg};
     hipKernelNodeParams np{};
@@ -458,8 +472,6 @@ static int batch_graph(fvm_batch* b, int kind, int nsteps, double* log, int log_
       a.grids = b->drecs();
       a.gscr = b->gscr();
       a.bscr = b->bscr();
-      a.dt_log = log;
-      a.dt_log_cap = log_cap;
       a.ngrids = b->n;
       a.nitems = b->nitems;
       a.dt_scale = kind == 2 ? 0.0 : 1.0;
@@ -474,9 +486,6 @@ static int batch_graph(fvm_batch* b, int kind, int nsteps, double* log, int log_
         a.win = in + r.offset;
         a.wout = out + r.offset;
         a.scr = b->gscr() + r.user;
-        a.dt_log = log ? log + r.user : nullptr;
-        a.dt_log_cap = log_cap;
-        a.dt_log_stride = b->n;
         a.mode = kDtAdaptive;
         a.g = r.g;
         // the single-grid kernel's workgroup tiles
@@ -499,7 +508,7 @@ static int batch_graph(fvm_batch* b, int kind, int nsteps, double* log, int log_
     return FVM_EDEVICE;
   }
   b->graphs.push_front(c);
-  while (b->graphs.size() > 8) {
+  while (b->graphs.size() > kBatchGraphCacheMax) {
     auto& x = b->graphs.back();
     (void)hipGraphExecDestroy(x.exec);
     (void)hipGraphDestroy(x.graph);
@@ -509,22 +518,56 @@ static int batch_graph(fvm_batch* b, int kind, int nsteps, double* log, int log_
   return FVM_OK;
 }
 
+static int batch_graph(fvm_batch* b, int kind, int nsteps, hipGraphExec_t* exec) {
+  if (BatchGraph* c = find_batch_graph(b, kind, nsteps, b->cur)) {
+    *exec = c->exec;
+    return FVM_OK;
+  }
+  return build_batch_graph(b, kind, nsteps, b->cur, exec);
+}
+
+// Persistent runs are cut into graphs of 32, 16, 8, 4, 2 and 1 steps; a miss
+// builds every chunk size from both ping-pong buffers, so a later run of any
+// length only replays cached graphs.
+static int batch_chunk_graph(fvm_batch* b, int n, hipGraphExec_t* exec) {
+  if (BatchGraph* c = find_batch_graph(b, 0, n, b->cur)) {
+    *exec = c->exec;
+    return FVM_OK;
+  }
+  for (const double* start : {static_cast<const double*>(b->other(b->cur)),
+                              static_cast<const double*>(b->cur)}) {
+    for (int m : kBatchChunks) {
+      if (start == b->cur && m == n) continue;  // built last: it heads the cache
+      hipGraphExec_t e;
+      if (!find_batch_graph(b, 0, m, start) && build_batch_graph(b, 0, m, start, &e) != FVM_OK)
+        return FVM_EDEVICE;
+    }
+  }
+  return build_batch_graph(b, 0, n, b->cur, exec);
+}
+
 static int batch_run(fvm_batch* b, int kind, int nsteps, double* log) {
   if (!b || !b->bound || nsteps < 0) return FVM_EINVAL;
   int rc = FVM_OK;
   if (!b->speeds_valid) rc = fvm_batch_cfl(b);
+  if (rc == FVM_OK) rc = arm_batch_log(b, log, nsteps);
   if (rc) return rc;
-  if (log) {
-    hipLaunchKernelGGL(batch_log_rewind_kernel, dim3((b->n + 63) / 64), dim3(64), 0, b->stream,
-                       b->gscr(), b->n);
-    if (hipGetLastError() != hipSuccess) return FVM_EDEVICE;
-  }
-  const int chunk = kind == 0 ? 32 : 2;
   int done = 0;
   while (done < nsteps) {
-    const int n = std::min(chunk, nsteps - done);
+    const int left = nsteps - done;
+    int n = std::min(2, left);
     hipGraphExec_t exec;
-    rc = batch_graph(b, kind, n, log, log ? nsteps : 0, &exec);
+    if (kind == 0) {
+      n = 1;
+      for (int m : kBatchChunks)
+        if (m <= left) {
+          n = m;
+          break;
+        }
+      rc = batch_chunk_graph(b, n, &exec);
+    } else {
+      rc = batch_graph(b, kind, n, &exec);
+    }
     if (rc) return rc;
     if (hipGraphLaunch(exec, b->stream) != hipSuccess) return FVM_EDEVICE;
     if (n % 2) b->cur = b->other(b->cur);
@@ -607,10 +650,11 @@ int fvm_batch_autotune(fvm_batch* b, const char* cache_path) {
     b->fit = ft;
     for (int r : {8, 16, 32, 48, 64, 96, 128}) {
       rc = fvm_batch_set_tiling(b, r, w);
+      if (rc == FVM_OK) rc = arm_batch_log(b, nullptr, 0);
       if (rc) break;
       hipGraphExec_t exec;
       const int n = 4;
-      rc = batch_graph(b, 2, n, nullptr, 0, &exec);
+      rc = batch_graph(b, 2, n, &exec);
       if (rc) break;
       bool ok = hipGraphLaunch(exec, b->stream) == hipSuccess;
       ok = ok && hipEventRecord(e0, b->stream) == hipSuccess;

@@ -39,6 +39,8 @@ enum : int {
 };
 
 // Per-grid device scratch (256-byte aligned, cleared by the init kernel).
+// The dt log of a run lives here too, set by a small kernel before the run's
+// steps, so that cached graphs of steps do not depend on the log buffer.
 struct alignas(256) GridScratch {
   unsigned long long smax[2];  // running maxima (bit patterns) of the state being produced
   unsigned int arrive;         // arrival counter of the current launch
@@ -49,6 +51,9 @@ struct alignas(256) GridScratch {
   double cur_sx, cur_sy;       // finalized maxima of the current state
   double zero;                 // always 0: the dt of the tuner's dry-run steps
   double pad1;
+  double* log;                 // dt log of the current run (null: none)
+  int log_cap;                 // entries the log holds
+  int log_stride;              // elements between consecutive logged dts
 };
 static_assert(sizeof(GridScratch) == 256, "scratch layout");
 
@@ -105,13 +110,10 @@ struct StepArgs {
   double* wout;
   const double* ug;           // spray gas velocity (2 planes) or null
   GridScratch* scr;
-  double* dt_log;             // nullable
-  int dt_log_cap;
   int mode;
+  int k;                      // kDtArray index
   double dt_arg;              // kDtFixedCheck
   const double* dts;          // kDtArray
-  int k;                      // kDtArray index
-  int dt_log_stride;          // elements between consecutive logged dts
   GridGeom g;
   Tiling t;
   ModelConsts m;
@@ -172,8 +174,6 @@ struct BatchArgs {
   const BatchGrid* grids;     // device array of n records
   GridScratch* gscr;          // device array of n per-grid scratch blocks
   BatchScratch* bscr;
-  double* dt_log;             // nullable, dt_log[step * ngrids + grid]
-  int dt_log_cap;             // steps the log can hold
   int ngrids;                 // records sorted by item0 (tallest row blocks first)
   int nitems;                 // work items of all grids
   double dt_scale;            // 1; 0 for the tuner's dry runs (state unchanged)

@@ -83,7 +83,7 @@ __global__ FVM_STEP_BOUNDS(WPB) void step_kernel(StepArgs a) {
   if constexpr (M::kCommit) {
     if (block_commit<WPB>(bx, by, a.scr, gridDim.x) && threadIdx.x == 0) {
       if (cfl_fail) atomicOr(&a.scr->status, kStatusCfl);
-      finalize_grid(a.scr, a.g, dt_eff, a.dt_log, a.dt_log_cap, a.dt_log_stride, nullptr);
+      finalize_grid(a.scr, a.g, dt_eff, true, nullptr);
     }
   }
 }
@@ -105,7 +105,7 @@ __global__ __launch_bounds__(256) void cfl_kernel(CflArgs a) {
     by = umax64(by, bits(sy));
   }
   if (block_commit<4>(bx, by, a.scr, gridDim.x) && threadIdx.x == 0)
-    finalize_grid(a.scr, a.g, 0.0, nullptr, 0, 1, a.dt_out);
+    finalize_grid(a.scr, a.g, 0.0, false, a.dt_out);
 }
 
 __global__ void clear_scratch_kernel(GridScratch* s, int n) {
@@ -116,7 +116,18 @@ __global__ void clear_scratch_kernel(GridScratch* s, int n) {
   }
 }
 
-__global__ void clear_log_cursor_kernel(GridScratch* s) { s->nstep = 0; }
+// Sets the dt log of the next run on n grids' scratch blocks: grid k logs
+// into base + k every `stride` elements, at most cap entries; base == null
+// turns logging off. Rewinds the cursors.
+__global__ void set_log_kernel(GridScratch* s, int n, double* base, int cap, int stride) {
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k < n) {
+    s[k].log = base ? base + k : nullptr;
+    s[k].log_cap = base ? cap : 0;
+    s[k].log_stride = stride;
+    s[k].nstep = 0;
+  }
+}
 
 }  // namespace fvm
 
@@ -200,8 +211,10 @@ hipError_t launch_clear_scratch(GridScratch* s, int n, hipStream_t st) {
   return hipGetLastError();
 }
 
-hipError_t launch_clear_log_cursor(GridScratch* s, hipStream_t st) {
-  hipLaunchKernelGGL(clear_log_cursor_kernel, dim3(1), dim3(1), 0, st, s);
+hipError_t launch_set_log(GridScratch* s, int n, double* base, int cap, int stride,
+                          hipStream_t st) {
+  hipLaunchKernelGGL(set_log_kernel, dim3((n + 63) / 64), dim3(64), 0, st, s, n, base, cap,
+                     stride);
   return hipGetLastError();
 }
 

@@ -264,7 +264,7 @@ __global__ __launch_bounds__(kMeThreads) FVM_MAXENT_ATTR void maxent_source_kern
   }
   if (block_commit<kMeThreads / kWave>(bx, by, a.scr, gridDim.x) && threadIdx.x == 0) {
     if (cfl_fail) atomicOr(&a.scr->status, kStatusCfl);
-    finalize_grid(a.scr, a.g, dte, a.dt_log, a.dt_log_cap, a.dt_log_stride, nullptr);
+    finalize_grid(a.scr, a.g, dte, true, nullptr);
   }
 }
 

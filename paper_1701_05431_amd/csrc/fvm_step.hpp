@@ -426,9 +426,10 @@ __device__ __forceinline__ double next_dt(const GridGeom& g, double sx, double s
 }
 
 // Called by the last workgroup of a launch: reads and clears the maxima,
-// records the current state's maxima and the next dt, logs the dt used.
+// records the current state's maxima and the next dt, and for a step
+// (log_step) appends the dt used to the run's dt log if it has one.
 __device__ inline void finalize_grid(GridScratch* s, const GridGeom& g, double dt_used,
-                                     double* dt_log, int cap, int stride, double* dt_out) {
+                                     bool log_step, double* dt_out) {
   const double sx = __longlong_as_double(static_cast<long long>(atomicExch(&s->smax[0], 0ull)));
   const double sy = __longlong_as_double(static_cast<long long>(atomicExch(&s->smax[1], 0ull)));
   unsigned int st = 0;
@@ -439,9 +440,11 @@ __device__ inline void finalize_grid(GridScratch* s, const GridGeom& g, double d
   s->cur_sy = sy;
   s->dt = dtn;
   if (st) atomicOr(&s->status, st);
-  if (dt_log) {
+  double* const dt_log = s->log;
+  if (log_step && dt_log) {
     const unsigned int n = s->nstep;
-    if (n < static_cast<unsigned int>(cap)) dt_log[static_cast<size_t>(n) * stride] = dt_used;
+    if (n < static_cast<unsigned int>(s->log_cap))
+      dt_log[static_cast<size_t>(n) * s->log_stride] = dt_used;
     s->nstep = n + 1;
   }
   if (dt_out) *dt_out = dtn;

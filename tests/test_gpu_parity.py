@@ -624,6 +624,8 @@ def test_paper_test_cases_converge_on_gpu(case):
         W = gpu_state(s)
         if n == 128:
             ref = orc.run_dts(oparams(p), W0, [T / steps] * steps)
+            print(f"{case} 128^2, {steps} fixed steps: rel Linf vs oracle "
+                  f"{rel_linf(W, ref):.2e}", flush=True)
             assert rel_linf(W, ref) <= 1e-11, rel_linf(W, ref)
         e = W[0] - fn(n, n, T)[0]
         errs.append((np.mean(np.abs(e)), math.sqrt(np.mean(e * e))))
@@ -873,6 +875,8 @@ def test_fvrun_gradient_matches_oracle_and_fd():
     lamN = np.zeros_like(W0)
     lamN[0] = WN[0] - inputs.adjoint_target_density(n, n, 0)
     gref = orc.adjoint_run(P, W0, odts, lamN)
+    print(f"euler gradient 32^2 x 30 steps: rel Linf vs oracle {rel_linf(g, gref):.2e}",
+          flush=True)
     assert rel_linf(g, gref) <= 1e-10
     # central differences with the forward dts frozen
     def L(W):
@@ -903,7 +907,9 @@ def test_fvrun_gradient_with_dirichlet_boundaries():
     WN, odts = orc.run(P, W0, 20)
     lamN = np.zeros_like(W0)
     lamN[0] = WN[0] - inputs.adjoint_target_density(n, n, 9)
-    assert rel_linf(g, orc.adjoint_run(P, W0, odts, lamN)) <= 1e-10
+    e = rel_linf(g, orc.adjoint_run(P, W0, odts, lamN))
+    print(f"dirichlet gradient 40^2 x 20 steps: rel Linf vs oracle {e:.2e}", flush=True)
+    assert e <= 1e-10
 
 
 def _spray_adjoint_case(nx, ny, seed):
@@ -960,7 +966,7 @@ def test_spray_adjoint_step(bc, theta):
 @pytest.mark.parametrize("nx,ny", [(1, 1), (1, 6), (2, 5), (63, 3), (64, 4), (65, 9),
                                    (129, 7), (300, 2)])
 def test_spray_adjoint_covers_every_cell(nx, ny, bc):
-    """The spray adjoint's 64 x 4 cell tiles cover every cell of ragged grids,
+    """The spray adjoint's 64 x 16 cell tiles cover every cell of ragged grids,
     periodic wrap onto the cell itself (nx = 1) included."""
     print(f"spray adjoint cells nx={nx} ny={ny} bc={bc}", flush=True)
     W, ug = _spray_adjoint_case(nx, ny, nx + ny)
@@ -978,7 +984,7 @@ def test_spray_adjoint_covers_every_cell(nx, ny, bc):
     assert rel_linf(got[:, :, :nx].cpu().numpy(), ref) <= TOL
 
 
-@pytest.mark.parametrize("bc", [0, 2])
+@pytest.mark.parametrize("bc", [0, 1, 2])
 def test_fvrun_spray_gradient(bc):
     """The differentiable spray run: the checkpointed GPU adjoint (forward
     recomputation with the fused source, then the spray adjoint steps)
@@ -1010,10 +1016,14 @@ def test_fvrun_spray_gradient(bc):
     assert torch.equal(Yr, Y) and np.array_equal(Xr.grad.cpu().numpy(), g)
     P = oparams(p, gh)
     WN, odts = orc.run(P, W0, 12, ug)
-    assert rel_linf(Y.detach().cpu().numpy(), WN) <= 1e-11
+    ey = rel_linf(Y.detach().cpu().numpy(), WN)
     lamN = np.zeros_like(W0)
     lamN[0] = WN[0] - tgt_np
-    assert rel_linf(g, orc.adjoint_run(P, W0, odts, lamN, ug)) <= 1e-10
+    eg = rel_linf(g, orc.adjoint_run(P, W0, odts, lamN, ug))
+    print(f"spray bc={bc} 40^2 x 12 steps: rel Linf state {ey:.2e}, gradient {eg:.2e}",
+          flush=True)
+    assert ey <= 1e-11
+    assert eg <= 1e-10
     def L(W):
         out = orc.run_dts(P, W, odts, ug)
         return 0.5 * np.sum((out[0] - tgt_np) ** 2)

@@ -13,6 +13,7 @@ import numpy as np
 import pytest
 
 from oracle import bruteforce as bf
+from fd_gate import adjoint_fd_gate, check_fd_gate
 from paper_1701_05431_amd import inputs
 
 GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
@@ -678,6 +679,63 @@ def test_nonfinite_and_nonphysical_states(orc, what):
     assert rc == orc.ENONFINITE
 
 
+def test_zero_speeds_take_dt_max(orc):
+    """Sec. 2.2.1 eq. CFL_cond bounds dt by the largest speed; with every
+    speed zero it bounds nothing, and the adaptive step is the caller's
+    dt_max exactly (not C/0 = inf, not 0). Advection with a = (0, 0) leaves
+    the state unchanged bit for bit and logs dt_max every step; a spray at
+    rest (q = 0) has zero speeds too. With one speed zero the formula keeps
+    only the other term."""
+    n = 16
+    u0 = inputs.advection_state(n, n, 3)
+    P = orc.params(orc.ADV, n, n, ax=0.0, ay=0.0, cfl=0.9, dt_max=0.0625)
+    assert orc.cfl(P, u0) == (0.0, 0.0, 0.0625)
+    W, dts = orc.run(P, u0, 3)
+    assert np.array_equal(W, u0) and np.array_equal(dts, [0.0625] * 3)
+    P.ay = 0.5
+    sx, sy, dt = orc.cfl(P, u0)
+    assert (sx, sy) == (0.0, 0.5) and dt == 0.9 / (0.5 * n)
+    Ws, ug = inputs.spray_state(n, n, 4)
+    Ws = Ws.copy()
+    Ws[4:] = 0.0
+    Ps = orc.params(orc.SPRAY, n, n, cfl=0.9, dt_max=0.01)
+    assert orc.cfl(Ps, Ws) == (0.0, 0.0, 0.01)
+
+
+def test_zero_speeds_without_dt_max_are_an_error(orc):
+    """dt_max = 0 (unset) with all speeds zero: no time step exists, and the
+    oracle reports an invalid argument instead of stepping."""
+    n = 8
+    u0 = inputs.advection_state(n, n, 1)
+    P = orc.params(orc.ADV, n, n, ax=0.0, ay=0.0, dt_max=0.0)
+    with pytest.raises(orc.OracleError) as e:
+        orc.cfl(P, u0)
+    assert e.value.code == orc.EINVAL
+    rc, W, _ = orc.run(P, u0, 2, return_status=True)
+    assert rc == orc.EINVAL and np.array_equal(W, u0)
+
+
+@pytest.mark.parametrize("k", [0, 1, 2, 3])
+def test_negative_spray_moment_is_reported(orc, k):
+    """A size moment m_{k/2} < 0 is outside the moment space (Sec. 6.1): the
+    checkTimeStep of the oracle rejects the state as non-physical, before
+    any step, and leaves it unchanged."""
+    n = 8
+    W, ug = inputs.spray_state(n, n, 5)
+    W = W.copy()
+    W[k, 2, 5] = -1e-9 * abs(W[k, 2, 5])
+    P = orc.params(orc.SPRAY, n, n, cfl=0.9)
+    with pytest.raises(orc.OracleError) as e:
+        orc.cfl(P, W)
+    assert e.value.code == orc.ENONFINITE
+    rc, got, _ = orc.run(P, W, 1, ug, return_status=True)
+    assert rc == orc.ENONFINITE and np.array_equal(got, W)
+    bad, _, _ = orc.cell_speeds(P, W[:, 2, 5])
+    assert bad
+    W[k, 2, 5] = 0.0  # zero moments are admissible (vacuum)
+    assert not orc.cell_speeds(P, W[:, 2, 5])[0]
+
+
 def test_validation(orc):
     assert orc.validate(orc.params(orc.EULER, 10, 10, npx=3)) == orc.EINVAL
     assert orc.validate(orc.params(7, 10, 10)) == orc.EINVAL
@@ -825,3 +883,15 @@ def test_euler_adjoint_central_differences(orc):
         eps = 1e-6
         fd = (loss(W0 + eps * v) - loss(W0 - eps * v)) / (2 * eps)
         assert abs(np.sum(g * v) - fd) <= 1e-6 * max(1.0, abs(fd))
+
+
+def test_adjoint_central_differences_on_the_adjoint_workload(orc):
+    """The oracle's adjoint (Sec. 2.2.1 scheme, transposed by hand) against
+    central differences of its own forward steps on the adjoint workload's
+    construction at 32^2: 100 steps, 32 random directions and 256 random
+    single coordinates, each within 1e-6 of the largest finite difference."""
+    P, W0, dts, lamN, dirs, fd_dir, coords, fd_coord = adjoint_fd_gate(orc)
+    g = orc.adjoint_run(P, W0, dts, lamN)
+    e_dir, e_coord = check_fd_gate(g, dirs, fd_dir, coords, fd_coord)
+    print(f"adjoint FD gate 32^2 x 100 steps: rel err directions {e_dir:.2e}, "
+          f"coordinates {e_coord:.2e}")
