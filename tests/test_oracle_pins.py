@@ -895,3 +895,74 @@ def test_adjoint_central_differences_on_the_adjoint_workload(orc):
     e_dir, e_coord = check_fd_gate(g, dirs, fd_dir, coords, fd_coord)
     print(f"adjoint FD gate 32^2 x 100 steps: rel err directions {e_dir:.2e}, "
           f"coordinates {e_coord:.2e}")
+
+
+@pytest.mark.parametrize("bc", [0, 1])
+def test_spray_uniform_state_without_source_is_fixed_point(orc, bc):
+    """Spray transport with the source off (K = 0, no drag): a uniform state
+    has the same kinetic flux on every face, so its differences vanish
+    exactly and the state stays bit for bit unchanged (Sec. 2.2.1
+    eq. VF_scheme), also on a moving spray and at rest."""
+    n = 12
+    for ux, uy in ((0.3, -0.2), (-0.4, 0.0), (0.0, 0.0)):
+        m = [1.1, 0.4, 0.17, 0.08]
+        w = np.array(m + [m[2] * ux, m[2] * uy])
+        W = np.broadcast_to(w[:, None, None], (6, n, n)).copy()
+        ug = np.stack([np.full((n, n), 0.3), np.full((n, n), -0.7)])
+        P = orc.params(orc.SPRAY, n, n, bc=bc, npx=3, npy=2, K=0.0, theta=float("inf"),
+                       cfl=0.9, dt_max=0.01)
+        got, dts = orc.run(P, W, 4, ug=ug)
+        assert np.array_equal(got, W)
+        assert all(d > 0 for d in dts)
+
+
+def _rusanov_row(W, gamma, dt_dx, bc):
+    """A textbook 1-D Rusanov (local Lax-Friedrichs) step of one grid row of
+    the Euler equations, written independently of the oracle: numerical flux
+    (F(W_L) + F(W_R))/2 - s/2 (W_R - W_L) with s the larger of |u| + c on the
+    two sides, the transverse momentum carried passively by u."""
+    rho, mx, my, E = W
+    u, v = mx / rho, my / rho
+    p = (gamma - 1.0) * (E - 0.5 * rho * (u * u + v * v))
+    c = np.sqrt(gamma * p / rho)
+    F = np.stack([mx, mx * u + p, my * u, (E + p) * u])
+    s = np.abs(u) + c
+    if bc == 0:  # periodic: the left neighbour of cell 0 is the last cell
+        WL, FL, sL = np.roll(W, 1, axis=1), np.roll(F, 1, axis=1), np.roll(s, 1)
+        WR, FR, sR = W, F, s
+        face = 0.5 * (FL + FR) - 0.5 * np.maximum(sL, sR) * (WR - WL)   # face i - 1/2
+        east = np.roll(face, -1, axis=1)
+    else:        # zero-gradient ghosts
+        Wg = np.concatenate([W[:, :1], W, W[:, -1:]], axis=1)
+        Fg = np.concatenate([F[:, :1], F, F[:, -1:]], axis=1)
+        sg = np.concatenate([s[:1], s, s[-1:]])
+        face = 0.5 * (Fg[:, :-1] + Fg[:, 1:]) - 0.5 * np.maximum(sg[:-1], sg[1:]) * (
+            Wg[:, 1:] - Wg[:, :-1])                                     # faces -1/2 .. n-1/2
+        east = face[:, 1:]
+        face = face[:, :-1]
+    return W - dt_dx * (east - face), np.max(s), np.max(np.abs(v) + c)
+
+
+@pytest.mark.parametrize("bc", [0, 1])
+def test_x_only_data_reduce_to_the_textbook_one_dimensional_step(orc, bc):
+    """Euler data that vary only along x: the y-faces carry equal fluxes, so
+    every row of the 2-D step is a 1-D Rusanov step of that row
+    (Sec. 2.2.1 eq. VF_scheme), here written out independently, with the
+    oracle's own dt; that dt is the adaptive step C / (Sx/dx + Sy/dy) of the
+    row's speeds. Three steps, each from the oracle's previous state; the
+    y-direction speeds only enter through dt."""
+    nx, ny = 48, 10
+    prim = inputs.riemann_primitives(nx, 2, 3)
+    row = inputs.conservative_from_primitive(*(a[:1] for a in prim))
+    W = np.broadcast_to(row, (4, ny, nx)).copy()
+    P = orc.params(orc.EULER, nx, ny, bc=bc, npx=4, npy=2, cfl=0.45)
+    for _ in range(3):
+        got, dts = orc.run(P, W, 1)
+        sx, sy = _rusanov_row(W[:, 0, :], 1.4, 0.0, bc)[1:]
+        assert dts[0] == pytest.approx(0.45 / (sx * nx + sy * ny), rel=1e-15)
+        ref, _, _ = _rusanov_row(W[:, 0, :], 1.4, dts[0] * nx, bc)
+        # the textbook step evaluates each face once in the same order as
+        # the oracle, so the rows agree bit for bit
+        for j in range(ny):
+            assert np.array_equal(got[:, j], ref)
+        W = got
