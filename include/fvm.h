@@ -227,6 +227,35 @@ int fvm_run_fixed(fvm_grid* g, int nsteps, double dt);
 int fvm_run_ckpt(fvm_grid* g, int nsteps, int ckpt_every,
                  double* const* ckpts, double* dts_dev);
 
+/* For callers that cannot allocate (code under HIP graph capture, tight
+ * serving loops, harnesses that forbid allocation): fvm_run without a plan
+ * and without a scratch buffer. It allocates nothing, host or device, and
+ * builds no graph: it enqueues plain kernel launches on `stream` (hipStream_t
+ * as void*, NULL = null stream) and returns.
+ *   p         : parameters as for fvm_create; periodic or transmissive
+ *               boundaries and the lognormal closure (FVM_EUNSUPPORTED for
+ *               Dirichlet boundaries and the entropy closure);
+ *   w_a, w_b  : two state buffers as for fvm_bind; w_a holds W^0 on entry.
+ *               Step k reads one and writes the other, so W^nsteps ends in
+ *               w_a if nsteps is even and in w_b if it is odd;
+ *   ug        : the spray's gas velocity (as for fvm_bind), NULL otherwise;
+ *   dts_dev   : nullable device array of >= nsteps doubles, receives
+ *               dt_0 .. dt_{nsteps-1};
+ *   status_dev: nullable device int, receives at the end FVM_OK,
+ *               FVM_ENONFINITE (a non-finite or non-physical state) or
+ *               FVM_EINVAL (every speed zero and dt_max == 0).
+ * The steps, tile shape and results are those of fvm_run with the default
+ * tiling (bitwise: the result does not depend on the tiling). The scratch
+ * block (fvm_scratch_bytes(p) bytes, at most 256) lives in a static device
+ * array of 256 bytes per device, kept until the process ends; parameters
+ * needing more are rejected with FVM_EINVAL. Each call clears it with a
+ * kernel before its steps. Calls that overlap on one device (several host
+ * threads, or several streams in flight) share that array and race.
+ * Invalid arguments are rejected before anything is enqueued. */
+int fvm_run_noalloc(const fvm_params* p, double* w_a, double* w_b,
+                    const double* ug, int nsteps, double* dts_dev,
+                    int* status_dev, void* stream);
+
 /* Waits for the stream and returns the sticky device status. */
 int fvm_sync(fvm_grid* g);
 

@@ -11,6 +11,7 @@
 #include <cstdio>
 #include <fstream>
 #include <list>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -1074,6 +1075,112 @@ int fvm_adjoint_run(fvm_grid* g, double* const* ckpts, int ckpt_every, const dou
                                   g->stream));
   }
   return FVM_OK;
+}
+
+}  // extern "C"
+
+// ---- adaptive run without any allocation -------------------------------------
+// fvm_run_noalloc keeps the grid's scratch block (speed maxima, arrival
+// counter, next dt, status word, dt-log cursor) in this file-scope device
+// array instead of a caller buffer. Host code never passes the array's name
+// to a kernel (on the host it is only a stand-in for the symbol): the first
+// call on a device looks up the array's device address with
+// hipGetSymbolAddress, with that device current, and every launch takes that
+// address. Each device holds its own copy until the process ends; calls
+// that overlap on one device share it and race.
+namespace {
+
+constexpr size_t kNoAllocScratchBytes = sizeof(GridScratch);  // one grid's block
+constexpr int kNoAllocMaxDevices = 64;
+
+__device__ __align__(256) unsigned char scratch[kNoAllocScratchBytes];
+
+std::mutex g_noalloc_mu;
+void* g_noalloc_ptr[kNoAllocMaxDevices] = {};
+
+// Device address of `scratch` on device `dev` (current), or null on error.
+void* noalloc_scratch(int dev) {
+  if (dev < 0 || dev >= kNoAllocMaxDevices) return nullptr;
+  std::lock_guard<std::mutex> lock(g_noalloc_mu);
+  if (!g_noalloc_ptr[dev]) {
+    void* ptr = nullptr;
+    if (hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)) != hipSuccess || !ptr) return nullptr;
+    if (reinterpret_cast<uintptr_t>(ptr) & 255) return nullptr;
+    g_noalloc_ptr[dev] = ptr;
+  }
+  return g_noalloc_ptr[dev];
+}
+
+// Writes the status code of the sticky bits (FVM_OK, FVM_ENONFINITE,
+// FVM_EINVAL) to *out.
+__global__ void noalloc_status_kernel(const GridScratch* s, int* out) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) {
+    const unsigned int st = s->status;
+    *out = (st & kStatusNonFinite) ? FVM_ENONFINITE
+                                   : ((st & kStatusCfl) ? FVM_ECFL
+                                                        : ((st & kStatusDt) ? FVM_EINVAL : FVM_OK));
+  }
+}
+
+}  // namespace
+
+extern "C" {
+
+int fvm_run_noalloc(const fvm_params* p, double* w_a, double* w_b, const double* ug,
+                    int nsteps, double* dts_dev, int* status_dev, void* stream) {
+  if (!valid_params(p) || !w_a || !w_b || w_a == w_b || nsteps < 0) return FVM_EINVAL;
+  if ((reinterpret_cast<uintptr_t>(w_a) & 7) || (reinterpret_cast<uintptr_t>(w_b) & 7))
+    return FVM_EINVAL;
+  if ((p->model == FVM_SPRAY) != (ug != nullptr)) return FVM_EINVAL;
+  if (p->bc == FVM_DIRICHLET || p->closure != FVM_CLOSURE_LOGNORMAL) return FVM_EUNSUPPORTED;
+  if (fvm_scratch_bytes(p) > kNoAllocScratchBytes) return FVM_EINVAL;  // beyond the array
+  int dev = -1;
+  if (hipGetDevice(&dev) != hipSuccess) return FVM_EDEVICE;
+  GridScratch* scr = static_cast<GridScratch*>(noalloc_scratch(dev));
+  if (!scr) return FVM_EDEVICE;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+
+  const GridGeom geom = grid_geometry(*p);
+  const ModelConsts mc = model_consts(*p);
+  auto al16 = [](const void* q) { return (reinterpret_cast<uintptr_t>(q) & 15) == 0; };
+  const int cpl = p->ld % 2 == 0 && al16(w_a) && al16(w_b) && (!ug || al16(ug)) ? 2 : 1;
+  int rows = kDefaultRows, wpb = kDefaultWpb;
+  default_tiling(*p, cpl, &rows, &wpb);
+
+  // clear the block (a kernel, not a memset), maxima and dt of w_a, arm the log
+  int rc = dev_err(launch_clear_scratch(scr, 1, st));
+  if (rc) return rc;
+  CflArgs c{};
+  c.w = w_a;
+  c.scr = scr;
+  c.g = geom;
+  c.m = mc;
+  const long long cells = static_cast<long long>(p->nx) * p->ny;
+  c.nblocks = static_cast<int>(std::min<long long>(2048, (cells + 255) / 256));
+  rc = dev_err(launch_cfl(c, p->model, st));
+  if (rc == FVM_OK) rc = dev_err(launch_set_log(scr, 1, dts_dev, nsteps, 1, st));
+  if (rc) return rc;
+  StepArgs a{};
+  a.ug = ug;
+  a.scr = scr;
+  a.mode = kDtAdaptive;
+  a.g = geom;
+  a.t = tiling(geom, rows, wpb, cpl);
+  a.m = mc;
+  const double* in = w_a;
+  for (int k = 0; k < nsteps; ++k) {
+    double* out = in == w_a ? w_b : w_a;
+    a.win = in;
+    a.wout = out;
+    rc = dev_err(launch_step(a, p->model, st));
+    if (rc) return rc;
+    in = out;
+  }
+  if (status_dev) {
+    hipLaunchKernelGGL(noalloc_status_kernel, dim3(1), dim3(64), 0, st, scr, status_dev);
+    rc = dev_err(hipGetLastError());
+  }
+  return rc;
 }
 
 }  // extern "C"

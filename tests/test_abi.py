@@ -157,3 +157,28 @@ def test_batch_create_validation(L):
     assert L.fvm_batch_create(1, sp, (C.c_size_t * 1)(0), C.byref(h)) == _lib.FVM_EUNSUPPORTED
     dp = (_lib.Params * 1)(params_from(model=1, nx=8, ny=8, bc=_lib.FVM_DIRICHLET))
     assert L.fvm_batch_create(1, dp, (C.c_size_t * 1)(0), C.byref(h)) == _lib.FVM_EUNSUPPORTED
+
+
+def test_noalloc_run_rejects_arguments_on_the_host(L):
+    """fvm_run_noalloc refuses invalid arguments before any HIP call (these
+    pointers are never dereferenced)."""
+    from paper_1701_05431_amd import _lib
+    from paper_1701_05431_amd.solver import params_from
+    a, b, u = C.c_void_p(4096), C.c_void_p(8192), C.c_void_p(1 << 20)
+    f = L.fvm_run_noalloc
+    eu = params_from(model=1, nx=64, ny=32)
+    assert f(None, a, b, None, 3, None, None, None) == _lib.FVM_EINVAL
+    assert f(eu, None, b, None, 3, None, None, None) == _lib.FVM_EINVAL
+    assert f(eu, a, None, None, 3, None, None, None) == _lib.FVM_EINVAL
+    assert f(eu, a, a, None, 3, None, None, None) == _lib.FVM_EINVAL
+    assert f(eu, a, b, None, -1, None, None, None) == _lib.FVM_EINVAL
+    assert f(eu, C.c_void_p(4100), b, None, 3, None, None, None) == _lib.FVM_EINVAL
+    assert f(eu, a, b, u, 3, None, None, None) == _lib.FVM_EINVAL       # ug for Euler
+    assert f(params_from(model=1, nx=64, ny=32, npart_x=3), a, b, None, 3, None, None,
+             None) == _lib.FVM_EINVAL
+    sp = params_from(model=2, nx=8, ny=8)
+    assert f(sp, a, b, None, 3, None, None, None) == _lib.FVM_EINVAL    # spray without ug
+    dp = params_from(model=1, nx=64, ny=32, bc=_lib.FVM_DIRICHLET)
+    assert f(dp, a, b, None, 3, None, None, None) == _lib.FVM_EUNSUPPORTED
+    me = params_from(model=2, nx=8, ny=8, closure=_lib.FVM_CLOSURE_MAXENT)
+    assert f(me, a, b, u, 3, None, None, None) == _lib.FVM_EUNSUPPORTED
