@@ -1069,8 +1069,10 @@ static void num_flux_jacobians(const orc_params* P, const double* wl,
     }
 }
 
-/* J = dS/dW of the spray source (Sec. 6.1 eq. Essadki) with the lognormal
- * closure (reading R6), differentiated by hand: with
+/* J = dS/dW of the spray source (Sec. 6.1 eq. Essadki), differentiated by
+ * hand; for the entropy-maximising closure (Sec. 6.2) the two closure rows
+ * follow from the optimality conditions of its dual (below); with the
+ * lognormal closure (reading R6):
  * L1 = ln(m_{1/2}/m_0), L2 = ln(m_{2/2}/m_0), s^2 = 4 (L2 - 2 L1) (a constant
  * where it is clipped at 1e-8), mu = 2 L1 - s^2/4,
  *   d ln m_{-1/2} = dm_0/m_0 - dmu/2 + ds^2/8,
@@ -1095,6 +1097,36 @@ static void spray_source_jacobian(const orc_params* P, const double* w,
   J[2][0] = -K;
   J[3][1] = -1.5 * K;
   if (K == 0.0) return;
+  if (P->closure == 1) {
+    /* The entropy maximiser's multipliers are fixed by the optimality
+     * conditions F_k(lambda, m) = mu_{k+1}(lambda) - m_{k/2} = 0, whose
+     * Jacobian in lambda is the Hessian H_kl = mu_{k+l+1} and in m is -I, so
+     * d lambda / d m = H^{-1} (implicit function theorem). With
+     * n(S=0) = exp(lambda_0) and m_{-1/2} = int S^{-1/2} n dS,
+     *   d n0 / d lambda = (n0, 0, 0, 0),
+     *   d m_{-1/2} / d lambda_l = int S^{-1/2} x^l n dS = mu_l,
+     * so each row is H^{-1} applied to that gradient (H is symmetric). */
+    double lam[4], mmh, n0, mu[8], H[4][4], g0[4], g1[4], a[4], b[4];
+    if (orc_maxent(w, lam, &mmh, &n0)) {
+      for (int l = 0; l < 4; ++l) J[0][l] = J[1][l] = NAN;
+      return;
+    }
+    maxent_moments(lam, mu);
+    for (int k = 0; k < 4; ++k) {
+      for (int l = 0; l < 4; ++l) H[k][l] = mu[k + l + 1];
+      g0[k] = k == 0 ? n0 : 0.0;
+      g1[k] = mu[k];
+    }
+    if (spd_solve4(H, g0, a) || spd_solve4(H, g1, b)) {
+      for (int l = 0; l < 4; ++l) J[0][l] = J[1][l] = NAN;
+      return;
+    }
+    for (int l = 0; l < 4; ++l) {
+      J[0][l] = -K * a[l];
+      J[1][l] = -(K / 2.0) * b[l];
+    }
+    return;
+  }
   double mmh, n0;
   lognormal_closure(P, w, &mmh, &n0);
   double L1 = log(m1 / m0), L2 = log(m2 / m0);
@@ -1173,7 +1205,6 @@ int orc_adjoint_step(const orc_params* P, const double* W, const double* ug,
   int rc = orc_validate(P);
   if (rc) return rc;
   int spray = P->model == ORC_SPRAY;
-  if (spray && P->closure != 0) return ORC_EUNSUPPORTED;
   if (spray && !ug) return ORC_EINVAL;
   int nv = orc_nvar(P->model), nx = P->nx, ny = P->ny;
   size_t plane = (size_t)nx * ny;
@@ -1256,7 +1287,6 @@ int orc_adjoint_run(const orc_params* P, const double* W0, const double* ug,
 {
   int rc = orc_validate(P);
   if (rc) return rc;
-  if (P->model == ORC_SPRAY && P->closure != 0) return ORC_EUNSUPPORTED;
   if (P->model == ORC_SPRAY && !ug) return ORC_EINVAL;
   int nv = orc_nvar(P->model);
   size_t n = (size_t)nv * P->nx * P->ny;

@@ -966,3 +966,76 @@ def test_x_only_data_reduce_to_the_textbook_one_dimensional_step(orc, bc):
         for j in range(ny):
             assert np.array_equal(got[:, j], ref)
         W = got
+
+
+def test_maxent_spray_adjoint_source_jacobian_by_columns(orc):
+    """The spray adjoint through the entropy-maximising closure (Sec. 6.2):
+    on a 1 x 1 periodic grid one step is W + dt S(W), so its adjoint is
+    (I + dt J_S)^T, whose closure rows come from the dual's optimality
+    conditions; compared column by column with central differences of the
+    oracle's own step (each evaluation a fresh Newton solve), for
+    lognormal-moment states and steep exp-cubic densities."""
+    ug = np.array([0.3, -0.2]).reshape(2, 1, 1)
+    P = orc.params(orc.SPRAY, 1, 1, bc=orc.PERIODIC, K=0.8, closure=1)
+    m = inputs.lognormal_moments(1.2, math.log(0.2), 0.25)
+    states = [[m[0], m[1], m[2], m[3], 0.1 * m[2], 0.4 * m[2]]]
+    for lam in ((-2.0, 40.0, -60.0, 10.0), (0.3, 2.0, -9.0, 4.0), (1.0, -3.0, 2.0, -1.0)):
+        mm = _exp_cubic_moments(lam)
+        states.append(mm[1:] + [0.2 * mm[3], -0.3 * mm[3]])
+    dt = 0.05
+    for w in states:
+        W = np.array(w, dtype=np.float64).reshape(6, 1, 1)
+        A = np.zeros((6, 6))
+        # the multipliers of these densities are large (|lambda| up to ~500
+        # for the lognormal moments), so the closure's higher derivatives are
+        # too: a small step (the Newton solves converge to ~1e-14)
+        for k in range(6):
+            h = 1e-7 * max(1e-3, abs(w[k]))
+            e = np.zeros((6, 1, 1))
+            e[k] = h
+            A[:, k] = ((orc.run_dts(P, W + e, [dt], ug) - orc.run_dts(P, W - e, [dt], ug))
+                       / (2 * h)).reshape(-1)
+        for k in range(6):
+            lam_k = np.zeros((6, 1, 1))
+            lam_k[k] = 1.0
+            row = orc.adjoint_step(P, W, dt, lam_k, ug).reshape(-1)
+            assert np.max(np.abs(row - A[k])) <= 1e-6 * max(1.0, np.max(np.abs(A[k]))), (w, k)
+        # the closure rows are not those of the lognormal fit
+        P0 = orc.params(orc.SPRAY, 1, 1, bc=orc.PERIODIC, K=0.8, closure=0)
+        lam0 = np.zeros((6, 1, 1))
+        lam0[1] = 1.0  # the m_{-1/2} row
+        assert not np.allclose(orc.adjoint_step(P0, W, dt, lam0, ug),
+                               orc.adjoint_step(P, W, dt, lam0, ug), rtol=1e-3)
+
+
+@pytest.mark.parametrize("bc", [0, 1])
+def test_maxent_spray_adjoint_central_differences(orc, bc):
+    """The checkpoint-free oracle adjoint of three spray steps with the
+    entropy-maximising closure against central differences of its forward
+    steps (dts held fixed), periodic and transmissive."""
+    n = 6
+    # lognormal moments (realisable; noise on them can leave the moment
+    # space of densities on [0, 1]) and velocities off the gas velocity
+    W0, ug = inputs.spray_state(n, n, 21)
+    W0 = W0.copy()
+    W0[4:] += 0.1 * W0[2] * np.random.default_rng(121).standard_normal((2, n, n))
+    P = orc.params(orc.SPRAY, n, n, bc=bc, cfl=0.3, K=0.5, theta=0.2, closure=1)
+    _, dts = orc.run(P, W0, 3, ug)
+    tgt = W0[0] * 0.9
+    def loss(W):
+        WN = orc.run_dts(P, W, dts, ug)
+        return 0.5 * np.sum((WN[0] - tgt) ** 2) + np.sum(WN[3] * WN[1])
+    WN = orc.run_dts(P, W0, dts, ug)
+    lamN = np.zeros_like(W0)
+    lamN[0] = WN[0] - tgt
+    lamN[3] = WN[1]
+    lamN[1] = WN[3]
+    g = orc.adjoint_run(P, W0, dts, lamN, ug)
+    rng = np.random.default_rng(9)
+    for _ in range(6):
+        v = rng.standard_normal(W0.shape) * np.abs(W0)
+        # the closure's multipliers reach |lambda| ~ 270 here: central
+        # differences lose 6e-7 (relative) at 1e-7 to curvature, 3e-8 at 1e-8
+        eps = 1e-8
+        fd = (loss(W0 + eps * v) - loss(W0 - eps * v)) / (2 * eps)
+        assert abs(np.sum(g * v) - fd) <= 1e-6 * max(1.0, abs(fd)), (np.sum(g * v), fd)
