@@ -263,9 +263,8 @@ int fvm_sync(fvm_grid* g);
 int fvm_get_status(fvm_grid* g, int clear);
 
 /* Gradient of a loss of the final state with respect to the initial state,
- * through nsteps steps with frozen time steps (advection, Euler and the spray
- * with the lognormal closure, every boundary condition; FVM_EUNSUPPORTED for
- * the entropy-maximising closure and with halo rows). A transmissive ghost is
+ * through nsteps steps with frozen time steps (every model, closure and
+ * boundary condition; FVM_EUNSUPPORTED with halo rows). A transmissive ghost is
  * a copy of its boundary cell, so its sensitivity goes to that cell; a
  * Dirichlet ghost is a constant state and takes none. The adjoint of one
  * transport step is
@@ -277,6 +276,13 @@ int fvm_get_status(fvm_grid* g, int clear);
  * lam^{n+1} is replaced by lam^{n+1} + dt J_S(W*)^T lam^{n+1}, with J_S the
  * Jacobian of the source of Sec. 6.1 at the transported state W* (a clipped
  * lognormal width counts as a constant), before the transport's adjoint.
+ * With the entropy-maximising closure (Sec. 6.2) the closure rows of J_S
+ * come from the dual's optimality conditions at the converged multipliers:
+ * d lambda / d m = H^{-1}, H the moment Hessian; each such step runs the
+ * transport step, the source's adjoint and the transport's adjoint in the
+ * grid's free ping-pong buffer (the one not holding the current state), so
+ * none of the buffers below may be that one (FVM_EINVAL), and it holds no
+ * state afterwards; Newton starts cold in every cell.
  * Inputs (all device memory, the grid's ld and layout):
  *   ckpts[s]   : host array of device pointers, W^{s * ckpt_every}, as
  *                written by fvm_run_ckpt;
@@ -294,8 +300,9 @@ int fvm_adjoint_run(fvm_grid* g, double* const* ckpts, int ckpt_every,
 
 /* One adjoint step at state w with time step dt: lam_out = (dW^{n+1}/dW^n)^T
  * lam_in (device pointers, the grid's ld and layout; lam_out must not alias
- * w or lam_in). The spray's step reads the bound gas velocity. Same model
- * and boundary restrictions as fvm_adjoint_run. Asynchronous. */
+ * w or lam_in). The spray's step reads the bound gas velocity. Same
+ * restrictions as fvm_adjoint_run (with the entropy closure none of w,
+ * lam_in, lam_out may be the grid's free ping-pong buffer). Asynchronous. */
 int fvm_adjoint_step(fvm_grid* g, const double* w, double dt,
                      const double* lam_in, double* lam_out);
 

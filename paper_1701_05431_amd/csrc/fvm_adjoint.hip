@@ -65,10 +65,11 @@ void* adjoint_kernel_ptr(int model, int bc, int wpb, int cpl) {
   return nullptr;
 }
 
-hipError_t launch_spray_adjoint(const AdjointArgs& a, const double* ug, hipStream_t st);
+hipError_t launch_spray_adjoint(const AdjointArgs& a, const double* ug, hipStream_t st,
+                                bool src);
 
 hipError_t launch_adjoint(const AdjointArgs& a, int model, const double* ug, hipStream_t st) {
-  if (model == FVM_SPRAY) return launch_spray_adjoint(a, ug, st);
+  if (model == FVM_SPRAY) return launch_spray_adjoint(a, ug, st, true);
   void* f = adjoint_kernel_ptr(model, a.g.bc, a.t.wpb, a.t.cpl);
   if (!f) return hipErrorInvalidValue;
   AdjointArgs copy = a;

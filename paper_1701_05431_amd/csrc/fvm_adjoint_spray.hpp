@@ -65,17 +65,20 @@ __device__ __forceinline__ void load6(const double* base, const GridGeom& g, int
   for (int v = 0; v < 6; ++v) w[v] = p[v * g.plane];
 }
 
-// velocity along axis D and 1/m_{2/2} (0, 0 below the vacuum threshold)
+// 1/m_{2/2} of a state, 0 at or below the vacuum threshold (velocity 0)
+__device__ __forceinline__ double inv_m2(const double* w) {
+  return w[2] > kVac ? 1.0 / w[2] : 0.0;
+}
+
+// velocity along axis D from the state and its 1/m_{2/2}
 template <int D>
-__device__ __forceinline__ double vel(const double* w, double& r) {
-  const bool ok = w[2] > kVac;
-  r = ok ? 1.0 / w[2] : 0.0;
-  return ok ? w[4 + D] * r : 0.0;
+__device__ __forceinline__ double vel(const double* w, double r) {
+  return r != 0.0 ? w[4 + D] * r : 0.0;
 }
 
 template <int D>
-__device__ __forceinline__ void flux(const double* wl, const double* wr, double* f) {
-  double rl, rr;
+__device__ __forceinline__ void flux(const double* wl, double rl, const double* wr, double rr,
+                                     double* f) {
   const double ul = vel<D>(wl, rl), ur = vel<D>(wr, rr);
   const double up = ul > 0.0 ? ul : 0.0;
   const double um = ur < 0.0 ? ur : 0.0;
@@ -83,11 +86,10 @@ __device__ __forceinline__ void flux(const double* wl, const double* wr, double*
   for (int k = 0; k < 6; ++k) f[k] = fma(wl[k], up, wr[k] * um);
 }
 
-// out += c * J_L(wl, .)^T d along axis D (the left state's Jacobian)
+// out += c * J_L(wl, .)^T d along axis D (the left state's Jacobian; r = 1/m_{2/2})
 template <int D>
-__device__ __forceinline__ void add_jl(const double* wl, const double* d, double c,
+__device__ __forceinline__ void add_jl(const double* wl, double r, const double* d, double c,
                                        double* out) {
-  double r;
   const double u = vel<D>(wl, r);
   if (!(u > 0.0)) return;
   double s = 0.0;
@@ -101,9 +103,8 @@ __device__ __forceinline__ void add_jl(const double* wl, const double* d, double
 
 // out += c * J_R(., wr)^T d along axis D (the right state's Jacobian)
 template <int D>
-__device__ __forceinline__ void add_jr(const double* wr, const double* d, double c,
+__device__ __forceinline__ void add_jr(const double* wr, double r, const double* d, double c,
                                        double* out) {
-  double r;
   const double u = vel<D>(wr, r);
   if (!(u < 0.0)) return;
   double s = 0.0;
@@ -115,66 +116,52 @@ __device__ __forceinline__ void add_jr(const double* wr, const double* d, double
   out[4 + D] = fma(c, s * r, out[4 + D]);
 }
 
+// index modulo n (n >= 1), for periodic wraps of any offset
+__device__ __forceinline__ int wrap(int i, int n) {
+  const int m = i % n;
+  return m < 0 ? m + n : m;
+}
+
 struct SprayAdj {
   const AdjointArgs& a;
   const double* ug;  // gas velocity, 2 planes (uplane, uld)
   double dt, mux, muy;
 
-  __device__ __forceinline__ void state(int kind, int s, int jj, int ii, double* w) const {
-    if (kind == kGhost) {
+  // g = J_S(W*)^T lam without the closure's part: the drag rows and the
+  // evaporation rows of m_{2/2}, m_{3/2} and q (zero where the source is off)
+  __device__ __forceinline__ static void source_rows(const double* ws, const double* lam,
+                                                     const double* ugc, double K, double it,
+                                                     double* g) {
 #pragma unroll
-      for (int v = 0; v < 6; ++v) w[v] = a.ghost[s * kMaxVar + v];
-    } else {
-      load6(a.w, a.g, jj, ii, w);
-    }
-  }
-
-  // W* of the real cell (j, i)
-  __device__ __forceinline__ void wstar(int j, int i, double* ws) const {
-    double c[6], nw[6], ne[6], ns[6], nn[6];
-    load6(a.w, a.g, j, i, c);
-    int jj, ii, k;
-    k = neighbour(a.g, j, i, 0, jj, ii);
-    state(k, 0, jj, ii, nw);
-    k = neighbour(a.g, j, i, 1, jj, ii);
-    state(k, 1, jj, ii, ne);
-    k = neighbour(a.g, j, i, 2, jj, ii);
-    state(k, 2, jj, ii, ns);
-    k = neighbour(a.g, j, i, 3, jj, ii);
-    state(k, 3, jj, ii, nn);
-    double fe[6], fw[6], gn[6], gs[6];
-    flux<0>(c, ne, fe);
-    flux<0>(nw, c, fw);
-    flux<1>(c, nn, gn);
-    flux<1>(ns, c, gs);
-#pragma unroll
-    for (int v = 0; v < 6; ++v) ws[v] = c[v] - (mux * (fe[v] - fw[v]) + muy * (gn[v] - gs[v]));
-  }
-
-  // mu = lam + dt J_S(W*)^T lam at the real cell (j, i)
-  __device__ __forceinline__ void mu_at(int j, int i, double* mu) const {
-    double ws[6];
-    wstar(j, i, ws);
-    load6(a.lam_in, a.g, j, i, mu);
-    const double m0 = ws[0], m1 = ws[1], m2 = ws[2];
-    if (!(m0 > kVac) || !(m1 > kVac) || !(m2 > kVac)) return;
-    const size_t u0 = static_cast<size_t>(j) * a.g.uld + i;
-    const double ugc[2] = {ug[u0], ug[a.g.uplane + u0]};
-    const double K = a.m.K, it = a.m.inv_theta;
+    for (int v = 0; v < 6; ++v) g[v] = 0.0;
+    const double m0 = ws[0], m2 = ws[2];
     const double r2 = 1.0 / m2;
-    const double l0 = mu[0], l1 = mu[1], l2 = mu[2], l3 = mu[3], l4 = mu[4], l5 = mu[5];
-    double g[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
     // momentum rows: S_{4+d} = m_0 (-K u_d + (ug_d - u_d)/theta), u_d = q_d / m_{2/2}
 #pragma unroll
     for (int d = 0; d < 2; ++d) {
       const double ud = ws[4 + d] * r2;
-      const double ld = d == 0 ? l4 : l5;
+      const double ld = lam[4 + d];
       g[0] = fma(ld, fma(-K, ud, (ugc[d] - ud) * it), g[0]);
       g[2] = fma(ld, m0 * (K + it) * ud * r2, g[2]);
       g[4 + d] = -ld * m0 * (K + it) * r2;
     }
-    g[0] = fma(-K, l2, g[0]);
-    g[1] = -1.5 * K * l3;
+    g[0] = fma(-K, lam[2], g[0]);
+    g[1] = -1.5 * K * lam[3];
+  }
+
+  // mu = lam + dt J_S(W*)^T lam at a real cell, given its W* (ws), lam
+  // (lam) and gas velocity (ugc), with the lognormal closure
+  __device__ __forceinline__ void mu_at(const double* ws, const double* lam, const double* ugc,
+                                        double* mu) const {
+#pragma unroll
+    for (int v = 0; v < 6; ++v) mu[v] = lam[v];
+    const double m0 = ws[0], m1 = ws[1], m2 = ws[2];
+    if (!(m0 > kVac) || !(m1 > kVac) || !(m2 > kVac)) return;
+    const double K = a.m.K, it = a.m.inv_theta;
+    const double r2 = 1.0 / m2;
+    const double l0 = lam[0], l1 = lam[1];
+    double g[6];
+    source_rows(ws, lam, ugc, K, it, g);
     if (K != 0.0) {
       // the closure rows: S_0 = -K n(S_eps), S_1 = -K/2 m_{-1/2}
       const double r0 = 1.0 / m0, r1 = 1.0 / m1;
@@ -205,14 +192,12 @@ struct SprayAdj {
     for (int v = 0; v < 6; ++v) mu[v] = fma(dt, g[v], mu[v]);
   }
 
-  // lam^n of the real cell (j, i)
-  // lam^n of the real cell (j, i) from its own mu (mc) and its neighbours'
-  // (nb_mu(side, m) fills mu of the neighbour cell on that side)
+  // lam^n of the real cell (j, i) from its state c (with r = 1/m_{2/2}), its
+  // own mu (mc) and its neighbours' (nb_mu(side, m) fills mu of the
+  // neighbour cell on that side)
   template <class NbMu>
-  __device__ __forceinline__ void gather(int j, int i, const double* mc, NbMu&& nb_mu,
-                                         double* out) const {
-    double c[6];
-    load6(a.w, a.g, j, i, c);
+  __device__ __forceinline__ void gather(int j, int i, const double* c, double r,
+                                         const double* mc, NbMu&& nb_mu, double* out) const {
 #pragma unroll
     for (int v = 0; v < 6; ++v) out[v] = mc[v];
     double m[6], d[6];
@@ -223,22 +208,22 @@ struct SprayAdj {
       nb_mu(1, m);
 #pragma unroll
       for (int v = 0; v < 6; ++v) d[v] = m[v] - mc[v];
-      add_jl<0>(c, d, mux, out);
+      add_jl<0>(c, r, d, mux, out);
     } else {
 #pragma unroll
       for (int v = 0; v < 6; ++v) d[v] = -mc[v];
-      add_jl<0>(c, d, mux, out);
-      if (k == kCopy) add_jr<0>(c, d, mux, out);
+      add_jl<0>(c, r, d, mux, out);
+      if (k == kCopy) add_jr<0>(c, r, d, mux, out);
     }
     k = neighbour(a.g, j, i, 0, jj, ii);
     if (k == kCell) {
       nb_mu(0, m);
 #pragma unroll
       for (int v = 0; v < 6; ++v) d[v] = mc[v] - m[v];
-      add_jr<0>(c, d, mux, out);
+      add_jr<0>(c, r, d, mux, out);
     } else {
-      if (k == kCopy) add_jl<0>(c, mc, mux, out);
-      add_jr<0>(c, mc, mux, out);
+      if (k == kCopy) add_jl<0>(c, r, mc, mux, out);
+      add_jr<0>(c, r, mc, mux, out);
     }
     // y faces: north, south
     k = neighbour(a.g, j, i, 3, jj, ii);
@@ -246,46 +231,56 @@ struct SprayAdj {
       nb_mu(3, m);
 #pragma unroll
       for (int v = 0; v < 6; ++v) d[v] = m[v] - mc[v];
-      add_jl<1>(c, d, muy, out);
+      add_jl<1>(c, r, d, muy, out);
     } else {
 #pragma unroll
       for (int v = 0; v < 6; ++v) d[v] = -mc[v];
-      add_jl<1>(c, d, muy, out);
-      if (k == kCopy) add_jr<1>(c, d, muy, out);
+      add_jl<1>(c, r, d, muy, out);
+      if (k == kCopy) add_jr<1>(c, r, d, muy, out);
     }
     k = neighbour(a.g, j, i, 2, jj, ii);
     if (k == kCell) {
       nb_mu(2, m);
 #pragma unroll
       for (int v = 0; v < 6; ++v) d[v] = mc[v] - m[v];
-      add_jr<1>(c, d, muy, out);
+      add_jr<1>(c, r, d, muy, out);
     } else {
-      if (k == kCopy) add_jl<1>(c, mc, muy, out);
-      add_jr<1>(c, mc, muy, out);
+      if (k == kCopy) add_jl<1>(c, r, mc, muy, out);
+      add_jr<1>(c, r, mc, muy, out);
     }
   }
 };
 
 // ---- tiles ------------------------------------------------------------------
 //
-// A workgroup of kTileThreads threads owns kTX x kTY cells. It first computes
-// mu once for every cell of the tile and of the one-cell ring around it (the
-// ring wraps on periodic grids; outside other grids it is not needed: those
-// faces use the ghost rules) into LDS, then each thread gathers the faces of
-// its cells from there. Every mu is computed as the per-cell formula does,
-// so the result does not depend on the tiling.
+// A workgroup of kTileThreads threads owns kTX x kTY cells, in three phases
+// separated by barriers, all from LDS after the first:
+//   1. the states of the tile and of the two-cell ring around it (the box),
+//      each loaded from HBM once, with 1/m_{2/2} (0 in vacuum) beside them,
+//      and (into registers) lam and u_g of the cells that phase 2 needs;
+//   2. mu of every cell of the tile and of the one-cell ring, its W* from the
+//      box (the ring wraps on periodic grids; outside other grids it is not
+//      needed: those faces use the ghost rules);
+//   3. lam^n of the tile's cells from mu and their own states.
+// Every W*, mu and lam^n is computed as the per-cell formula does, so the
+// result does not depend on the tiling. Box cells outside a non-periodic
+// grid are not loaded: the ghost rules never read them.
 
 #ifndef FVM_SADJ_THREADS
 #define FVM_SADJ_THREADS 512
 #endif
 #ifndef FVM_SADJ_ROWS
-#define FVM_SADJ_ROWS 16
+#define FVM_SADJ_ROWS 8
 #endif
 constexpr int kTileThreads = FVM_SADJ_THREADS;  // a multiple of kTX
 constexpr int kTX = 64;                         // one wave across
 constexpr int kTY = FVM_SADJ_ROWS;
-constexpr int kRX = kTX + 2, kRY = kTY + 2;  // with the ring
+constexpr int kBX = kTX + 4, kBY = kTY + 4;  // state box: the tile and a two-cell ring
+constexpr int kBox = kBX * kBY;
+constexpr int kBoxVars = 7;                  // W and 1/m_{2/2}
+constexpr int kRX = kTX + 2, kRY = kTY + 2;  // mu box: the tile and a one-cell ring
 constexpr int kRing = kRX * kRY;             // mu values per variable in LDS
+constexpr int kLdsDoubles = kBoxVars * kBox + 6 * kRing;
 static_assert(kTileThreads % kTX == 0, "whole waves across the tile");
 
 __device__ __forceinline__ SprayAdj make_adj(const AdjointArgs& a, const double* ug) {
@@ -296,44 +291,146 @@ __device__ __forceinline__ SprayAdj make_adj(const AdjointArgs& a, const double*
   return s;
 }
 
-// phase 1: mu of the tile and its ring into mu_s[v * kRing + r * kRX + c]
-__device__ __forceinline__ void tile_mu(const SprayAdj& s, int j0, int i0, int tid,
-                                        double* mu_s) {
+// phase 1: the state box into box[v * kBox + r * kBX + c], v = 6: 1/m_{2/2}
+__device__ __forceinline__ void tile_load(const SprayAdj& s, int j0, int i0, int tid,
+                                          double* box) {
   const GridGeom& g = s.a.g;
-  for (int idx = tid; idx < kRing; idx += kTileThreads) {
-    const int r = idx / kRX, c = idx % kRX;
-    int j = j0 - 1 + r, i = i0 - 1 + c;
-    bool need = j >= -1 && j <= g.ny && i >= -1 && i <= g.nx;
-    if (j < 0 || j >= g.ny || i < 0 || i >= g.nx) {
-      need = need && g.bc == FVM_PERIODIC;
-      j = j < 0 ? g.ny - 1 : (j >= g.ny ? 0 : j);
-      i = i < 0 ? g.nx - 1 : (i >= g.nx ? 0 : i);
+  const bool per = g.bc == FVM_PERIODIC;
+  for (int idx = tid; idx < kBox; idx += kTileThreads) {
+    const int r = idx / kBX, c = idx % kBX;
+    int j = j0 - 2 + r, i = i0 - 2 + c;
+    const bool inside = j >= 0 && j < g.ny && i >= 0 && i < g.nx;
+    double w[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+    if (inside || per) {
+      j = wrap(j, g.ny);
+      i = wrap(i, g.nx);
+      load6(s.a.w, g, j, i, w);
     }
+#pragma unroll
+    for (int v = 0; v < 6; ++v) box[v * kBox + idx] = w[v];
+    box[6 * kBox + idx] = inv_m2(w);
+  }
+}
+
+// The real cell of mu-box entry idx (the tile and its one-cell ring),
+// wrapped on periodic grids; false where no mu is needed there (outside a
+// non-periodic grid, or past the grid's far edge by more than one cell).
+__device__ __forceinline__ bool ring_cell(const GridGeom& g, int j0, int i0, int idx, int& j,
+                                          int& i) {
+  const int r = idx / kRX, c = idx % kRX;
+  j = j0 - 1 + r;
+  i = i0 - 1 + c;
+  bool need = j >= -1 && j <= g.ny && i >= -1 && i <= g.nx;
+  if (j < 0 || j >= g.ny || i < 0 || i >= g.nx) {
+    need = need && g.bc == FVM_PERIODIC;
+    j = wrap(j, g.ny);
+    i = wrap(i, g.nx);
+  }
+  return need;
+}
+
+// mu entries per thread, and what each needs from HBM besides the box:
+// lam (6) and the gas velocity (2)
+constexpr int kMuPasses = (kRing + kTileThreads - 1) / kTileThreads;
+constexpr int kPre = 8;
+
+// phase 1 (issued with the box loads): lam and u_g of this thread's mu
+// entries into pre[p * kPre + ...] (registers on the GPU)
+__device__ __forceinline__ void tile_prefetch(const SprayAdj& s, int j0, int i0, int tid,
+                                              double* pre) {
+  const GridGeom& g = s.a.g;
+#pragma unroll
+  for (int p = 0; p < kMuPasses; ++p) {
+    const int idx = tid + p * kTileThreads;
+    int j, i;
+    double* q = pre + p * kPre;
+    if (idx < kRing && ring_cell(g, j0, i0, idx, j, i)) {
+      load6(s.a.lam_in, g, j, i, q);
+      const size_t u0 = static_cast<size_t>(j) * g.uld + i;
+      q[6] = s.ug[u0];
+      q[7] = s.ug[g.uplane + u0];
+    } else {
+#pragma unroll
+      for (int v = 0; v < kPre; ++v) q[v] = 0.0;
+    }
+  }
+}
+
+// phase 2: mu of the tile and its ring into mu_s[v * kRing + r * kRX + c];
+// without SRC (the transport's adjoint alone) mu is the prefetched lam
+template <bool SRC = true>
+__device__ __forceinline__ void tile_mu(const SprayAdj& s, int j0, int i0, int tid,
+                                        const double* box, const double* pre, double* mu_s) {
+  const GridGeom& g = s.a.g;
+#pragma unroll
+  for (int p = 0; p < kMuPasses; ++p) {
+    const int idx = tid + p * kTileThreads;
+    if (idx >= kRing) break;
+    const int r = idx / kRX, c = idx % kRX;
+    int j, i;
     double m[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
-    if (need) s.mu_at(j, i, m);
+    if (!SRC) {
+#pragma unroll
+      for (int v = 0; v < 6; ++v) m[v] = pre[p * kPre + v];
+    } else if (ring_cell(g, j0, i0, idx, j, i)) {
+      // W* of the real cell (j, i): box position (r + 1, c + 1) and its four
+      // neighbours there, or a ghost for a side outside a non-periodic grid
+      const int at = (r + 1) * kBX + c + 1;
+      double w[5][6], rr[5];
+      const int off[5] = {0, -1, 1, -kBX, kBX};  // centre, west, east, south, north
+#pragma unroll
+      for (int q = 0; q < 5; ++q) {
+        int jj, ii;
+        const int kind = q == 0 ? kCell : neighbour(g, j, i, q - 1, jj, ii);
+        const int src = at + (kind == kCell ? off[q] : 0);
+        if (kind == kGhost) {
+#pragma unroll
+          for (int v = 0; v < 6; ++v) w[q][v] = s.a.ghost[(q - 1) * kMaxVar + v];
+          rr[q] = inv_m2(w[q]);
+        } else {
+#pragma unroll
+          for (int v = 0; v < 6; ++v) w[q][v] = box[v * kBox + src];
+          rr[q] = box[6 * kBox + src];
+        }
+      }
+      double fe[6], fw[6], gn[6], gs[6], ws[6];
+      flux<0>(w[0], rr[0], w[2], rr[2], fe);
+      flux<0>(w[1], rr[1], w[0], rr[0], fw);
+      flux<1>(w[0], rr[0], w[4], rr[4], gn);
+      flux<1>(w[3], rr[3], w[0], rr[0], gs);
+#pragma unroll
+      for (int v = 0; v < 6; ++v)
+        ws[v] = w[0][v] - (s.mux * (fe[v] - fw[v]) + s.muy * (gn[v] - gs[v]));
+      s.mu_at(ws, pre + p * kPre, pre + p * kPre + 6, m);
+    }
 #pragma unroll
     for (int v = 0; v < 6; ++v) mu_s[v * kRing + idx] = m[v];
   }
 }
 
-// phase 2: lam^n of the tile's cells from mu_s
+// phase 3: lam^n of the tile's cells from mu_s and the box
 __device__ __forceinline__ void tile_out(const SprayAdj& s, int j0, int i0, int tid,
-                                         const double* mu_s) {
+                                         const double* box, const double* mu_s) {
   const GridGeom& g = s.a.g;
   const int c = tid % kTX;
   for (int rr = tid / kTX; rr < kTY; rr += kTileThreads / kTX) {
     const int j = j0 + rr, i = i0 + c;
     if (j >= g.ny || i >= g.nx) continue;
     const int at = (rr + 1) * kRX + c + 1;
-    double mc[6], out[6];
+    const int bat = (rr + 2) * kBX + c + 2;
+    double mc[6], w[6], out[6];
 #pragma unroll
-    for (int v = 0; v < 6; ++v) mc[v] = mu_s[v * kRing + at];
+    for (int v = 0; v < 6; ++v) {
+      mc[v] = mu_s[v * kRing + at];
+      w[v] = box[v * kBox + bat];
+    }
+    const double r = box[6 * kBox + bat];
     auto nb_mu = [mu_s, at](int side, double* m) {
       const int o = side == 0 ? -1 : (side == 1 ? 1 : (side == 2 ? -kRX : kRX));
 #pragma unroll
       for (int v = 0; v < 6; ++v) m[v] = mu_s[v * kRing + at + o];
     };
-    s.gather(j, i, mc, nb_mu, out);
+    s.gather(j, i, w, r, mc, nb_mu, out);
     double* p = s.a.lam_out + static_cast<size_t>(j) * g.ld + i;
 #pragma unroll
     for (int v = 0; v < 6; ++v) p[v * g.plane] = out[v];

@@ -28,6 +28,9 @@ hipError_t launch_clear_scratch(GridScratch* s, int n, hipStream_t st);
 hipError_t launch_set_log(GridScratch* s, int n, double* base, int cap, int stride,
                           hipStream_t st);
 hipError_t launch_adjoint(const AdjointArgs& a, int model, const double* ug, hipStream_t st);
+hipError_t launch_spray_adjoint(const AdjointArgs& a, const double* ug, hipStream_t st,
+                                bool src);
+hipError_t launch_maxent_adjoint_source(const AdjointArgs& a, const double* ug, hipStream_t st);
 
 GridGeom grid_geometry(const fvm_params& p) {
   GridGeom g{};
@@ -313,12 +316,8 @@ static bool wide_layout_ok(const fvm_grid* g) {
   return g->p.ld % 2 == 0 && al(g->w_a) && al(g->w_b) && (!g->ug || al(g->ug));
 }
 
-// The adjoint covers advection, Euler and the spray with the lognormal
-// closure, without halo rows.
-static bool adjoint_supported(const fvm_grid* g) {
-  if (g->halo.s || g->halo.n) return false;
-  return g->p.model != FVM_SPRAY || g->p.closure == FVM_CLOSURE_LOGNORMAL;
-}
+// The adjoint covers every model and closure, without halo rows.
+static bool adjoint_supported(const fvm_grid* g) { return !g->halo.s && !g->halo.n; }
 
 // The adjoint's lane layout for one launch: two cells per lane needs an even
 // pitch and 16-byte aligned state and multiplier buffers.
@@ -1002,24 +1001,63 @@ int fvm_get_tiling(const fvm_grid* g, int* rows, int* wpb) {
   return FVM_OK;
 }
 
+// The entropy closure's adjoint step runs in the grid's free ping-pong
+// buffer (W* and then mu); none of the step's buffers may be that buffer,
+// and with two cells per lane the transport step needs 16-byte alignment.
+static bool maxent_adjoint_buffers_ok(const fvm_grid* g, const double* w, const double* lin,
+                                      const double* lout) {
+  if (kernel_model(g->p) != kSprayMaxEnt) return true;
+  const double* ws = g->other(g->cur);
+  auto al = [](const void* p) { return (reinterpret_cast<uintptr_t>(p) & 15) == 0; };
+  if (w == ws || lin == ws || lout == ws) return false;
+  return g->cpl != 2 || al(w);
+}
+
+// One adjoint step (w, lin -> lout) with dt = dts[k], or dt_arg if dts is
+// null. The entropy closure's step is three launches: the transport step
+// W -> W* into the free ping-pong buffer ws, the source's adjoint
+// mu = lam + dt J_S(W*)^T lam in place there, then the transport's adjoint
+// (w, mu -> lout).
+static int enqueue_adjoint(fvm_grid* g, const double* w, const double* lin, double* lout,
+                           const double* dts, int k, double dt_arg) {
+  AdjointArgs a{};
+  a.w = w;
+  a.lam_in = lin;
+  a.lam_out = lout;
+  a.dts = dts;
+  a.k = k;
+  a.dt_arg = dt_arg;
+  a.g = g->g;
+  a.t = adjoint_tiling(g->g, g->adj_rows, g->adj_wpb, adjoint_cpl(g, a.w, a.lam_in, a.lam_out));
+  a.m = g->m;
+  std::memcpy(a.ghost, g->ghost, sizeof a.ghost);
+  if (kernel_model(g->p) != kSprayMaxEnt)
+    return dev_err(launch_adjoint(a, g->p.model, g->ug, g->stream));
+  double* ws = g->other(g->cur);
+  StepArgs s = g->step_args(w, ws, dts ? kDtArray : kDtValue);
+  s.dts = dts;
+  s.k = k;
+  s.dt_arg = dt_arg;
+  int rc = dev_err(launch_step(s, kSprayMaxEnt, g->stream));
+  if (rc) return rc;
+  AdjointArgs b = a;
+  b.w = ws;
+  b.lam_out = ws;
+  rc = dev_err(launch_maxent_adjoint_source(b, g->ug, g->stream));
+  if (rc) return rc;
+  AdjointArgs c = a;
+  c.lam_in = ws;
+  return dev_err(launch_spray_adjoint(c, g->ug, g->stream, false));
+}
+
 int fvm_adjoint_step(fvm_grid* g, const double* w, double dt, const double* lam_in,
                      double* lam_out) {
   if (!g || !g->bound || !w || !lam_in || !lam_out || lam_in == lam_out || w == lam_out)
     return FVM_EINVAL;
   if (!adjoint_supported(g)) return FVM_EUNSUPPORTED;
   if (!(dt >= 0.0) || !std::isfinite(dt)) return FVM_EINVAL;
-  AdjointArgs a{};
-  a.w = w;
-  a.lam_in = lam_in;
-  a.lam_out = lam_out;
-  a.dts = nullptr;
-  a.dt_arg = dt;
-  a.g = g->g;
-  a.t = adjoint_tiling(g->g, g->adj_rows, g->adj_wpb,
-                       adjoint_cpl(g, a.w, a.lam_in, a.lam_out));
-  a.m = g->m;
-  std::memcpy(a.ghost, g->ghost, sizeof a.ghost);
-  return dev_err(launch_adjoint(a, g->p.model, g->ug, g->stream));
+  if (!maxent_adjoint_buffers_ok(g, w, lam_in, lam_out)) return FVM_EINVAL;
+  return enqueue_adjoint(g, w, lam_in, lam_out, nullptr, 0, dt);
 }
 
 int fvm_adjoint_run(fvm_grid* g, double* const* ckpts, int ckpt_every, const double* dts_dev,
@@ -1033,6 +1071,18 @@ int fvm_adjoint_run(fvm_grid* g, double* const* ckpts, int ckpt_every, const dou
   for (int s = 0; s < nck; ++s)
     if (!ckpts[s]) return FVM_EINVAL;
   const size_t state = g->elems();
+  if (kernel_model(g->p) == kSprayMaxEnt) {
+    // the entropy closure's steps work in the free ping-pong buffer
+    const double* ws = g->other(g->cur);
+    if (!maxent_adjoint_buffers_ok(g, lam, lam, lam_tmp)) return FVM_EINVAL;
+    for (int s = 0; s < nck; ++s)
+      if (!maxent_adjoint_buffers_ok(g, ckpts[s], lam, lam_tmp)) return FVM_EINVAL;
+    if (seg_buf && ckpt_every > 1) {
+      if (!maxent_adjoint_buffers_ok(g, seg_buf, lam, lam_tmp)) return FVM_EINVAL;
+      if (ws >= seg_buf && ws < seg_buf + static_cast<size_t>(ckpt_every - 1) * state)
+        return FVM_EINVAL;
+    }
+  }
   if (const int rc = arm_log(g, nullptr, 0)) return rc;  // the recomputed steps log nothing
   double* lin = lam;
   double* lout = lam_tmp;
@@ -1052,24 +1102,15 @@ int fvm_adjoint_run(fvm_grid* g, double* const* ckpts, int ckpt_every, const dou
     }
     for (int k = k1 - 1; k >= k0; --k) {
       const double* wk = (k == k0) ? ckpts[s] : seg_buf + static_cast<size_t>(k - k0 - 1) * state;
-      AdjointArgs a{};
-      a.w = wk;
-      a.lam_in = lin;
-      a.lam_out = lout;
-      a.dts = dts_dev;
-      a.k = k;
-      a.g = g->g;
-      a.t = adjoint_tiling(g->g, g->adj_rows, g->adj_wpb,
-                           adjoint_cpl(g, a.w, a.lam_in, a.lam_out));
-      a.m = g->m;
-      std::memcpy(a.ghost, g->ghost, sizeof a.ghost);
-      int rc = dev_err(launch_adjoint(a, g->p.model, g->ug, g->stream));
+      int rc = enqueue_adjoint(g, wk, lin, lout, dts_dev, k, 0.0);
       if (rc) return rc;
       std::swap(lin, lout);
     }
   }
-  // the recompute left the scratch maxima describing a recomputed state
+  // the recompute left the scratch maxima (and the entropy closure's kept
+  // multipliers) describing a recomputed state
   g->speeds_valid = false;
+  g->me_valid = false;
   if (lin != lam) {
     return dev_err(hipMemcpyAsync(lam, lin, sizeof(double) * state, hipMemcpyDeviceToDevice,
                                   g->stream));

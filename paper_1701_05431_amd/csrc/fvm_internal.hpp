@@ -36,6 +36,7 @@ enum : int {
   kDtAdaptive = 0,  // dt from the device scratch (previous finalize)
   kDtFixedCheck = 1,// dt from the argument, checked against eq. CFL_cond
   kDtArray = 2,     // dt = dts[k]
+  kDtValue = 3,     // dt from the argument, unchecked (adjoint recomputation)
 };
 
 // Per-grid device scratch (256-byte aligned, cleared by the init kernel).

@@ -29,6 +29,7 @@
 #include <cmath>
 #include <cstdint>
 
+#include "fvm_adjoint_spray.hpp"
 #include "fvm_host.hpp"
 #include "fvm_internal.hpp"
 #include "fvm_models.hpp"
@@ -268,6 +269,64 @@ __global__ __launch_bounds__(kMeThreads) FVM_MAXENT_ATTR void maxent_source_kern
   }
 }
 
+// Adjoint of the source step at the transported state, cell by cell:
+// mu = lam + dt J_S(W*)^T lam (Sec. 2.2.2 eq. SourceTerm, Sec. 6.1 eq.
+// Essadki). a.w holds W*, a.lam_in lam^{n+1}; mu goes to a.lam_out, which
+// may be a.w itself (each thread reads its cell's W* before writing its mu).
+// The closure rows: the multipliers l solve the dual's optimality
+// conditions mu_{k+1}(l) = m_{k/2}, whose Jacobian in l is the moment
+// Hessian H (H_kl = mu_{k+l+1}) and in m is -I, so dl/dm = H^{-1}; with
+// n(S=0) = exp(l_0) and m_{-1/2} = int S^{-1/2} n dS,
+//   dn0/dl = (n0, 0, 0, 0),   dm_{-1/2}/dl_k = int S^{-1/2} x^k n dS = mu_k,
+// and the transposed rows are H^{-1} (-K lam_0 dn0/dl - K/2 lam_1 dm_{-1/2}/dl)
+// (H is symmetric). Newton starts cold in every cell. A cell whose moments the
+// closure cannot match gets NaN multipliers.
+__global__ __launch_bounds__(kMeThreads) FVM_MAXENT_ATTR void maxent_adjoint_source_kernel(
+    AdjointArgs a, const double* ug, MaxEntRule r) {
+  const double dt = a.dts ? a.dts[a.k] : a.dt_arg;
+  const double K = a.m.K, it = a.m.inv_theta;
+  const long long ncell = static_cast<long long>(a.g.nx) * a.g.ny;
+  for (long long c = static_cast<long long>(blockIdx.x) * kMeThreads + threadIdx.x; c < ncell;
+       c += static_cast<long long>(kMeThreads) * gridDim.x) {
+    const int j = static_cast<int>(c / a.g.nx), i = static_cast<int>(c % a.g.nx);
+    const size_t at = static_cast<size_t>(j) * a.g.ld + i;
+    double ws[6], lam[6], mu[6];
+#pragma unroll
+    for (int v = 0; v < 6; ++v) {
+      ws[v] = a.w[v * a.g.plane + at];
+      lam[v] = a.lam_in[v * a.g.plane + at];
+      mu[v] = lam[v];
+    }
+    if (ws[0] > sadj::kVac && ws[1] > sadj::kVac && ws[2] > sadj::kVac) {
+      const size_t uc = ucell(a.g, j, i);
+      const double ugc[2] = {ug[uc], ug[a.g.uplane + uc]};
+      double g[6];
+      sadj::SprayAdj::source_rows(ws, lam, ugc, K, it, g);
+      if (K != 0.0) {
+        double l[4] = {0.0, 0.0, 0.0, 0.0}, mmh, n0, m[8];
+        bool ok = maxent_closure(ws, r, false, l, mmh, n0);
+        double ya[4], yb[4];
+        if (ok) {
+          me_moments(l, r, m);
+          // H y = rhs through the Newton direction solver (H d = -g)
+          const double ra[4] = {K * lam[0] * n0, 0.0, 0.0, 0.0};
+          const double rb[4] = {0.5 * K * lam[1] * m[0], 0.5 * K * lam[1] * m[1],
+                                0.5 * K * lam[1] * m[2], 0.5 * K * lam[1] * m[3]};
+          ok = me_direction(m, ra, ya) && me_direction(m, rb, yb);
+        }
+#pragma unroll
+        for (int k = 0; k < 4; ++k) g[k] += ok ? ya[k] + yb[k] : __builtin_nan("");
+      }
+#pragma unroll
+      for (int v = 0; v < 6; ++v) mu[v] = fma(dt, g[v], mu[v]);
+    }
+#pragma unroll
+    for (int v = 0; v < 6; ++v) a.lam_out[v * a.g.plane + at] = mu[v];
+  }
+}
+
+hipError_t launch_maxent_adjoint_source(const AdjointArgs& a, const double* ug, hipStream_t st);
+
 // Gauss-Legendre rule of 8 points on [0, 1]: the roots of the Legendre
 // polynomial P_8 (by Newton's method on the three-term recurrence, from the
 // Chebyshev points) mapped from [-1, 1], weights 1 / ((1 - t^2) P_8'(t)^2).
@@ -313,6 +372,16 @@ hipError_t launch_maxent_source(const StepArgs& a, const MaxEntWarm& wm, hipStre
   MaxEntWarm w = wm;
   void* args[] = {&copy, &l.rule, &w};
   return hipLaunchKernel(l.fn, l.grid, l.block, args, 0, st);
+}
+
+hipError_t launch_maxent_adjoint_source(const AdjointArgs& a, const double* ug, hipStream_t st) {
+  static const MaxEntRule rule = gauss_legendre_8();
+  const long long ncell = static_cast<long long>(a.g.nx) * a.g.ny;
+  const long long blocks =
+      std::min<long long>(kMeMaxBlocks, (ncell + kMeThreads - 1) / kMeThreads);
+  hipLaunchKernelGGL(maxent_adjoint_source_kernel, dim3(static_cast<unsigned>(blocks < 1 ? 1 : blocks)),
+                     dim3(kMeThreads), 0, st, a, ug, rule);
+  return hipGetLastError();
 }
 
 }  // namespace fvm

@@ -490,6 +490,7 @@ __device__ __forceinline__ double launch_dt(const StepArgs& a, bool& cfl_fail) {
   cfl_fail = false;
   if (a.mode == kDtAdaptive) return a.scr->dt;
   if (a.mode == kDtArray) return a.dts[a.k];
+  if (a.mode == kDtValue) return a.dt_arg;
   const double smax = a.scr->cur_sx > a.scr->cur_sy ? a.scr->cur_sx : a.scr->cur_sy;
   cfl_fail = a.dt_arg * smax > a.g.hmin;
   return a.dt_arg;

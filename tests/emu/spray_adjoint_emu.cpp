@@ -96,16 +96,27 @@ int main(int argc, char** argv) {
   for (int s = 0; s < 4; ++s)
     for (int v = 0; v < 6; ++v) a.ghost[s * kMaxVar + v] = raw[14 * n + s * 6 + v];
 
-  // every tile's two phases, thread by thread, with a heap LDS stand-in of
-  // exactly the kernel's size (the barrier sits between the phases)
+  // every tile's three phases, thread by thread, with a heap LDS stand-in of
+  // exactly the kernel's size (the barriers sit between the phases)
   const sadj::SprayAdj sa = sadj::make_adj(a, ug);
   const int tx = (nx + sadj::kTX - 1) / sadj::kTX, ty = (ny + sadj::kTY - 1) / sadj::kTY;
   for (int b = 0; b < tx * ty; ++b) {
     const int i0 = (b % tx) * sadj::kTX, j0 = (b / tx) * sadj::kTY;
-    double* lds = new double[6 * sadj::kRing];
-    for (int k = 0; k < 6 * sadj::kRing; ++k) lds[k] = NAN;
-    for (int t = 0; t < sadj::kTileThreads; ++t) sadj::tile_mu(sa, j0, i0, t, lds);
-    for (int t = 0; t < sadj::kTileThreads; ++t) sadj::tile_out(sa, j0, i0, t, lds);
+    double* lds = new double[sadj::kLdsDoubles];
+    for (int k = 0; k < sadj::kLdsDoubles; ++k) lds[k] = NAN;
+    double* box = lds;
+    double* mu_s = lds + sadj::kBoxVars * sadj::kBox;
+    // each thread's prefetched values (registers on the GPU)
+    std::vector<double> pre(static_cast<size_t>(sadj::kTileThreads) * sadj::kMuPasses * sadj::kPre);
+    for (int t = 0; t < sadj::kTileThreads; ++t) {
+      double* q = pre.data() + static_cast<size_t>(t) * sadj::kMuPasses * sadj::kPre;
+      sadj::tile_prefetch(sa, j0, i0, t, q);
+      sadj::tile_load(sa, j0, i0, t, box);
+    }
+    for (int t = 0; t < sadj::kTileThreads; ++t)
+      sadj::tile_mu(sa, j0, i0, t, box,
+                    pre.data() + static_cast<size_t>(t) * sadj::kMuPasses * sadj::kPre, mu_s);
+    for (int t = 0; t < sadj::kTileThreads; ++t) sadj::tile_out(sa, j0, i0, t, box, mu_s);
     delete[] lds;
   }
 

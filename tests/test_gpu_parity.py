@@ -966,7 +966,7 @@ def test_spray_adjoint_step(bc, theta):
 @pytest.mark.parametrize("nx,ny", [(1, 1), (1, 6), (2, 5), (63, 3), (64, 4), (65, 9),
                                    (129, 7), (300, 2)])
 def test_spray_adjoint_covers_every_cell(nx, ny, bc):
-    """The spray adjoint's 64 x 16 cell tiles cover every cell of ragged grids,
+    """The spray adjoint's cell tiles cover every cell of ragged grids,
     periodic wrap onto the cell itself (nx = 1) included."""
     print(f"spray adjoint cells nx={nx} ny={ny} bc={bc}", flush=True)
     W, ug = _spray_adjoint_case(nx, ny, nx + ny)
