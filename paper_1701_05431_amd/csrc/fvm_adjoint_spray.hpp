@@ -32,6 +32,7 @@
 
 #include "../../include/fvm.h"
 #include "fvm_internal.hpp"
+#include "fvm_models.hpp"
 
 namespace fvm {
 namespace sadj {
@@ -67,7 +68,7 @@ __device__ __forceinline__ void load6(const double* base, const GridGeom& g, int
 
 // 1/m_{2/2} of a state, 0 at or below the vacuum threshold (velocity 0)
 __device__ __forceinline__ double inv_m2(const double* w) {
-  return w[2] > kVac ? 1.0 / w[2] : 0.0;
+  return w[2] > kVac ? recip(w[2]) : 0.0;
 }
 
 // velocity along axis D from the state and its 1/m_{2/2}
@@ -131,11 +132,10 @@ struct SprayAdj {
   // evaporation rows of m_{2/2}, m_{3/2} and q (zero where the source is off)
   __device__ __forceinline__ static void source_rows(const double* ws, const double* lam,
                                                      const double* ugc, double K, double it,
-                                                     double* g) {
+                                                     double r2, double* g) {
 #pragma unroll
     for (int v = 0; v < 6; ++v) g[v] = 0.0;
-    const double m0 = ws[0], m2 = ws[2];
-    const double r2 = 1.0 / m2;
+    const double m0 = ws[0];
     // momentum rows: S_{4+d} = m_0 (-K u_d + (ug_d - u_d)/theta), u_d = q_d / m_{2/2}
 #pragma unroll
     for (int d = 0; d < 2; ++d) {
@@ -158,13 +158,13 @@ struct SprayAdj {
     const double m0 = ws[0], m1 = ws[1], m2 = ws[2];
     if (!(m0 > kVac) || !(m1 > kVac) || !(m2 > kVac)) return;
     const double K = a.m.K, it = a.m.inv_theta;
-    const double r2 = 1.0 / m2;
+    const double r2 = recip(m2);
     const double l0 = lam[0], l1 = lam[1];
     double g[6];
-    source_rows(ws, lam, ugc, K, it, g);
+    source_rows(ws, lam, ugc, K, it, r2, g);
     if (K != 0.0) {
       // the closure rows: S_0 = -K n(S_eps), S_1 = -K/2 m_{-1/2}
-      const double r0 = 1.0 / m0, r1 = 1.0 / m1;
+      const double r0 = recip(m0), r1 = recip(m1);
       const double L1 = log(m1 * r0), L2 = log(m2 * r0);
       double s2 = 4.0 * fma(-2.0, L1, L2);
       const bool clipped = s2 < 1e-8;
@@ -172,9 +172,9 @@ struct SprayAdj {
       const double mu_ = fma(2.0, L1, -0.25 * s2);
       const double mmh = m0 * exp(fma(-0.5, mu_, 0.125 * s2));
       const double z = a.m.log_s_eps - mu_;
+      const double is2 = recip(s2);
       const double n0 =
-          m0 / (a.m.s_eps * sqrt(6.283185307179586 * s2)) * exp(-(z * z) / (2.0 * s2));
-      const double is2 = 1.0 / s2;
+          m0 * recip(a.m.s_eps * root(6.283185307179586 * s2)) * exp(-(z * z) * (0.5 * is2));
       const double dL1[3] = {-r0, r1, 0.0};
       const double dL2[3] = {-r0, 0.0, r2};
 #pragma unroll
@@ -203,7 +203,9 @@ struct SprayAdj {
     double m[6], d[6];
     int jj, ii;
     // x faces: east (c left of it), west (c right of it)
-    int k = neighbour(a.g, j, i, 1, jj, ii);
+    // on periodic grids every neighbour is a cell (uniform across the workgroup)
+    const bool per = a.g.bc == FVM_PERIODIC;
+    int k = per ? kCell : neighbour(a.g, j, i, 1, jj, ii);
     if (k == kCell) {
       nb_mu(1, m);
 #pragma unroll
@@ -215,7 +217,7 @@ struct SprayAdj {
       add_jl<0>(c, r, d, mux, out);
       if (k == kCopy) add_jr<0>(c, r, d, mux, out);
     }
-    k = neighbour(a.g, j, i, 0, jj, ii);
+    k = per ? kCell : neighbour(a.g, j, i, 0, jj, ii);
     if (k == kCell) {
       nb_mu(0, m);
 #pragma unroll
@@ -226,7 +228,7 @@ struct SprayAdj {
       add_jr<0>(c, r, mc, mux, out);
     }
     // y faces: north, south
-    k = neighbour(a.g, j, i, 3, jj, ii);
+    k = per ? kCell : neighbour(a.g, j, i, 3, jj, ii);
     if (k == kCell) {
       nb_mu(3, m);
 #pragma unroll
@@ -238,7 +240,7 @@ struct SprayAdj {
       add_jl<1>(c, r, d, muy, out);
       if (k == kCopy) add_jr<1>(c, r, d, muy, out);
     }
-    k = neighbour(a.g, j, i, 2, jj, ii);
+    k = per ? kCell : neighbour(a.g, j, i, 2, jj, ii);
     if (k == kCell) {
       nb_mu(2, m);
 #pragma unroll
@@ -381,7 +383,8 @@ __device__ __forceinline__ void tile_mu(const SprayAdj& s, int j0, int i0, int t
 #pragma unroll
       for (int q = 0; q < 5; ++q) {
         int jj, ii;
-        const int kind = q == 0 ? kCell : neighbour(g, j, i, q - 1, jj, ii);
+        const int kind =
+            q == 0 || g.bc == FVM_PERIODIC ? kCell : neighbour(g, j, i, q - 1, jj, ii);
         const int src = at + (kind == kCell ? off[q] : 0);
         if (kind == kGhost) {
 #pragma unroll

@@ -301,7 +301,7 @@ __global__ __launch_bounds__(kMeThreads) FVM_MAXENT_ATTR void maxent_adjoint_sou
       const size_t uc = ucell(a.g, j, i);
       const double ugc[2] = {ug[uc], ug[a.g.uplane + uc]};
       double g[6];
-      sadj::SprayAdj::source_rows(ws, lam, ugc, K, it, g);
+      sadj::SprayAdj::source_rows(ws, lam, ugc, K, it, 1.0 / ws[2], g);
       if (K != 0.0) {
         double l[4] = {0.0, 0.0, 0.0, 0.0}, mmh, n0, m[8];
         bool ok = maxent_closure(ws, r, false, l, mmh, n0);

@@ -238,7 +238,7 @@ struct Spray {
       : K(m.K), inv_theta(m.inv_theta), s_eps(m.s_eps), log_s_eps(m.log_s_eps) {}
   __device__ __forceinline__ void prim(const double* w, Prim& q) const {
     const bool ok = w[2] > 1e-300;
-    const double r = 1.0 / (ok ? w[2] : 1.0);
+    const double r = recip(ok ? w[2] : 1.0);
     q.ux = ok ? w[4] * r : 0.0;
     q.uy = ok ? w[5] * r : 0.0;
   }
@@ -272,9 +272,9 @@ struct Spray {
   __device__ __forceinline__ void source(double* w, double ugx, double ugy, double dt) const {
     const double m0 = w[0], m1 = w[1], m2 = w[2];
     if (!(m0 > 1e-300) || !(m1 > 1e-300) || !(m2 > 1e-300)) return;
-    const double r2 = 1.0 / m2;
+    const double r2 = recip(m2);
     const double ux = w[4] * r2, uy = w[5] * r2;
-    const double r0 = 1.0 / m0;
+    const double r0 = recip(m0);
     const double L1 = log(m1 * r0);
     const double L2 = log(m2 * r0);
     double s2 = 4.0 * fma(-2.0, L1, L2);
@@ -282,7 +282,9 @@ struct Spray {
     const double mu = fma(2.0, L1, -0.25 * s2);
     const double mmh = m0 * exp(fma(-0.5, mu, 0.125 * s2));
     const double z = log_s_eps - mu;
-    const double n0 = m0 / (s_eps * sqrt(6.283185307179586 * s2)) * exp(-(z * z) / (2.0 * s2));
+    const double is2 = recip(s2);
+    const double n0 =
+        m0 * recip(s_eps * root(6.283185307179586 * s2)) * exp(-(z * z) * (0.5 * is2));
     const double Km0 = K * m0;
     w[0] = fma(dt, -K * n0, m0);
     w[1] = fma(dt, -(0.5 * K) * mmh, m1);
