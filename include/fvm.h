@@ -409,6 +409,14 @@ int fvm_batch_set_tiling(fvm_batch* b, int rows_per_strip, int waves_per_block);
  * of the tiling's height. Results are bitwise the same either way. */
 int fvm_batch_set_schedule(fvm_batch* b, int persistent, int fit_blocks);
 
+/* Lane layout of the batched step: cells_per_lane 2 (the default) runs two
+ * adjacent cells per lane (16-byte accesses) on every grid whose pitch is
+ * even and one elsewhere; 1 runs one cell per lane on every grid (a kernel
+ * with fewer registers per lane, so more waves per SIMD, and fewer idle lanes
+ * in each grid's last strip). Other values give FVM_EINVAL. Results are
+ * bitwise the same either way. */
+int fvm_batch_set_layout(fvm_batch* b, int cells_per_lane);
+
 /* Autotuner of the batched step's tile shape and schedule (dry runs with
  * every dt scaled to 0, states unchanged); cache as for fvm_autotune, keyed
  * by the device, model and the list of grid shapes. Synchronises the

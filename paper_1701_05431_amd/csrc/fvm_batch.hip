@@ -58,12 +58,16 @@ __global__ void batch_clear_kernel(BatchScratch* b, GridScratch* g, int n) {
 
 // PERSIST: a resident set of workgroups takes items from the queue until it
 // runs dry; otherwise (grouped launch) workgroup b does item b and the
-// hardware dispatcher balances the load.
-template <class M, int BC, int WPB, bool PERSIST>
+// hardware dispatcher balances the load. NARROW: every grid runs one cell
+// per lane, and the two-cell strips are left out of the kernel (about 150
+// registers per lane for the Euler strips instead of about 245, so three
+// waves per SIMD instead of two, and the last strip of a grid idles at most
+// 63 lanes instead of 127).
+template <class M, int BC, int WPB, bool PERSIST, bool NARROW>
 __global__ FVM_STEP_BOUNDS(WPB) void batch_kernel(BatchArgs a) {
-  // both lane layouts live in this kernel, so the Euler strips keep one row
-  // of loads in flight (not two) to stay within 256 registers per lane (two
-  // rows in flight, even with the one-cell strips left out, spill)
+  // both lane layouts live in the mixed kernel, so the Euler strips keep one
+  // row of loads in flight (not two) to stay within 256 registers per lane
+  // (two rows in flight, even with the one-cell strips left out, spill)
   constexpr int kPF = M::NV >= 4 ? 1 : M::kPrefetch2;
   const M m(a.m);
   const int wave = wave_index();
@@ -94,7 +98,7 @@ __global__ FVM_STEP_BOUNDS(WPB) void batch_kernel(BatchArgs a) {
     unsigned long long bx = 0, by = 0;
     if (k < G.nstrips) {
       const int sx = k % G.strips_x, ty = k / G.strips_x;
-      const bool wide_grid = G.cpl == 2;  // uniform across the workgroup
+      const bool wide_grid = !NARROW && G.cpl == 2;  // uniform across the workgroup
       const int xs = sx * (wide_grid ? strip_width(2) : strip_width(1));
       // a two-cells-per-lane grid's last strip with at most 64 columns left
       // runs one cell per lane (bitwise the same cells, half the idle lanes)
@@ -128,27 +132,32 @@ __global__ FVM_STEP_BOUNDS(WPB) void batch_kernel(BatchArgs a) {
   }
 }
 
-template <class M, int BC, bool P>
+template <class M, int BC, bool P, bool N>
 static void* batch_fn_wpb(int wpb) {
   switch (wpb) {
-    case 1: return reinterpret_cast<void*>(&batch_kernel<M, BC, 1, P>);
-    case 2: return reinterpret_cast<void*>(&batch_kernel<M, BC, 2, P>);
-    case 4: return reinterpret_cast<void*>(&batch_kernel<M, BC, 4, P>);
-    case 8: return reinterpret_cast<void*>(&batch_kernel<M, BC, 8, P>);
+    case 1: return reinterpret_cast<void*>(&batch_kernel<M, BC, 1, P, N>);
+    case 2: return reinterpret_cast<void*>(&batch_kernel<M, BC, 2, P, N>);
+    case 4: return reinterpret_cast<void*>(&batch_kernel<M, BC, 4, P, N>);
+    case 8: return reinterpret_cast<void*>(&batch_kernel<M, BC, 8, P, N>);
     default: return nullptr;
   }
 }
 
-template <class M, bool P>
+template <class M, bool P, bool N>
 static void* batch_fn_bc(int bc, int wpb) {
-  return bc == 0 ? batch_fn_wpb<M, 0, P>(wpb) : batch_fn_wpb<M, 1, P>(wpb);
+  return bc == 0 ? batch_fn_wpb<M, 0, P, N>(wpb) : batch_fn_wpb<M, 1, P, N>(wpb);
 }
 
-static void* batch_kernel_ptr(int model, int bc, int wpb, bool persist = true) {
-  if (model == 0)
-    return persist ? batch_fn_bc<Adv, true>(bc, wpb) : batch_fn_bc<Adv, false>(bc, wpb);
-  if (model == 1)
-    return persist ? batch_fn_bc<Euler, true>(bc, wpb) : batch_fn_bc<Euler, false>(bc, wpb);
+template <class M>
+static void* batch_fn(int bc, int wpb, bool persist, bool narrow) {
+  if (persist)
+    return narrow ? batch_fn_bc<M, true, true>(bc, wpb) : batch_fn_bc<M, true, false>(bc, wpb);
+  return narrow ? batch_fn_bc<M, false, true>(bc, wpb) : batch_fn_bc<M, false, false>(bc, wpb);
+}
+
+static void* batch_kernel_ptr(int model, int bc, int wpb, bool persist, bool narrow) {
+  if (model == 0) return batch_fn<Adv>(bc, wpb, persist, narrow);
+  if (model == 1) return batch_fn<Euler>(bc, wpb, persist, narrow);
   return nullptr;
 }
 
@@ -167,7 +176,7 @@ struct BatchGraph {
   int kind;  // 0 persistent, 1 per grid
   int nsteps;
   const double* start;
-  int rows, wpb;
+  int rows, wpb, cpl_max;
   bool persist, fit;
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
@@ -185,6 +194,8 @@ struct fvm_batch {
   int rows = 32, wpb = 2;
   bool persist = true;           // persistent workgroups or one per item
   bool fit = false;              // row blocks chosen to fill whole workgroups
+  int cpl_max = 2;               // 2: two cells per lane where the pitch is even; 1: one
+  bool narrow = false;           // every grid runs one cell per lane
   double* w_a = nullptr;
   double* w_b = nullptr;
   double* cur = nullptr;
@@ -230,7 +241,7 @@ struct fvm_batch {
       // two cells per lane needs 16-byte aligned rows: an even pitch (the
       // grid offsets are multiples of 32 elements, the buffers 256-byte
       // aligned)
-      r.cpl = p[k].ld % 2 == 0 ? 2 : 1;
+      r.cpl = cpl_max == 2 && p[k].ld % 2 == 0 ? 2 : 1;
       const int w = strip_width(r.cpl);
       r.strips_x = (g.nx + w - 1) / w;
       // row blocks of near-equal height (a workgroup waits for its longest
@@ -268,9 +279,11 @@ struct fvm_batch {
     std::stable_sort(recs.begin(), recs.end(),
                      [](const BatchGrid& x, const BatchGrid& y) { return x.rows > y.rows; });
     int item = 0;
+    narrow = true;
     for (auto& r : recs) {
       r.item0 = item;
       item += r.nitems;
+      narrow = narrow && r.cpl == 1;
     }
     nitems = item;
   }
@@ -343,6 +356,20 @@ static int upload_records(fvm_batch* b) {
   return berr(e);
 }
 
+// The persistent launch's workgroup count: as many as fit on the device at
+// once for the kernel of the current tiling and layout.
+static int size_resident_set(fvm_batch* b) {
+  int dev = 0, cus = 0, per_cu = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return FVM_EDEVICE;
+  if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+    return FVM_EDEVICE;
+  void* f = batch_kernel_ptr(b->model, b->bc, b->wpb, true, b->narrow);
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, f, b->wpb * kWave, 0) != hipSuccess)
+    return FVM_EDEVICE;
+  b->nblocks = std::max(1, cus * std::max(1, per_cu));
+  return FVM_OK;
+}
+
 int fvm_batch_bind(fvm_batch* b, double* w_a, double* w_b, void* scratch, void* stream) {
   if (!b || !w_a || !w_b || !scratch || w_a == w_b) return FVM_EINVAL;
   if (reinterpret_cast<uintptr_t>(scratch) & 255) return FVM_EINVAL;
@@ -357,14 +384,7 @@ int fvm_batch_bind(fvm_batch* b, double* w_a, double* w_b, void* scratch, void* 
   b->bound = true;
   b->speeds_valid = false;
   b->log_armed = nullptr;
-  int dev = 0, cus = 0, per_cu = 0;
-  if (hipGetDevice(&dev) != hipSuccess) return FVM_EDEVICE;
-  if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
-    return FVM_EDEVICE;
-  void* f = batch_kernel_ptr(b->model, b->bc, b->wpb);
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, f, b->wpb * kWave, 0) != hipSuccess)
-    return FVM_EDEVICE;
-  b->nblocks = std::max(1, cus * std::max(1, per_cu));
+  if (size_resident_set(b) != FVM_OK) return FVM_EDEVICE;
   hipLaunchKernelGGL(batch_clear_kernel, dim3((b->n + 63) / 64), dim3(64), 0, b->stream,
                      b->bscr(), b->gscr(), b->n);
   if (hipGetLastError() != hipSuccess) return FVM_EDEVICE;
@@ -381,14 +401,7 @@ int fvm_batch_set_tiling(fvm_batch* b, int rows, int wpb) {
   b->wpb = w;
   b->plan();
   if (!b->bound) return FVM_OK;
-  int dev = 0, cus = 0, per_cu = 0;
-  if (hipGetDevice(&dev) != hipSuccess) return FVM_EDEVICE;
-  if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
-    return FVM_EDEVICE;
-  void* f = batch_kernel_ptr(b->model, b->bc, b->wpb);
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, f, b->wpb * kWave, 0) != hipSuccess)
-    return FVM_EDEVICE;
-  b->nblocks = std::max(1, cus * std::max(1, per_cu));
+  if (size_resident_set(b) != FVM_OK) return FVM_EDEVICE;
   return upload_records(b);
 }
 
@@ -425,7 +438,7 @@ static BatchGraph* find_batch_graph(fvm_batch* b, int kind, int nsteps, const do
   for (auto it = b->graphs.begin(); it != b->graphs.end(); ++it) {
     if (it->kind == kind && it->nsteps == nsteps && it->start == start &&
         it->rows == b->rows && it->wpb == b->wpb && it->persist == b->persist &&
-        it->fit == b->fit) {
+        it->fit == b->fit && it->cpl_max == b->cpl_max) {
       b->graphs.splice(b->graphs.begin(), b->graphs, it);
       return &b->graphs.front();
     }
@@ -443,6 +456,7 @@ static int build_batch_graph(fvm_batch* b, int kind, int nsteps, const double* s
   c.wpb = b->wpb;
   c.persist = b->persist;
   c.fit = b->fit;
+  c.cpl_max = b->cpl_max;
   if (hipGraphCreate(&c.graph, 0) != hipSuccess) return FVM_EDEVICE;
   hipGraphNode_t prev = nullptr;
   const double* in = start;
@@ -476,7 +490,7 @@ static int build_batch_graph(fvm_batch* b, int kind, int nsteps, const double* s
       a.nitems = b->nitems;
       a.dt_scale = kind == 2 ? 0.0 : 1.0;
       a.m = b->m;
-      ok = add(batch_kernel_ptr(b->model, b->bc, b->wpb, b->persist),
+      ok = add(batch_kernel_ptr(b->model, b->bc, b->wpb, b->persist, b->narrow),
                dim3(b->persist ? std::min(b->nblocks, b->nitems) : b->nitems),
                dim3(b->wpb * kWave), &a);
     } else {
@@ -614,17 +628,22 @@ int fvm_batch_autotune(fvm_batch* b, const char* cache_path) {
   if (cache_path) {
     std::ifstream in(cache_path);
     std::string line;
-    int r = 0, w = 0, ps = 1, ft = 0, found = 0;
+    int r = 0, w = 0, ps = 1, ft = 0, cl = 2, found = 0;
     while (std::getline(in, line)) {
       const size_t bar = line.find(" | ");
       if (bar == std::string::npos || line.substr(0, bar) != key) continue;
-      if (std::sscanf(line.c_str() + bar + 3, "rows=%d wpb=%d persist=%d fit=%d", &r, &w, &ps,
-                      &ft) == 4)
+      int rr = 0, ww = 0, pp = 1, ff = 0, cc = 2;
+      const int got = std::sscanf(line.c_str() + bar + 3, "rows=%d wpb=%d persist=%d fit=%d cpl=%d",
+                                  &rr, &ww, &pp, &ff, &cc);
+      if (got >= 4 && (cc == 1 || cc == 2)) {  // lines without a layout: two cells per lane
+        r = rr, w = ww, ps = pp, ft = ff, cl = got == 5 ? cc : 2;
         found = 1;
+      }
     }
     if (found) {
       b->persist = ps != 0;
       b->fit = ft != 0;
+      b->cpl_max = cl;
       return fvm_batch_set_tiling(b, r, w);
     }
   }
@@ -639,16 +658,18 @@ int fvm_batch_autotune(fvm_batch* b, const char* cache_path) {
     return FVM_EDEVICE;
   }
   double best = 1e300;
-  int br = b->rows, bw = b->wpb;
+  int br = b->rows, bw = b->wpb, bc = b->cpl_max;
   bool bp = b->persist, bf = b->fit;
   int rc = FVM_OK;
-  for (int c = 0; c < 16 && !rc; ++c) {
-    const bool ps = c < 8;  // persistent, then grouped launches
+  for (int c = 0; c < 32 && !rc; ++c) {
+    const int cl = c < 16 ? 2 : 1;  // two cells per lane, then one
+    const bool ps = c % 16 < 8;     // persistent, then grouped launches
     const bool ft = c % 2 == 1;
     const int w = 1 << ((c / 2) % 4);
     b->persist = ps;
     b->fit = ft;
-    for (int r : {8, 16, 32, 48, 64, 96, 128}) {
+    b->cpl_max = cl;
+    for (int r : {8, 16, 32, 48, 64, 96, 128, 192, 256}) {
       rc = fvm_batch_set_tiling(b, r, w);
       if (rc == FVM_OK) rc = arm_batch_log(b, nullptr, 0);
       if (rc) break;
@@ -673,6 +694,7 @@ int fvm_batch_autotune(fvm_batch* b, const char* cache_path) {
         bw = w;
         bp = ps;
         bf = ft;
+        bc = cl;
       }
     }
   }
@@ -681,11 +703,12 @@ int fvm_batch_autotune(fvm_batch* b, const char* cache_path) {
   if (rc) return rc;
   b->persist = bp;
   b->fit = bf;
+  b->cpl_max = bc;
   rc = fvm_batch_set_tiling(b, br, bw);
   if (rc == FVM_OK && cache_path) {
     std::ofstream out(cache_path, std::ios::app);
     out << key << " | rows=" << br << " wpb=" << bw << " persist=" << (bp ? 1 : 0)
-        << " fit=" << (bf ? 1 : 0) << " us=" << best << "\n";
+        << " fit=" << (bf ? 1 : 0) << " cpl=" << bc << " us=" << best << "\n";
   }
   return rc;
 }
@@ -694,6 +717,12 @@ int fvm_batch_set_schedule(fvm_batch* b, int persistent, int fit_blocks) {
   if (!b) return FVM_EINVAL;
   b->persist = persistent != 0;
   b->fit = fit_blocks != 0;
+  return fvm_batch_set_tiling(b, b->rows, b->wpb);
+}
+
+int fvm_batch_set_layout(fvm_batch* b, int cells_per_lane) {
+  if (!b || (cells_per_lane != 1 && cells_per_lane != 2)) return FVM_EINVAL;
+  b->cpl_max = cells_per_lane;
   return fvm_batch_set_tiling(b, b->rows, b->wpb);
 }
 

@@ -367,8 +367,14 @@ class Batch:
         check(lib().fvm_batch_set_schedule(self.h, int(bool(persistent)), int(bool(fit_blocks))),
               "fvm_batch_set_schedule")
 
+    def set_layout(self, cells_per_lane: int = 2) -> None:
+        """2: two cells per lane on every even-pitch grid; 1: one cell per
+        lane on every grid."""
+        check(lib().fvm_batch_set_layout(self.h, int(cells_per_lane)), "fvm_batch_set_layout")
+
     def autotune(self, cache_path: str | None = None) -> None:
-        """Picks the batched step's tile shape and schedule by timing dry runs."""
+        """Picks the batched step's tile shape, schedule and lane layout by
+        timing dry runs."""
         path = cache_path.encode() if cache_path else None
         check(lib().fvm_batch_autotune(self.h, path), "fvm_batch_autotune")
 

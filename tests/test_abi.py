@@ -147,6 +147,12 @@ def test_batch_create_validation(L):
     h = C.c_void_p()
     assert L.fvm_batch_create(2, arr, (C.c_size_t * 2)(0, 4 * 64 * 64), C.byref(h)) == 0
     assert L.fvm_batch_scratch_bytes(h) % 256 == 0
+    # lane layouts: one or two cells per lane (an unbound batch only re-plans)
+    assert L.fvm_batch_set_layout(h, 1) == 0
+    assert L.fvm_batch_set_layout(h, 2) == 0
+    for bad in (0, 3, -1):
+        assert L.fvm_batch_set_layout(h, bad) == _lib.FVM_EINVAL
+    assert L.fvm_batch_set_layout(None, 1) == _lib.FVM_EINVAL
     assert L.fvm_batch_destroy(h) == 0
     # overlapping grids
     assert L.fvm_batch_create(2, arr, (C.c_size_t * 2)(0, 32), C.byref(h)) == _lib.FVM_EINVAL

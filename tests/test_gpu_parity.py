@@ -697,10 +697,23 @@ def test_batch_equals_single_grid_runs():
     b4.set_states(states)
     dts4 = b4.run(9, record_dt=True).cpu().numpy()
     got4 = [x.cpu().numpy() for x in b4.states()]
+    narrow = []  # one cell per lane on every grid, persistent and grouped
+    for persistent, tiling in ((True, (48, 4)), (False, (8, 2))):
+        b5 = Batch(plist)
+        b5.set_layout(1)
+        b5.set_schedule(persistent)
+        b5.set_tiling(*tiling)
+        b5.set_states(states)
+        narrow.append((b5.run(9, record_dt=True).cpu().numpy(),
+                       [x.cpu().numpy() for x in b5.states()]))
     assert np.array_equal(dts3, dts) and np.array_equal(dts4, dts)
     for k in range(len(sizes)):
         assert np.array_equal(got3[k], got[k]), k
         assert np.array_equal(got4[k], got[k]), k
+    for d5, got5 in narrow:
+        assert np.array_equal(d5, dts)
+        for k in range(len(sizes)):
+            assert np.array_equal(got5[k], got[k]), k
     for k, n in enumerate(sizes):
         s = Solver(plist[k])
         s.set_state(states[k])
