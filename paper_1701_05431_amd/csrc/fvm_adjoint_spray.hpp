@@ -117,10 +117,13 @@ __device__ __forceinline__ void add_jr(const double* wr, double r, const double*
   out[4 + D] = fma(c, s * r, out[4 + D]);
 }
 
-// index modulo n (n >= 1), for periodic wraps of any offset
+// index modulo n (n >= 1) for periodic wraps; the offsets stay within a
+// tile and its ring of the grid, so one step is the rule and several happen
+// only on grids narrower than the ring (no integer division)
 __device__ __forceinline__ int wrap(int i, int n) {
-  const int m = i % n;
-  return m < 0 ? m + n : m;
+  while (i < 0) i += n;
+  while (i >= n) i -= n;
+  return i;
 }
 
 struct SprayAdj {
@@ -271,11 +274,18 @@ struct SprayAdj {
 #ifndef FVM_SADJ_THREADS
 #define FVM_SADJ_THREADS 512
 #endif
-#ifndef FVM_SADJ_ROWS
-#define FVM_SADJ_ROWS 8
+// 30 x 14 cells: the mu box (32 x 16) is one value per thread, so no wave
+// takes a second mu pass while the others wait at the barrier (3 % faster
+// than 64 x 8, whose 66 x 10 mu box is 1.29 per thread)
+#ifndef FVM_SADJ_COLS
+#define FVM_SADJ_COLS 30
 #endif
-constexpr int kTileThreads = FVM_SADJ_THREADS;  // a multiple of kTX
-constexpr int kTX = 64;                         // one wave across
+#ifndef FVM_SADJ_ROWS
+#define FVM_SADJ_ROWS 14
+#endif
+
+constexpr int kTileThreads = FVM_SADJ_THREADS;
+constexpr int kTX = FVM_SADJ_COLS;
 constexpr int kTY = FVM_SADJ_ROWS;
 constexpr int kBX = kTX + 4, kBY = kTY + 4;  // state box: the tile and a two-cell ring
 constexpr int kBox = kBX * kBY;
@@ -283,7 +293,6 @@ constexpr int kBoxVars = 7;                  // W and 1/m_{2/2}
 constexpr int kRX = kTX + 2, kRY = kTY + 2;  // mu box: the tile and a one-cell ring
 constexpr int kRing = kRX * kRY;             // mu values per variable in LDS
 constexpr int kLdsDoubles = kBoxVars * kBox + 6 * kRing;
-static_assert(kTileThreads % kTX == 0, "whole waves across the tile");
 
 __device__ __forceinline__ SprayAdj make_adj(const AdjointArgs& a, const double* ug) {
   SprayAdj s{a, ug, 0.0, 0.0, 0.0};
@@ -415,8 +424,8 @@ __device__ __forceinline__ void tile_mu(const SprayAdj& s, int j0, int i0, int t
 __device__ __forceinline__ void tile_out(const SprayAdj& s, int j0, int i0, int tid,
                                          const double* box, const double* mu_s) {
   const GridGeom& g = s.a.g;
-  const int c = tid % kTX;
-  for (int rr = tid / kTX; rr < kTY; rr += kTileThreads / kTX) {
+  for (int idx = tid; idx < kTX * kTY; idx += kTileThreads) {
+    const int rr = idx / kTX, c = idx % kTX;
     const int j = j0 + rr, i = i0 + c;
     if (j >= g.ny || i >= g.nx) continue;
     const int at = (rr + 1) * kRX + c + 1;

@@ -26,8 +26,11 @@ def emu(tmp_path_factory):
     if not os.path.exists(CLANG) or shutil.which("true") is None:
         pytest.skip("needs the ROCm clang++ for a host build")
     out = str(tmp_path_factory.mktemp("sadjemu") / "spray_adjoint_emu")
+    # FVM_EMU_DEFINES: extra -D flags, e.g. another tile shape
+    # ("-DFVM_SADJ_COLS=62 -DFVM_SADJ_ROWS=6")
+    extra = os.environ.get("FVM_EMU_DEFINES", "").split()
     cmd = [CLANG, "-std=c++20", "-O1", "-g", "-fsanitize=address", "-fno-omit-frame-pointer",
-           "-ffp-contract=off", "-I", os.path.join(EMU, "shim"),
+           "-ffp-contract=off", *extra, "-I", os.path.join(EMU, "shim"),
            os.path.join(EMU, "spray_adjoint_emu.cpp"), "-o", out, "-pthread"]
     subprocess.run(cmd, check=True, capture_output=True)
     return out
