@@ -332,8 +332,10 @@ int fvm_get_cells_per_lane(const fvm_grid* g);
 
 /* Autotuner: picks the tiling and lane layout of the fused step by timing
  * dry-run steps of every candidate (dt = 0, which leaves the bound state bit
- * for bit unchanged) on the bound buffers and stream, applies the fastest,
- * and, if cache_path is non-NULL, appends it to that text file; a later call
+ * for bit unchanged) on the bound buffers and stream, re-times the six
+ * fastest three more times over longer windows and applies the lowest
+ * median, and, if cache_path is non-NULL, appends it to that text file; a
+ * later call
  * with the same device, model, grid shape and layout reuses the stored
  * choice without timing (the spray's closure is part of the key). For
  * advection and Euler grids it then picks the adjoint kernel's tile shape

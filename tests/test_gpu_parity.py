@@ -866,6 +866,36 @@ def test_adjoint_tuner_on_caller_buffers():
     assert rel_linf(got[:, :, :nx].cpu().numpy(), orc.adjoint_step(P, W, dt, lam)) <= TOL
 
 
+@pytest.mark.parametrize("model", [1, 2])
+def test_forward_tuner_keeps_the_state_and_caches_its_choice(model, tmp_path):
+    """fvm_autotune (dry runs, then the fastest candidates re-timed) leaves
+    the state bit for bit, writes its choice to the cache, reads the same
+    choice back, and the chosen tiling still steps like the oracle."""
+    nx, ny = 200, 72
+    if model == 1:
+        W, ug = inputs.riemann_state(nx, ny, 5), None
+        p = params_from(model=1, bc=1, nx=nx, ny=ny, ld=nx, layout=_lib.FVM_LAYOUT_ROWS)
+    else:
+        W, ug = inputs.spray_state(nx, ny, 5)
+        p = params_from(inputs.SPRAY_2048, nx=nx, ny=ny, npart_x=1, npart_y=1, cfl=0.45,
+                        layout=_lib.FVM_LAYOUT_ROWS)
+    s = Solver(p, ug=ug)
+    s.set_state(W)
+    cache = str(tmp_path / "tune.txt")
+    chosen = s.autotune(cache)
+    assert np.array_equal(gpu_state(s), W)
+    lines = open(cache).read().splitlines()
+    assert lines and all(" | rows=" in x for x in lines)
+    s2 = Solver(p, ug=ug)
+    s2.set_state(W)
+    assert s2.autotune(cache) == chosen
+    assert open(cache).read().splitlines() == lines  # read, not re-tuned
+    dts = s.run(3, record_dt=True).cpu().numpy()
+    ref = orc.run_dts(oparams(p), W, dts, ug=ug)
+    assert rel_linf(gpu_state(s), ref) <= TOL
+    print(f"model {model}: tuned tiling {chosen}", flush=True)
+
+
 def test_fvrun_gradient_matches_oracle_and_fd():
     n = 32
     W0 = inputs.riemann_state(n, n, 0)
