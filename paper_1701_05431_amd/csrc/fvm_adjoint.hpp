@@ -75,33 +75,35 @@ struct AdjEuler {
     q.p = gm1 * fma(-0.5, fma(w[1], q.u, w[2] * q.v), w[3]);
     q.c = root(gamma * q.p * q.r);
   }
-  // out = A(W)^T d along axis D
+  // out = A(W)^T d along axis D (written with fused multiply-adds: the
+  // kernel is bound by this arithmetic)
   template <int D>
   __device__ __forceinline__ void at_d(const double* w, const Prim& q, const double* d,
                                        double* out) const {
     const double un = D == 0 ? q.u : q.v;
-    const double T = d[1] * w[1] + d[2] * w[2] + d[3] * (w[3] + q.p);
-    const double Q = d[1 + D] + d[3] * un;
+    const double T = fma(d[1], w[1], fma(d[2], w[2], d[3] * (w[3] + q.p)));
+    const double gQ = gm1 * fma(d[3], un, d[1 + D]);
     const double Tr = T * q.r;
-    const double hq2 = 0.5 * (q.u * q.u + q.v * q.v);
-    out[0] = -un * Tr + gm1 * hq2 * Q;
-    out[1] = un * d[1] - gm1 * q.u * Q;
-    out[2] = un * d[2] - gm1 * q.v * Q;
-    out[3] = un * d[3] + gm1 * Q;
+    const double hq2 = 0.5 * fma(q.u, q.u, q.v * q.v);
+    out[0] = fma(-un, Tr, hq2 * gQ);
+    out[1] = fma(-gQ, q.u, un * d[1]);
+    out[2] = fma(-gQ, q.v, un * d[2]);
+    out[3] = fma(un, d[3], gQ);
     out[1 + D] += d[0] + Tr;
   }
   // ds/dW of s = |u_n| + c
   template <int D>
   __device__ __forceinline__ void dspeed(const Prim& q, double* gs) const {
     const double un = D == 0 ? q.u : q.v;
-    const double sg = un >= 0.0 ? 1.0 : -1.0;
+    const double sr = un >= 0.0 ? q.r : -q.r;  // sign(u_n) / rho
     const double k = 0.5 * gamma * q.r * recip(q.c);
-    const double hq2 = 0.5 * (q.u * q.u + q.v * q.v);
-    gs[0] = -sg * un * q.r + k * (gm1 * hq2 - q.p * q.r);
-    gs[1] = -k * gm1 * q.u;
-    gs[2] = -k * gm1 * q.v;
-    gs[3] = k * gm1;
-    gs[1 + D] += sg * q.r;
+    const double hq2 = 0.5 * fma(q.u, q.u, q.v * q.v);
+    const double kg = k * gm1;
+    gs[0] = fma(k, fma(gm1, hq2, -q.p * q.r), -sr * un);
+    gs[1] = -kg * q.u;
+    gs[2] = -kg * q.v;
+    gs[3] = kg;
+    gs[1 + D] += sr;
   }
   template <int D>
   __device__ __forceinline__ void face(const double* wl, const Prim& pl, const double* wr,
@@ -117,14 +119,15 @@ struct AdjEuler {
     at_d<D>(wl, pl, d, al);
     at_d<D>(wr, pr, d, ar);
     if (left) dspeed<D>(pl, gs); else dspeed<D>(pr, gs);
-    const double dwd = (wr[0] - wl[0]) * d[0] + (wr[1] - wl[1]) * d[1] +
-                       (wr[2] - wl[2]) * d[2] + (wr[3] - wl[3]) * d[3];
+    const double dwd = fma(wr[0] - wl[0], d[0],
+                           fma(wr[1] - wl[1], d[1],
+                               fma(wr[2] - wl[2], d[2], (wr[3] - wl[3]) * d[3])));
     const double h = 0.5 * dwd;
     const double hl = left ? h : 0.0, hr = left ? 0.0 : h;
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
-      a[k] = 0.5 * al[k] + hs * d[k] - hl * gs[k];
-      b[k] = 0.5 * ar[k] - hs * d[k] - hr * gs[k];
+      a[k] = fma(-hl, gs[k], fma(hs, d[k], 0.5 * al[k]));
+      b[k] = fma(-hr, gs[k], fma(-hs, d[k], 0.5 * ar[k]));
     }
   }
   __device__ __forceinline__ void shift_next(const double* w, const Prim& q, double* wr,
@@ -252,7 +255,7 @@ __device__ __forceinline__ void adjoint_strip1(const M& m, const AdjointArgs& a,
         double sy = Ay[v] + Bs[v];
         if (south) sy += As[v];
         if (north) sy += By[v];
-        const double lo = L[c][v] + (mux * sx + muy * sy);
+        const double lo = L[c][v] + fma(mux, sx, muy * sy);
         if (out && j < j1) a.lam_out[v * g.plane + cell] = lo;
       }
 #pragma unroll
@@ -436,8 +439,8 @@ __device__ __forceinline__ void adjoint_strip2(const M& m, const AdjointArgs& a,
         double syb = AyB[v] + BsB[v];
         if (south) syb += AsB[v];
         if (north) syb += ByB[v];
-        OA[v] = LA[c][v] + (mux * sxa + muy * sya);
-        OB[v] = LB[c][v] + (mux * sxb + muy * syb);
+        OA[v] = LA[c][v] + fma(mux, sxa, muy * sya);
+        OB[v] = LB[c][v] + fma(mux, sxb, muy * syb);
       }
       if (j < j1) {
         const size_t row = static_cast<size_t>(j) * g.ld;
