@@ -330,6 +330,18 @@ int fvm_set_adjoint_tiling(fvm_grid* g, int rows_per_strip, int waves_per_block,
 int fvm_set_cells_per_lane(fvm_grid* g, int cells_per_lane);
 int fvm_get_cells_per_lane(const fvm_grid* g);
 
+/* Resident runs: fvm_run on a grid whose two states fit in one workgroup's
+ * LDS (2 x nVar x nx x ny <= 18432 doubles, e.g. advection up to 96 x 96,
+ * Euler up to 48 x 48; no halo rows; the spray with the lognormal closure
+ * only) executes all its adaptive steps (Sec. 2.2.1 eq. VF_scheme and
+ * eq. CFL_cond, one dt per step) in one launch of one workgroup, which keeps
+ * the state in LDS between steps, instead of one launch per step. States,
+ * dts, the dt log, the maxima and the status are bitwise those of the step
+ * launches; the other ping-pong buffer ends up holding the state before the
+ * last step, as with step launches. enable != 0 (the default) allows it,
+ * 0 forces step launches. FVM_EINVAL for a NULL grid. */
+int fvm_set_resident_runs(fvm_grid* g, int enable);
+
 /* Autotuner: picks the tiling and lane layout of the fused step by timing
  * dry-run steps of every candidate (dt = 0, which leaves the bound state bit
  * for bit unchanged) on the bound buffers and stream, re-times the six

@@ -65,6 +65,7 @@ SIGNATURES = {
     "fvm_set_halo_rows": (C.c_int, [_V, _V, _V]),
     "fvm_batch_set_schedule": (C.c_int, [_V, C.c_int, C.c_int]),
     "fvm_batch_set_layout": (C.c_int, [_V, C.c_int]),
+    "fvm_set_resident_runs": (C.c_int, [_V, C.c_int]),
     "fvm_run_ckpt": (C.c_int, [_V, C.c_int, C.c_int, C.POINTER(_V), _V]),
     "fvm_run_noalloc": (C.c_int, [_P, _V, _V, _V, C.c_int, _V, _V, _V]),
     "fvm_sync": (C.c_int, [_V]),

@@ -17,7 +17,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libfvm.so")
 SOURCES = ["fvm_api.hip", "fvm_kernels.hip", "fvm_batch.hip", "fvm_adjoint.hip",
-           "fvm_output.hip", "fvm_maxent.hip", "fvm_adjoint_spray.hip"]
+           "fvm_output.hip", "fvm_maxent.hip", "fvm_adjoint_spray.hip", "fvm_resident.hip"]
 ARCH = os.environ.get("FVM_OFFLOAD_ARCH", "gfx950")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 

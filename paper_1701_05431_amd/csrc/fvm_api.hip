@@ -22,6 +22,8 @@
 
 namespace fvm {
 void* step_kernel_ptr(int model, int bc, int wpb, int cpl, bool halo);
+hipError_t launch_resident_run(const StepArgs& a, int model, double* w_last, double* w_prev,
+                               int nsteps, hipStream_t st);
 hipError_t launch_step(const StepArgs& a, int model, hipStream_t st);
 hipError_t launch_cfl(const CflArgs& a, int model, hipStream_t st);
 hipError_t launch_clear_scratch(GridScratch* s, int n, hipStream_t st);
@@ -212,6 +214,7 @@ struct fvm_grid {
   int adj_rows = kDefaultRows, adj_wpb = kDefaultWpb;  // adjoint kernel tile shape
   int adj_cpl = 1;   // adjoint cells per lane (the tuner may pick 2 where allowed)
   int cpl_req = 0;   // requested cells per lane (0: the widest the buffers allow)
+  bool resident = true;  // small grids run whole adaptive runs in one workgroup
   int cpl = 1;       // layout in use
   double* w_a = nullptr;
   double* w_b = nullptr;
@@ -660,6 +663,16 @@ static int chunk_size(int left) {
   return 1;
 }
 
+// A run of adaptive steps on this grid can stay in one workgroup's LDS:
+// advection, Euler or the lognormal spray, no halo rows, two states within
+// kResidentDoubles.
+static bool resident_ok(const fvm_grid* g) {
+  if (!g->resident || g->halo.s || g->halo.n) return false;
+  if (g->p.model == FVM_SPRAY && g->p.closure != FVM_CLOSURE_LOGNORMAL) return false;
+  const long long need = 2LL * fvm_nvar(g->p.model) * g->p.nx * g->p.ny;
+  return need <= kResidentDoubles;
+}
+
 static int run_steps(fvm_grid* g, int kind, int nsteps, const double* dts, double* log,
                      double dt = 0.0) {
   int rc = FVM_OK;
@@ -667,6 +680,17 @@ static int run_steps(fvm_grid* g, int kind, int nsteps, const double* dts, doubl
   if ((kind == 0 || kind == 3) && !g->speeds_valid) rc = enqueue_cfl(g, nullptr);
   if (rc == FVM_OK) rc = arm_log(g, log, nsteps);
   if (rc) return rc;
+  if (kind == 0 && nsteps > 0 && resident_ok(g)) {
+    double* other = g->other(g->cur);
+    double* last = nsteps % 2 ? other : g->cur;
+    double* prev = nsteps % 2 ? g->cur : other;
+    const StepArgs a = g->step_args(g->cur, other, kDtAdaptive);
+    rc = dev_err(launch_resident_run(a, kernel_model(g->p), last, prev, nsteps, g->stream));
+    if (rc) return rc;
+    g->cur = last;
+    g->speeds_valid = true;
+    return FVM_OK;
+  }
   int done = 0;
   while (done < nsteps) {
     hipGraphExec_t exec;
@@ -1031,6 +1055,12 @@ int fvm_set_cells_per_lane(fvm_grid* g, int cpl) {
 }
 
 int fvm_get_cells_per_lane(const fvm_grid* g) { return g ? g->cpl : 0; }
+
+int fvm_set_resident_runs(fvm_grid* g, int enable) {
+  if (!g) return FVM_EINVAL;
+  g->resident = enable != 0;
+  return FVM_OK;
+}
 
 int fvm_set_adjoint_tiling(fvm_grid* g, int rows, int wpb, int cells_per_lane) {
   if (!g) return FVM_EINVAL;

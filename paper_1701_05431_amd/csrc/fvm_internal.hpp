@@ -96,6 +96,9 @@ GridGeom grid_geometry(const fvm_params& p);
 // Cells a wave strip updates: 64 with one cell per lane, 128 with two.
 __host__ __device__ constexpr int strip_width(int cpl) { return cpl == 2 ? 2 * kWave : kWave; }
 
+// LDS doubles of the resident run (two states of nVar x nx x ny): 144 KiB
+constexpr int kResidentDoubles = 18432;
+
 // Tile decomposition of one grid for a launch.
 struct Tiling {
   int rows;        // rows marched per strip

@@ -264,6 +264,11 @@ class Solver:
     def cells_per_lane(self) -> int:
         return int(lib().fvm_get_cells_per_lane(self.h))
 
+    def set_resident_runs(self, enable: bool = True) -> None:
+        """Whole adaptive runs of a grid that fits in one workgroup's LDS in
+        one launch (the default), or one launch per step."""
+        check(lib().fvm_set_resident_runs(self.h, int(bool(enable))), "fvm_set_resident_runs")
+
     def autotune(self, cache_path: str | None = None):
         """Times dry-run steps of every tiling and lane layout on this grid,
         applies the fastest (optionally cached in a text file); returns

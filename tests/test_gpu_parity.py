@@ -674,6 +674,56 @@ def _batch_case(sizes, seed=100):
     return plist, states
 
 
+@pytest.mark.parametrize("case", [(0, 0, 64, 64), (1, 0, 40, 33), (1, 1, 40, 33), (1, 2, 47, 48),
+                                  (2, 0, 30, 20), (2, 1, 31, 17), (2, 2, 25, 25), (1, 1, 1, 1)])
+def test_resident_runs_equal_step_launches(case):
+    """fvm_run on a grid that fits in one workgroup's LDS runs in one launch:
+    the states (both ping-pong buffers), the logged dts and the next dt are
+    bitwise those of one launch per step, and match the oracle."""
+    model, bc, nx, ny = case
+    ug = None
+    if model == 0:
+        p = params_from(inputs.ADVECTION_64, nx=nx, ny=ny, npart_x=1, npart_y=1)
+        W = inputs.advection_state(nx, ny, 4)
+    elif model == 1:
+        p = params_from(model=1, bc=bc, nx=nx, ny=ny, cfl=0.45)
+        W = inputs.riemann_state(nx, ny, 4)
+    else:
+        p = params_from(inputs.SPRAY_2048, nx=nx, ny=ny, npart_x=1, npart_y=1, bc=bc, cfl=0.05)
+        W, ug = inputs.spray_state(nx, ny, 4)
+    ghost = None
+    if bc == 2:
+        ghost = np.stack([W[:, 0, 0], W[:, -1, -1], W[:, 0, -1], W[:, -1, 0]])
+    out = []
+    for resident in (True, False):
+        s = Solver(p, ug=ug)
+        if ghost is not None:
+            s.set_boundary_states(ghost)
+        s.set_resident_runs(resident)
+        s.set_state(W)
+        d1 = s.run(9, record_dt=True).cpu().numpy()
+        d2 = s.run(4, record_dt=True).cpu().numpy()
+        torch.cuda.synchronize()
+        cur = s.current_storage().clone()
+        other = (s.wb if s.current_storage() is s.wa else s.wa).clone()
+        out.append((np.concatenate([d1, d2]), cur.cpu().numpy(), other.cpu().numpy(),
+                    s.cfl_dt()[0], s.sync()))
+    (da, ca, oa, na, sa), (db, cb, ob, nb, sb) = out
+    assert sa == sb
+    assert np.array_equal(da, db, equal_nan=True)
+    assert np.array_equal(ca, cb, equal_nan=True) and np.array_equal(oa, ob, equal_nan=True)
+    assert na == nb or (math.isnan(na) and math.isnan(nb))
+    if sa == 0:
+        P = oparams(p, ghost)
+        ref = orc.run_dts(P, W, da, ug=ug)
+        s = Solver(p, ug=ug)
+        if ghost is not None:
+            s.set_boundary_states(ghost)
+        s.set_state(W)
+        s.run(13)
+        assert rel_linf(gpu_state(s), ref) <= TOL
+
+
 def test_batch_equals_single_grid_runs():
     sizes = [64, 65, 97, 130, 200, 71, 64, 257]
     plist, states = _batch_case(sizes)
