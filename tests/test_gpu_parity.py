@@ -674,8 +674,11 @@ def _batch_case(sizes, seed=100):
     return plist, states
 
 
+# (model, bc, nx, ny); Euler 48 x 48 fills the LDS exactly (2 x 4 x 2304 =
+# 18432 doubles), 49 x 48 just does not (step launches either way)
 @pytest.mark.parametrize("case", [(0, 0, 64, 64), (1, 0, 40, 33), (1, 1, 40, 33), (1, 2, 47, 48),
-                                  (2, 0, 30, 20), (2, 1, 31, 17), (2, 2, 25, 25), (1, 1, 1, 1)])
+                                  (1, 1, 48, 48), (1, 1, 49, 48), (2, 0, 30, 20), (2, 1, 31, 17),
+                                  (2, 2, 25, 25), (1, 1, 1, 1)])
 def test_resident_runs_equal_step_launches(case):
     """fvm_run on a grid that fits in one workgroup's LDS runs in one launch:
     the states (both ping-pong buffers), the logged dts and the next dt are
