@@ -168,7 +168,7 @@ struct SprayAdj {
     if (K != 0.0) {
       // the closure rows: S_0 = -K n(S_eps), S_1 = -K/2 m_{-1/2}
       const double r0 = recip(m0), r1 = recip(m1);
-      const double L1 = log(m1 * r0), L2 = log(m2 * r0);
+      const double L1 = logd(m1 * r0), L2 = logd(m2 * r0);
       double s2 = 4.0 * fma(-2.0, L1, L2);
       const bool clipped = s2 < 1e-8;
       s2 = clipped ? 1e-8 : s2;

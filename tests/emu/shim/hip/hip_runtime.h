@@ -31,6 +31,7 @@ extern thread_local emu_dim3 emu_threadIdx;
 using std::exp;
 using std::fabs;
 using std::fma;
+using std::frexp;
 using std::log;
 using std::sqrt;
 inline int min(int a, int b) { return a < b ? a : b; }
