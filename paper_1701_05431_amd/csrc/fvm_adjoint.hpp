@@ -45,6 +45,7 @@ namespace fvm {
 
 struct AdjAdv {
   static constexpr int NV = 1;
+  static constexpr bool kCellA = false;  // face() returns the whole shares
   struct Prim {};
   double ax, ay;
   __device__ explicit AdjAdv(const ModelConsts& m) : ax(m.ax), ay(m.ay) {}
@@ -64,6 +65,9 @@ struct AdjAdv {
 
 struct AdjEuler {
   static constexpr int NV = 4;
+  // face() leaves out the 0.5 A(W)^T d terms; each cell adds 0.5 A(W)^T of
+  // the sum of its faces' d (at_d), once per axis
+  static constexpr bool kCellA = true;
   struct Prim { double r, u, v, p, c; };
   double gamma, gm1;
   __device__ explicit AdjEuler(const ModelConsts& m) : gamma(m.gamma), gm1(m.gm1) {}
@@ -105,6 +109,11 @@ struct AdjEuler {
     gs[3] = kg;
     gs[1 + D] += sr;
   }
+  // The Rusanov face F = (F(W_L) + F(W_R))/2 - s (W_R - W_L)/2 with
+  // d = lambda_R - lambda_L: a = (dF/dW_L)^T d, b = (dF/dW_R)^T d, each
+  // without its A(W)^T d / 2 term. Those terms are linear in d and depend on
+  // one side only, so a cell's two faces along an axis share one product
+  // A(W)^T (d_west + d_east) (at_d) instead of taking one each.
   template <int D>
   __device__ __forceinline__ void face(const double* wl, const Prim& pl, const double* wr,
                                        const Prim& pr, const double* d, double* a,
@@ -115,10 +124,16 @@ struct AdjEuler {
     const double sr = fabs(unr) + pr.c;
     const bool left = sl >= sr;
     const double hs = 0.5 * (left ? sl : sr);
-    double al[4], ar[4], gs[4];
-    at_d<D>(wl, pl, d, al);
-    at_d<D>(wr, pr, d, ar);
-    if (left) dspeed<D>(pl, gs); else dspeed<D>(pr, gs);
+    // the faster side's primitives, selected field by field (a choice
+    // between the two structs' addresses would put them in scratch memory)
+    Prim q;
+    q.r = left ? pl.r : pr.r;
+    q.u = left ? pl.u : pr.u;
+    q.v = left ? pl.v : pr.v;
+    q.p = left ? pl.p : pr.p;
+    q.c = left ? pl.c : pr.c;
+    double gs[4];
+    dspeed<D>(q, gs);
     const double dwd = fma(wr[0] - wl[0], d[0],
                            fma(wr[1] - wl[1], d[1],
                                fma(wr[2] - wl[2], d[2], (wr[3] - wl[3]) * d[3])));
@@ -126,8 +141,9 @@ struct AdjEuler {
     const double hl = left ? h : 0.0, hr = left ? 0.0 : h;
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
-      a[k] = fma(-hl, gs[k], fma(hs, d[k], 0.5 * al[k]));
-      b[k] = fma(-hr, gs[k], fma(-hs, d[k], 0.5 * ar[k]));
+      const double t = hs * d[k];
+      a[k] = fma(-hl, gs[k], t);
+      b[k] = fma(-hr, gs[k], -t);
     }
   }
   __device__ __forceinline__ void shift_next(const double* w, const Prim& q, double* wr,
@@ -197,6 +213,7 @@ __device__ __forceinline__ void adjoint_strip1(const M& m, const AdjointArgs& a,
   const double* gh = a.ghost;
   const bool west = BC == 1 && i == 0;
   const bool east = BC == 1 && i == g.nx - 1;
+  const double kw = west ? 2.0 : 1.0, ke = east ? 2.0 : 1.0;
   const double* wb = a.w + ic;
   const double* lb = a.lam_in + ic;
 
@@ -206,7 +223,7 @@ __device__ __forceinline__ void adjoint_strip1(const M& m, const AdjointArgs& a,
   // the strip are computed from clamped loads and not stored.
   constexpr int PF = FVM_ADJ_PREFETCH;
   constexpr int R = PF + 2;
-  double W[R][NV], L[R][NV], Bs[NV], As[NV];
+  double W[R][NV], L[R][NV], Bs[NV], As[NV], Ds[NV];
   Prim P[R];
   load_adj_row<NV, BC>(W[R - 1], L[R - 1], wb, lb, g, j0 - 1, ghost_col, gh, col_side);
   load_adj_row<NV, BC>(W[0], L[0], wb, lb, g, j0, ghost_col, gh, col_side);
@@ -218,7 +235,7 @@ __device__ __forceinline__ void adjoint_strip1(const M& m, const AdjointArgs& a,
   {
     double d[NV];
 #pragma unroll
-    for (int v = 0; v < NV; ++v) d[v] = L[0][v] - L[R - 1][v];
+    for (int v = 0; v < NV; ++v) d[v] = Ds[v] = L[0][v] - L[R - 1][v];
     m.template face<1>(W[R - 1], P[R - 1], W[0], P[0], d, As, Bs);  // As: the row below's share
   }
 
@@ -230,21 +247,33 @@ __device__ __forceinline__ void adjoint_strip1(const M& m, const AdjointArgs& a,
       load_adj_row<NV, BC>(W[l], L[l], wb, lb, g, min(j + 1 + PF, j1), ghost_col, gh,
                            col_side);
       m.prim(W[n], P[n]);
-      double d[NV], Ay[NV], By[NV], Wr[NV], Lr[NV], Ax[NV], Bx[NV];
+      double dy[NV], dx[NV], Ay[NV], By[NV], Wr[NV], Ax[NV], Bx[NV];
       Prim Pr;
 #pragma unroll
-      for (int v = 0; v < NV; ++v) d[v] = L[n][v] - L[c][v];
-      m.template face<1>(W[c], P[c], W[n], P[n], d, Ay, By);
+      for (int v = 0; v < NV; ++v) dy[v] = L[n][v] - L[c][v];
+      m.template face<1>(W[c], P[c], W[n], P[n], dy, Ay, By);
       m.shift_next(W[c], P[c], Wr, Pr);
 #pragma unroll
-      for (int v = 0; v < NV; ++v) {
-        Lr[v] = from_next(L[c][v]);
-        d[v] = Lr[v] - L[c][v];
-      }
-      m.template face<0>(W[c], P[c], Wr, Pr, d, Ax, Bx);
+      for (int v = 0; v < NV; ++v) dx[v] = from_next(L[c][v]) - L[c][v];
+      m.template face<0>(W[c], P[c], Wr, Pr, dx, Ax, Bx);
       const bool south = BC == 1 && j == 0;
       const bool north = BC == 1 && j == g.ny - 1;
       const size_t cell = static_cast<size_t>(j) * g.ld + ic;
+      // A(W)^T of the sums of the cell's faces' d along each axis (a
+      // transmissive ghost is a copy of the cell: its face counts twice)
+      double gx[NV], gy[NV];
+      if constexpr (M::kCellA) {
+        double Dx[NV], Dy[NV];
+        const double ks = south ? 2.0 : 1.0, kn = north ? 2.0 : 1.0;
+#pragma unroll
+        for (int v = 0; v < NV; ++v) {
+          const double dw = from_prev(dx[v]);  // the west face's d
+          Dx[v] = fma(kw, dw, ke * dx[v]);
+          Dy[v] = fma(ks, Ds[v], kn * dy[v]);
+        }
+        m.template at_d<0>(W[c], P[c], Dx, gx);
+        m.template at_d<1>(W[c], P[c], Dy, gy);
+      }
 #pragma unroll
       for (int v = 0; v < NV; ++v) {
         const double bw = from_prev(Bx[v]);
@@ -255,6 +284,10 @@ __device__ __forceinline__ void adjoint_strip1(const M& m, const AdjointArgs& a,
         double sy = Ay[v] + Bs[v];
         if (south) sy += As[v];
         if (north) sy += By[v];
+        if constexpr (M::kCellA) {
+          sx = fma(0.5, gx[v], sx);
+          sy = fma(0.5, gy[v], sy);
+        }
         const double lo = L[c][v] + fma(mux, sx, muy * sy);
         if (out && j < j1) a.lam_out[v * g.plane + cell] = lo;
       }
@@ -262,6 +295,7 @@ __device__ __forceinline__ void adjoint_strip1(const M& m, const AdjointArgs& a,
       for (int v = 0; v < NV; ++v) {
         Bs[v] = By[v];
         As[v] = 0.0;
+        Ds[v] = dy[v];
       }
     }
   }
@@ -299,6 +333,7 @@ __device__ __forceinline__ void adjoint_strip2(const M& m, const AdjointArgs& a,
   const bool west = BC == 1 && xa == 0;
   const bool east_a = BC == 1 && xa == g.nx - 1;
   const bool east_b = BC == 1 && xb == g.nx - 1;
+  const double kwa = west ? 2.0 : 1.0, kea = east_a ? 2.0 : 1.0, keb = east_b ? 2.0 : 1.0;
 
   auto prow = [&](double* wa, double* wbv, double* la, double* lbv, int r) {
     const size_t off = static_cast<size_t>(adj_row<BC>(r, g.ny)) * g.ld;
@@ -351,7 +386,7 @@ __device__ __forceinline__ void adjoint_strip2(const M& m, const AdjointArgs& a,
   constexpr int PF = FVM_ADJ_PREFETCH2;
   constexpr int R = PF + 2;
   double WA[R][NV], WB[R][NV], LA[R][NV], LB[R][NV], WH[R][NV], LH[R][NV];
-  double BsA[NV], BsB[NV], AsA[NV], AsB[NV];
+  double BsA[NV], BsB[NV], AsA[NV], AsB[NV], DsA[NV], DsB[NV];
   Prim PA[R], PB[R];
   prow(WA[R - 1], WB[R - 1], LA[R - 1], LB[R - 1], j0 - 1);
   prow(WA[0], WB[0], LA[0], LB[0], j0);
@@ -368,10 +403,10 @@ __device__ __forceinline__ void adjoint_strip2(const M& m, const AdjointArgs& a,
   {
     double d[NV];
 #pragma unroll
-    for (int v = 0; v < NV; ++v) d[v] = LA[0][v] - LA[R - 1][v];
+    for (int v = 0; v < NV; ++v) d[v] = DsA[v] = LA[0][v] - LA[R - 1][v];
     m.template face<1>(WA[R - 1], PA[R - 1], WA[0], PA[0], d, AsA, BsA);
 #pragma unroll
-    for (int v = 0; v < NV; ++v) d[v] = LB[0][v] - LB[R - 1][v];
+    for (int v = 0; v < NV; ++v) d[v] = DsB[v] = LB[0][v] - LB[R - 1][v];
     m.template face<1>(WB[R - 1], PB[R - 1], WB[0], PB[0], d, AsB, BsB);
   }
 
@@ -384,40 +419,61 @@ __device__ __forceinline__ void adjoint_strip2(const M& m, const AdjointArgs& a,
       hrow(WH[l], LH[l], min(j + 1 + PF, j1 - 1));
       m.prim(WA[n], PA[n]);
       m.prim(WB[n], PB[n]);
-      double d[NV], AyA[NV], ByA[NV], AyB[NV], ByB[NV];
+      double dyA[NV], dyB[NV], AyA[NV], ByA[NV], AyB[NV], ByB[NV];
 #pragma unroll
-      for (int v = 0; v < NV; ++v) d[v] = LA[n][v] - LA[c][v];
-      m.template face<1>(WA[c], PA[c], WA[n], PA[n], d, AyA, ByA);
+      for (int v = 0; v < NV; ++v) dyA[v] = LA[n][v] - LA[c][v];
+      m.template face<1>(WA[c], PA[c], WA[n], PA[n], dyA, AyA, ByA);
 #pragma unroll
-      for (int v = 0; v < NV; ++v) d[v] = LB[n][v] - LB[c][v];
-      m.template face<1>(WB[c], PB[c], WB[n], PB[n], d, AyB, ByB);
+      for (int v = 0; v < NV; ++v) dyB[v] = LB[n][v] - LB[c][v];
+      m.template face<1>(WB[c], PB[c], WB[n], PB[n], dyB, AyB, ByB);
       // (a | b)
-      double Aab[NV], Bab[NV];
+      double dab[NV], Aab[NV], Bab[NV];
 #pragma unroll
-      for (int v = 0; v < NV; ++v) d[v] = LB[c][v] - LA[c][v];
-      m.template face<0>(WA[c], PA[c], WB[c], PB[c], d, Aab, Bab);
+      for (int v = 0; v < NV; ++v) dab[v] = LB[c][v] - LA[c][v];
+      m.template face<0>(WA[c], PA[c], WB[c], PB[c], dab, Aab, Bab);
       // (b | next lane's a); lane 63's is replaced by its halo face below
-      double Wr[NV], Ar[NV], Br[NV];
+      double dr[NV], Wr[NV], Ar[NV], Br[NV];
       Prim Pr;
       m.shift_next(WA[c], PA[c], Wr, Pr);
 #pragma unroll
-      for (int v = 0; v < NV; ++v) d[v] = from_next(LA[c][v]) - LB[c][v];
-      m.template face<0>(WB[c], PB[c], Wr, Pr, d, Ar, Br);
+      for (int v = 0; v < NV; ++v) dr[v] = from_next(LA[c][v]) - LB[c][v];
+      m.template face<0>(WB[c], PB[c], Wr, Pr, dr, Ar, Br);
       // the strip's end faces: lane 0 (halo | a), lane 63 (b | halo)
-      double Wl[NV], Wt[NV], Ah[NV], Bh[NV];
+      double dh[NV], Wl[NV], Wt[NV], Ah[NV], Bh[NV];
       Prim Ph;
       m.prim(WH[c], Ph);
 #pragma unroll
       for (int v = 0; v < NV; ++v) {
         Wl[v] = first ? WH[c][v] : WB[c][v];
         Wt[v] = first ? WA[c][v] : WH[c][v];
-        d[v] = (first ? LA[c][v] : LH[c][v]) - (first ? LH[c][v] : LB[c][v]);
+        dh[v] = (first ? LA[c][v] : LH[c][v]) - (first ? LH[c][v] : LB[c][v]);
       }
       const Prim Pl = first ? Ph : PB[c];
       const Prim Pt = first ? PA[c] : Ph;
-      m.template face<0>(Wl, Pl, Wt, Pt, d, Ah, Bh);
+      m.template face<0>(Wl, Pl, Wt, Pt, dh, Ah, Bh);
       const bool south = BC == 1 && j == 0;
       const bool north = BC == 1 && j == g.ny - 1;
+      // A(W)^T of the sums of each cell's faces' d, formed as in the
+      // one-cell strip (a transmissive ghost's face counts twice)
+      double gxa[NV], gxb[NV], gya[NV], gyb[NV];
+      if constexpr (M::kCellA) {
+        double Dxa[NV], Dxb[NV], Dya[NV], Dyb[NV];
+        const double ks = south ? 2.0 : 1.0, kn = north ? 2.0 : 1.0;
+#pragma unroll
+        for (int v = 0; v < NV; ++v) {
+          const double dp = from_prev(dr[v]);
+          const double dwa = first ? dh[v] : dp;  // a's west face
+          const double deb = last ? dh[v] : dr[v];  // b's east face
+          Dxa[v] = fma(kwa, dwa, kea * dab[v]);
+          Dxb[v] = fma(1.0, dab[v], keb * deb);
+          Dya[v] = fma(ks, DsA[v], kn * dyA[v]);
+          Dyb[v] = fma(ks, DsB[v], kn * dyB[v]);
+        }
+        m.template at_d<0>(WA[c], PA[c], Dxa, gxa);
+        m.template at_d<0>(WB[c], PB[c], Dxb, gxb);
+        m.template at_d<1>(WA[c], PA[c], Dya, gya);
+        m.template at_d<1>(WB[c], PB[c], Dyb, gyb);
+      }
       double OA[NV], OB[NV];
 #pragma unroll
       for (int v = 0; v < NV; ++v) {
@@ -439,6 +495,12 @@ __device__ __forceinline__ void adjoint_strip2(const M& m, const AdjointArgs& a,
         double syb = AyB[v] + BsB[v];
         if (south) syb += AsB[v];
         if (north) syb += ByB[v];
+        if constexpr (M::kCellA) {
+          sxa = fma(0.5, gxa[v], sxa);
+          sxb = fma(0.5, gxb[v], sxb);
+          sya = fma(0.5, gya[v], sya);
+          syb = fma(0.5, gyb[v], syb);
+        }
         OA[v] = LA[c][v] + fma(mux, sxa, muy * sya);
         OB[v] = LB[c][v] + fma(mux, sxb, muy * syb);
       }
@@ -462,6 +524,8 @@ __device__ __forceinline__ void adjoint_strip2(const M& m, const AdjointArgs& a,
         BsB[v] = ByB[v];
         AsA[v] = 0.0;
         AsB[v] = 0.0;
+        DsA[v] = dyA[v];
+        DsB[v] = dyB[v];
       }
     }
   }

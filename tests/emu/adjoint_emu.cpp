@@ -2,14 +2,17 @@
 // host thread per lane in lockstep, to check memory bounds and to compare
 // the two lane layouts without a GPU.
 //
-// Usage: adjoint_emu model bc nx ny ld layout rows
+// Usage: adjoint_emu model bc nx ny ld layout rows [out]
 //
 // Buffers (W, lambda in, two lambda out) are exactly as large as the ABI
 // contract (nVar * ny * ld doubles) and end where their allocation ends, so
 // AddressSanitizer reports any access outside them. W is a smooth positive
 // state, lambda a pseudo-random field. Both layouts run every tile; every
 // grid cell must be written, no padding column touched, and the two
-// results must agree bit for bit.
+// results must agree bit for bit. With `out`, the file receives raw doubles:
+// W and lambda (nVar * ny * nx each, compact), the one-cell layout's
+// multipliers (the same shape), then the Dirichlet states (4 x nVar), for a
+// comparison with the oracle's adjoint step (dt 1e-3, unit square).
 #include <hip/hip_runtime.h>
 
 #include <cmath>
@@ -78,8 +81,8 @@ static double* exact_buffer(size_t n, double fill, std::vector<void*>& keep) {
 }
 
 int main(int argc, char** argv) {
-  if (argc != 8) {
-    std::fprintf(stderr, "usage: %s model bc nx ny ld layout rows\n", argv[0]);
+  if (argc != 8 && argc != 9) {
+    std::fprintf(stderr, "usage: %s model bc nx ny ld layout rows [out]\n", argv[0]);
     return 2;
   }
   const int model = atoi(argv[1]), bc = atoi(argv[2]), nx = atoi(argv[3]), ny = atoi(argv[4]);
@@ -179,6 +182,18 @@ int main(int argc, char** argv) {
           differ += std::memcmp(&o1, &o2, 8) != 0;
         }
       }
+  if (argc == 9) {
+    std::vector<double> dump;
+    for (double* b : {w, lin, out1})
+      for (int v = 0; v < nv; ++v)
+        for (int j = 0; j < ny; ++j)
+          for (int i = 0; i < nx; ++i) dump.push_back(at(b, v, j, i));
+    for (int side = 0; side < 4; ++side)
+      for (int v = 0; v < nv; ++v) dump.push_back(ghost[side * kMaxVar + v]);
+    std::FILE* f = std::fopen(argv[8], "wb");
+    if (!f || std::fwrite(dump.data(), 8, dump.size(), f) != dump.size()) return 3;
+    std::fclose(f);
+  }
   std::printf("model=%d bc=%d %dx%d ld=%d layout=%d rows=%d missing=%ld stray=%ld differ=%ld\n",
               model, bc, nx, ny, ld, layout, rows, missing, stray, differ);
   for (void* p : keep) free(p);
