@@ -38,6 +38,7 @@ namespace fvm {
 namespace sadj {
 
 constexpr double kVac = 1e-300;  // moments at or below it switch velocity and source off
+constexpr double kExpQuarterClip = 1.000000002500000003125;  // exp(1e-8 / 4)
 
 enum { kCell = 0, kCopy = 1, kGhost = 2 };
 
@@ -173,11 +174,17 @@ struct SprayAdj {
       const bool clipped = s2 < 1e-8;
       s2 = clipped ? 1e-8 : s2;
       const double mu_ = fma(2.0, L1, -0.25 * s2);
-      const double mmh = m0 * exp(fma(-0.5, mu_, 0.125 * s2));
+      // m_{-1/2} = m_0 exp(s^2/8 - mu/2) = m_0 q exp(s^2/4), q = m_0 / m_{1/2}:
+      // m_{2/2} q^3 with the fitted width, m_0 q e^{1/4e-8} with the clipped
+      // one; n(S_eps) with 1/S_eps folded into its exponential
+      const double q = m0 * r1;
+      const double mmh = clipped ? m0 * q * kExpQuarterClip : m2 * (q * q * q);
       const double z = a.m.log_s_eps - mu_;
-      const double is2 = recip(s2);
-      const double n0 =
-          m0 * recip(a.m.s_eps * root(6.283185307179586 * s2)) * exp(-(z * z) * (0.5 * is2));
+      const double rs = rroot(6.283185307179586 * s2);
+      const double is2 = 6.283185307179586 * (rs * rs);
+      const double n0 = m0 * rs * exp(fma(-(z * z), 0.5 * is2, -a.m.log_s_eps));
+      // d ln n(S_eps) = d ln m_0 - ds2 / (2 s^2) + z dmu / s^2 + z^2 ds2 / (2 s^4)
+      const double c1 = 0.5 * fma(z * z, is2, -1.0);
       const double dL1[3] = {-r0, r1, 0.0};
       const double dL2[3] = {-r0, 0.0, r2};
 #pragma unroll
@@ -185,8 +192,8 @@ struct SprayAdj {
         const double ds2 = clipped ? 0.0 : 4.0 * fma(-2.0, dL1[l], dL2[l]);
         const double dmu = fma(2.0, dL1[l], -0.25 * ds2);
         const double dm0 = l == 0 ? r0 : 0.0;
-        const double dlm = dm0 - 0.5 * dmu + 0.125 * ds2;
-        const double dln = dm0 - 0.5 * ds2 * is2 + z * dmu * is2 + 0.5 * z * z * ds2 * is2 * is2;
+        const double dlm = fma(-0.5, dmu, fma(0.125, ds2, dm0));
+        const double dln = fma(is2, fma(z, dmu, ds2 * c1), dm0);
         g[l] = fma(l1, -0.5 * K * mmh * dlm, g[l]);
         g[l] = fma(l0, -K * n0 * dln, g[l]);
       }

@@ -120,6 +120,21 @@ __device__ __forceinline__ double root(double x) {
 #endif
 }
 
+// 1/sqrt(x) for a positive normal argument: the hardware estimate refined by
+// two Newton-Raphson steps y <- y + y (1 - x y^2) / 2 (each squares the
+// relative error), or the exact quotient with FVM_FAST_DIVSQRT=0.
+__device__ __forceinline__ double rroot(double x) {
+#if FVM_FAST_DIVSQRT
+  double y = __builtin_amdgcn_rsq(x);
+  double e = fma(-x * y, y, 1.0);
+  y = fma(0.5 * y, e, y);
+  e = fma(-x * y, y, 1.0);
+  return fma(0.5 * y, e, y);
+#else
+  return 1.0 / sqrt(x);
+#endif
+}
+
 // Natural logarithm of a positive finite argument (the spray closure's
 // moment ratios), from the series log(m) = 2 atanh(s) = 2 (s + s^3/3 + s^5/5
 // + ...), s = (m - 1) / (m + 1), after splitting x = m 2^e with m in
@@ -321,10 +336,12 @@ struct Spray {
     s2 = s2 < 1e-8 ? 1e-8 : s2;
     const double mu = fma(2.0, L1, -0.25 * s2);
     const double mmh = m0 * exp(fma(-0.5, mu, 0.125 * s2));
+    // n(S_eps) = m_0 exp(-z^2 / (2 s^2)) / (S_eps sqrt(2 pi s^2)), z = ln S_eps - mu,
+    // with 1/S_eps folded into the exponential
     const double z = log_s_eps - mu;
-    const double is2 = recip(s2);
-    const double n0 =
-        m0 * recip(s_eps * root(6.283185307179586 * s2)) * exp(-(z * z) * (0.5 * is2));
+    const double rs = rroot(6.283185307179586 * s2);
+    const double is2 = 6.283185307179586 * (rs * rs);
+    const double n0 = m0 * rs * exp(fma(-(z * z), 0.5 * is2, -log_s_eps));
     const double Km0 = K * m0;
     w[0] = fma(dt, -K * n0, m0);
     w[1] = fma(dt, -(0.5 * K) * mmh, m1);
