@@ -7,6 +7,7 @@
 //   flux<D>(wl,pl,wr,pr,f)  numerical flux across a face with axis normal D
 //                     (0 = x, 1 = y); left = lower index;
 //   shift_next(w,p,wr,pr)   the right neighbour's (W, Prim) from lane+1;
+//   pick(t, a, b)     t ? a : b for two Prims, field by field;
 //   speeds(w, sx, sy) largest |eigenvalue| along x and y of a new state, NaN
 //                     when the state is non-finite or non-physical;
 //   source(w, ugx, ugy, dt) the split source step (spray only);
@@ -192,6 +193,7 @@ struct Adv {
   static constexpr int kPrefetch2 = FVM_PREFETCH2_ADV;
   static constexpr int kPrefetch1 = FVM_PREFETCH1_ADV;
   struct Prim {};
+  __device__ static Prim pick(bool, const Prim&, const Prim&) { return {}; }
   double ax, ay;
   __device__ explicit Adv(const ModelConsts& m) : ax(m.ax), ay(m.ay) {}
   __device__ __forceinline__ void prim(const double*, Prim&) const {}
@@ -226,6 +228,10 @@ struct Euler {
   static constexpr int kPrefetch2 = FVM_PREFETCH2_EULER;
   static constexpr int kPrefetch1 = FVM_PREFETCH1_EULER;
   struct Prim { double u, v, p, c; };
+  // t ? a : b, field by field (registers, not a choice of address)
+  __device__ static Prim pick(bool t, const Prim& a, const Prim& b) {
+    return {t ? a.u : b.u, t ? a.v : b.v, t ? a.p : b.p, t ? a.c : b.c};
+  }
   double gamma, gm1;
   __device__ explicit Euler(const ModelConsts& m) : gamma(m.gamma), gm1(m.gm1) {}
   __device__ __forceinline__ void prim(const double* w, Prim& q) const {
@@ -288,6 +294,9 @@ struct Spray {
   static constexpr int kPrefetch2 = FVM_PREFETCH2_SPRAY;
   static constexpr int kPrefetch1 = FVM_PREFETCH1_SPRAY;
   struct Prim { double ux, uy; };
+  __device__ static Prim pick(bool t, const Prim& a, const Prim& b) {
+    return {t ? a.ux : b.ux, t ? a.uy : b.uy};
+  }
   double K, inv_theta, s_eps, log_s_eps;
   __device__ explicit Spray(const ModelConsts& m)
       : K(m.K), inv_theta(m.inv_theta), s_eps(m.s_eps), log_s_eps(m.log_s_eps) {}

@@ -198,28 +198,24 @@ __device__ __forceinline__ void march_strip1(const M& m, const double* __restric
       hrow(H[l], min(j + 1 + PF, j1 - 1));
       m.prim(W[n], P[n]);
       m.template flux<1>(W[c], P[c], W[n], P[n], G[n]);
-      double Fr[NV], Fh[NV], Wr[NV], L[NV], Rt[NV], Fp[NV], Wo[NV];
+      double Fr[NV], Fh[NV], Wr[NV], Fp[NV], Wo[NV];
       Prim Pr, Ph;
-      m.shift_next(W[c], P[c], Wr, Pr);
-      m.template flux<0>(W[c], P[c], Wr, Pr, Fr);
       m.prim(H[c], Ph);
+      // east face: the next lane's cell, lane 63's halo cell
+      m.shift_next(W[c], P[c], Wr, Pr);
 #pragma unroll
-      for (int v = 0; v < NV; ++v) {
-        L[v] = first ? H[c][v] : W[c][v];
-        Rt[v] = first ? W[c][v] : H[c][v];
-      }
-      const Prim Pl = first ? Ph : P[c];
-      const Prim Prt = first ? P[c] : Ph;
-      m.template flux<0>(L, Pl, Rt, Prt, Fh);
-      // the cross-lane move runs with every lane active, then each lane
-      // picks its faces
+      for (int v = 0; v < NV; ++v) Wr[v] = last ? H[c][v] : Wr[v];
+      Pr = M::pick(last, Ph, Pr);
+      m.template flux<0>(W[c], P[c], Wr, Pr, Fr);
+      // west face: the previous lane's east face, lane 0's from its halo cell
+      // (the cross-lane move runs with every lane active)
+      m.template flux<0>(H[c], Ph, W[c], P[c], Fh);
 #pragma unroll
       for (int v = 0; v < NV; ++v) Fp[v] = from_prev(Fr[v]);
 #pragma unroll
       for (int v = 0; v < NV; ++v) {
         const double fw = first ? Fh[v] : Fp[v];
-        const double fe = last ? Fh[v] : Fr[v];
-        Wo[v] = W[c][v] - fma(mux, fe - fw, muy * (G[n][v] - G[c][v]));
+        Wo[v] = W[c][v] - fma(mux, Fr[v] - fw, muy * (G[n][v] - G[c][v]));
       }
       const size_t cell = static_cast<size_t>(j) * g.ld + cx;
       if constexpr (M::kSource) {
@@ -246,9 +242,10 @@ __device__ __forceinline__ void march_strip1(const M& m, const double* __restric
 // consecutive cells and every load and store is an aligned 16-byte access
 // (row pitch even, buffers 16-byte aligned). The face between a lane's two
 // cells is computed in the lane, the face to the next lane's first cell with
-// DPP moves, and the two faces at the strip's ends (left of lane 0, right of
-// lane 63) from a halo cell that each lane loads (lane 0: column xs-1, lane
-// 63: column xs+128) and passes through the same flux code. EDGE strips
+// DPP moves, and the two faces at the strip's ends from a halo cell that
+// each lane loads (lane 0: column xs-1, lane 63: column xs+128): lane 63 takes
+// it as the right cell of its (b | next) face, and every lane evaluates
+// (halo | a), which only lane 0 keeps as its west face. EDGE strips
 // reach past the grid's last column: there every cell is addressed through
 // the boundary map (past-the-end cells hold the ghost values that their left
 // neighbour needs) and stores are masked per cell.
@@ -349,32 +346,28 @@ __device__ __forceinline__ void march_strip2(const M& m, const double* __restric
       m.prim(B[n], PB[n]);
       m.template flux<1>(A[c], PA[c], A[n], PA[n], GA[n]);
       m.template flux<1>(B[c], PB[c], B[n], PB[n], GB[n]);
-      double Fab[NV], Fr[NV], Fh[NV], Wr[NV], L[NV], Rt[NV], Oa[NV], Ob[NV];
+      double Fab[NV], Fr[NV], Fh[NV], Wr[NV], Oa[NV], Ob[NV];
       Prim Pr, Ph;
       m.template flux<0>(A[c], PA[c], B[c], PB[c], Fab);
-      m.shift_next(A[c], PA[c], Wr, Pr);
-      m.template flux<0>(B[c], PB[c], Wr, Pr, Fr);
-      // the strip's end faces: lane 0 (halo | a), lane 63 (b | halo)
       m.prim(H[c], Ph);
+      // (b | next lane's a); lane 63's right cell is its halo cell
+      m.shift_next(A[c], PA[c], Wr, Pr);
 #pragma unroll
-      for (int v = 0; v < NV; ++v) {
-        L[v] = first ? H[c][v] : B[c][v];
-        Rt[v] = first ? A[c][v] : H[c][v];
-      }
-      const Prim Pl = first ? Ph : PB[c];
-      const Prim Prt = first ? PA[c] : Ph;
-      m.template flux<0>(L, Pl, Rt, Prt, Fh);
-      // the cross-lane move runs with every lane active (a DPP read from a
-      // lane that is switched off yields 0), then each lane picks its face
+      for (int v = 0; v < NV; ++v) Wr[v] = last ? H[c][v] : Wr[v];
+      Pr = M::pick(last, Ph, Pr);
+      m.template flux<0>(B[c], PB[c], Wr, Pr, Fr);
+      // a's west face: the previous lane's (b | a), lane 0's (halo | a); the
+      // cross-lane move runs with every lane active (a DPP read from a lane
+      // that is switched off yields 0)
+      m.template flux<0>(H[c], Ph, A[c], PA[c], Fh);
       double Fp[NV];
 #pragma unroll
       for (int v = 0; v < NV; ++v) Fp[v] = from_prev(Fr[v]);
 #pragma unroll
       for (int v = 0; v < NV; ++v) {
         const double fw = first ? Fh[v] : Fp[v];
-        const double fe = last ? Fh[v] : Fr[v];
         Oa[v] = A[c][v] - fma(mux, Fab[v] - fw, muy * (GA[n][v] - GA[c][v]));
-        Ob[v] = B[c][v] - fma(mux, fe - Fab[v], muy * (GB[n][v] - GB[c][v]));
+        Ob[v] = B[c][v] - fma(mux, Fr[v] - Fab[v], muy * (GB[n][v] - GB[c][v]));
       }
       const size_t row = static_cast<size_t>(j) * g.ld;
       if constexpr (M::kSource) {
