@@ -52,8 +52,13 @@ int emu_dpp(int x, int ctrl);
 unsigned long long emu_shfl_xor(unsigned long long x, int o);
 #define __builtin_amdgcn_update_dpp(old, x, ctrl, rm, bm, bc) emu_dpp((x), (ctrl))
 #define __builtin_amdgcn_readfirstlane(x) (x)
-#define __builtin_amdgcn_rcp(x) (1.0 / (x))
-#define __builtin_amdgcn_rsq(x) (1.0 / std::sqrt(x))
+// FVM_EMU_EST_ERR: a relative error given to both estimates, to exercise
+// the refinement steps that follow them in the device code
+#ifndef FVM_EMU_EST_ERR
+#define FVM_EMU_EST_ERR 0.0
+#endif
+#define __builtin_amdgcn_rcp(x) ((1.0 / (x)) * (1.0 + FVM_EMU_EST_ERR))
+#define __builtin_amdgcn_rsq(x) ((1.0 / std::sqrt(x)) * (1.0 + FVM_EMU_EST_ERR))
 template <class T>
 inline T __shfl_xor(T x, int o, int) {
   return (T)emu_shfl_xor((unsigned long long)x, o);
