@@ -1158,6 +1158,41 @@ def test_spray_adjoint_degenerate_cases(bc):
         assert rel_linf(got[:, :, :nx].cpu().numpy(), ref) <= TOL
 
 
+@pytest.mark.parametrize("bc", [0, 1, 2])
+def test_spray_clipped_lognormal_width(bc):
+    """Cells whose moments leave no room for a lognormal width
+    (m_{1/2}^2 >= m_0 m_{2/2}: a monodisperse block, and a column beyond it)
+    take the clipped width s^2 = 1e-8 in the closure, where m_{-1/2} and the
+    closure Jacobian follow their clipped forms: one forward step with a
+    fixed dt and one adjoint step against the oracle, on a state that mixes
+    such cells with fitted ones."""
+    nx, ny = 70, 21
+    print(f"spray clipped width bc={bc}", flush=True)
+    W, ug = _spray_adjoint_case(nx, ny, 23)
+    n, S = W[0, 3:9, 10:30].copy(), 0.2
+    for k in range(4):  # m_{k/2} = n S^{k/2}: zero width
+        W[k, 3:9, 10:30] = n * S ** (0.5 * k)
+    W[1, :, 50] = 1.05 * np.sqrt(W[0, :, 50] * W[2, :, 50])
+    gh = _spray_ghosts() if bc == _lib.FVM_DIRICHLET else None
+    p = params_from(model=2, bc=bc, nx=nx, ny=ny, K=0.7, cfl=0.9)
+    P = oparams(p, gh)
+    _, _, dt = orc.cfl(P, W)
+    s = Solver(p, ug=ug)
+    if gh is not None:
+        s.set_boundary_states(gh)
+    s.set_state(W)
+    s.step(dt)
+    assert s.sync() == 0
+    rc, ref = orc.step_fixed(P, W, dt, ug=ug)
+    assert rc == 0
+    assert rel_linf(gpu_state(s), ref) <= TOL
+    lam = np.random.default_rng(29).standard_normal(W.shape)
+    got = s.adjoint_step(W, dt, lam)
+    torch.cuda.synchronize()
+    ref = orc.adjoint_step(P, W, dt, lam, ug)
+    assert rel_linf(got[:, :, :nx].cpu().numpy(), ref) <= TOL
+
+
 def test_spray_adjoint_2048_full_size_step():
     """One spray adjoint step on the 2048^2 spray workload's state (lognormal
     closure, K = 1, theta = 0.1) in the benchmark's storage layout against
