@@ -33,7 +33,12 @@ __global__ __launch_bounds__(WPB * kWave) void adjoint_kernel(AdjointArgs a) {
   } else {
     const int xs = (tx * WPB + wave) * kOutPerWave;
     if (xs >= a.g.nx) return;
-    adjoint_strip1<M, BC>(m, a, xs, j0, j1, mux, muy);
+    // tiles of odd rows march down (vertical neighbours meet at their
+    // shared rows)
+    if (ty & 1)
+      adjoint_strip1<M, BC, true>(m, a, xs, j0, j1, mux, muy);
+    else
+      adjoint_strip1<M, BC, false>(m, a, xs, j0, j1, mux, muy);
   }
 }
 

@@ -197,8 +197,14 @@ __device__ __forceinline__ void load_adj_row(double* w, double* l, const double*
 }
 
 // One strip of 62 cells, one per lane (lanes 0 and 63 only supply the halo
-// cells): the layout for odd pitches and unaligned buffers.
-template <class M, int BC>
+// cells): the layout for odd pitches and unaligned buffers. DOWN marches the
+// rows from the top of the tile down instead of up: alternate tiles of a
+// column run in opposite directions, so two vertically adjacent tiles reach
+// the rows they share (one's last row, the other's halo row) at about the
+// same time and the second read is served from L2. Every face is evaluated
+// with the same arguments and every cell sums its shares in the same order
+// in both directions, so the multipliers do not depend on it.
+template <class M, int BC, bool DOWN = false>
 __device__ __forceinline__ void adjoint_strip1(const M& m, const AdjointArgs& a, int xs, int j0,
                                                int j1, double mux, double muy) {
   constexpr int NV = M::NV;
@@ -217,41 +223,61 @@ __device__ __forceinline__ void adjoint_strip1(const M& m, const AdjointArgs& a,
   const double* wb = a.w + ic;
   const double* lb = a.lam_in + ic;
 
-  // Register ring of R = PF + 2 rows of (W, lambda): row j in slot c, row j+1
-  // in slot n, rows up to j+1+PF loading into the slot row j-1 vacated. The
-  // row loop is unrolled R times so every slot index is static; rows past
-  // the strip are computed from clamped loads and not stored.
+  // Register ring of R = PF + 2 rows of (W, lambda): row j in slot c, the
+  // next row in the march (j + S) in slot n, rows up to PF further loading
+  // into the slot the row behind vacated. The row loop is unrolled R times
+  // so every slot index is static; rows past the tile are computed from
+  // loads clamped to its halo row and not stored.
   constexpr int PF = FVM_ADJ_PREFETCH;
   constexpr int R = PF + 2;
-  double W[R][NV], L[R][NV], Bs[NV], As[NV], Ds[NV];
+  constexpr int S = DOWN ? -1 : 1;
+  const int jf = DOWN ? j1 - 1 : j0;   // the first row of the march
+  const int jh = DOWN ? j0 - 1 : j1;   // the halo row past its last
+  auto ahead = [&](int r) { return DOWN ? max(r, jh) : min(r, jh); };
+  auto row = [&](double* w, double* l, int r) {
+    load_adj_row<NV, BC>(w, l, wb, lb, g, r, ghost_col, gh, col_side);
+  };
+  // the face behind the current row (between it and the previous one in
+  // the march): lower row's share Fl, upper row's share Fu, d = lam_upper -
+  // lam_lower
+  double W[R][NV], L[R][NV], Fl[NV], Fu[NV], Fd[NV];
   Prim P[R];
-  load_adj_row<NV, BC>(W[R - 1], L[R - 1], wb, lb, g, j0 - 1, ghost_col, gh, col_side);
-  load_adj_row<NV, BC>(W[0], L[0], wb, lb, g, j0, ghost_col, gh, col_side);
+  row(W[R - 1], L[R - 1], jf - S);
+  row(W[0], L[0], jf);
 #pragma unroll
-  for (int p = 1; p <= PF; ++p)
-    load_adj_row<NV, BC>(W[p], L[p], wb, lb, g, min(j0 + p, j1), ghost_col, gh, col_side);
+  for (int p = 1; p <= PF; ++p) row(W[p], L[p], ahead(jf + S * p));
   m.prim(W[R - 1], P[R - 1]);
   m.prim(W[0], P[0]);
   {
-    double d[NV];
+    const int lo = DOWN ? 0 : R - 1, up = DOWN ? R - 1 : 0;
 #pragma unroll
-    for (int v = 0; v < NV; ++v) d[v] = Ds[v] = L[0][v] - L[R - 1][v];
-    m.template face<1>(W[R - 1], P[R - 1], W[0], P[0], d, As, Bs);  // As: the row below's share
+    for (int v = 0; v < NV; ++v) Fd[v] = L[up][v] - L[lo][v];
+    m.template face<1>(W[lo], P[lo], W[up], P[up], Fd, Fl, Fu);
   }
 
-  for (int jb = j0; jb < j1; jb += R) {
+  for (int jb = jf; DOWN ? jb > jh : jb < jh; jb += S * R) {
 #pragma unroll
     for (int u = 0; u < R; ++u) {
-      const int j = jb + u;
+      const int j = jb + S * u;
       const int c = u, n = (u + 1) % R, l = (u + R - 1) % R;
-      load_adj_row<NV, BC>(W[l], L[l], wb, lb, g, min(j + 1 + PF, j1), ghost_col, gh,
-                           col_side);
+      row(W[l], L[l], ahead(j + S * (1 + PF)));
       m.prim(W[n], P[n]);
-      double dy[NV], dx[NV], Ay[NV], By[NV], Wr[NV], Ax[NV], Bx[NV];
-      Prim Pr;
+      // the face ahead: north of row j going up, south of it going down
+      double Gd[NV], Gl[NV], Gu[NV];
+      const int glo = DOWN ? n : c, gup = DOWN ? c : n;
 #pragma unroll
-      for (int v = 0; v < NV; ++v) dy[v] = L[n][v] - L[c][v];
-      m.template face<1>(W[c], P[c], W[n], P[n], dy, Ay, By);
+      for (int v = 0; v < NV; ++v) Gd[v] = L[gup][v] - L[glo][v];
+      m.template face<1>(W[glo], P[glo], W[gup], P[gup], Gd, Gl, Gu);
+      // row j's north face (its lower share An, the upper Bn, dn) and south
+      // face (As, Bs, ds)
+      const double* An = DOWN ? Fl : Gl;
+      const double* Bn = DOWN ? Fu : Gu;
+      const double* dn = DOWN ? Fd : Gd;
+      const double* As = DOWN ? Gl : Fl;
+      const double* Bs = DOWN ? Gu : Fu;
+      const double* ds = DOWN ? Gd : Fd;
+      double dx[NV], Wr[NV], Ax[NV], Bx[NV];
+      Prim Pr;
       m.shift_next(W[c], P[c], Wr, Pr);
 #pragma unroll
       for (int v = 0; v < NV; ++v) dx[v] = from_next(L[c][v]) - L[c][v];
@@ -269,7 +295,7 @@ __device__ __forceinline__ void adjoint_strip1(const M& m, const AdjointArgs& a,
         for (int v = 0; v < NV; ++v) {
           const double dw = from_prev(dx[v]);  // the west face's d
           Dx[v] = fma(kw, dw, ke * dx[v]);
-          Dy[v] = fma(ks, Ds[v], kn * dy[v]);
+          Dy[v] = fma(ks, ds[v], kn * dn[v]);
         }
         m.template at_d<0>(W[c], P[c], Dx, gx);
         m.template at_d<1>(W[c], P[c], Dy, gy);
@@ -281,21 +307,24 @@ __device__ __forceinline__ void adjoint_strip1(const M& m, const AdjointArgs& a,
         double sx = Ax[v] + bw;
         if (west) sx += aw;
         if (east) sx += Bx[v];
-        double sy = Ay[v] + Bs[v];
+        double sy = An[v] + Bs[v];
         if (south) sy += As[v];
-        if (north) sy += By[v];
+        if (north) sy += Bn[v];
         if constexpr (M::kCellA) {
           sx = fma(0.5, gx[v], sx);
           sy = fma(0.5, gy[v], sy);
         }
         const double lo = L[c][v] + fma(mux, sx, muy * sy);
-        if (out && j < j1) a.lam_out[v * g.plane + cell] = lo;
+        if (out && j >= j0 && j < j1) a.lam_out[v * g.plane + cell] = lo;
       }
+      // the face ahead is the next row's face behind; of its shares that
+      // row needs only its own (its other face's ghost share applies at the
+      // grid's first row alone)
 #pragma unroll
       for (int v = 0; v < NV; ++v) {
-        Bs[v] = By[v];
-        As[v] = 0.0;
-        Ds[v] = dy[v];
+        Fl[v] = DOWN ? Gl[v] : 0.0;
+        Fu[v] = DOWN ? 0.0 : Gu[v];
+        Fd[v] = Gd[v];
       }
     }
   }

@@ -52,7 +52,7 @@ using namespace fvm;
 
 template <class M, int BC>
 static void run_strip(const M& m, const AdjointArgs& a, int cpl, int xs, int j0, int j1,
-                      double mux, double muy) {
+                      double mux, double muy, bool down) {
   std::barrier<> bar(64);
   g_bar = &bar;
   std::vector<std::thread> lanes;
@@ -61,8 +61,10 @@ static void run_strip(const M& m, const AdjointArgs& a, int cpl, int xs, int j0,
       t_lane = lane;
       emu_threadIdx = {static_cast<unsigned>(lane), 0, 0};
       if (xs >= a.g.nx) return;  // uniform: the whole wave leaves
-      if (cpl == 1)
-        adjoint_strip1<M, BC>(m, a, xs, j0, j1, mux, muy);
+      if (cpl == 1 && down)
+        adjoint_strip1<M, BC, true>(m, a, xs, j0, j1, mux, muy);
+      else if (cpl == 1)
+        adjoint_strip1<M, BC, false>(m, a, xs, j0, j1, mux, muy);
       else if (xs + 2 * kWave <= a.g.nx)
         adjoint_strip2<M, BC, false>(m, a, xs, j0, j1, mux, muy);
       else
@@ -160,10 +162,12 @@ int main(int argc, char** argv) {
         const int xs = sx * sw, j0 = ty * rows, j1 = std::min(j0 + rows, ny);
         auto go = [&](auto bct) {
           constexpr int B = decltype(bct)::value;
+          // the one-cell strips of odd tile rows march down, as in the kernel
+          const bool down = (ty & 1) != 0;
           if (model == 0)
-            run_strip<AdjAdv, B>(AdjAdv(mc), a, cpl, xs, j0, j1, mux, muy);
+            run_strip<AdjAdv, B>(AdjAdv(mc), a, cpl, xs, j0, j1, mux, muy, down);
           else
-            run_strip<AdjEuler, B>(AdjEuler(mc), a, cpl, xs, j0, j1, mux, muy);
+            run_strip<AdjEuler, B>(AdjEuler(mc), a, cpl, xs, j0, j1, mux, muy, down);
         };
         if (bc == 0) go(std::integral_constant<int, 0>());
         else if (bc == 1) go(std::integral_constant<int, 1>());
