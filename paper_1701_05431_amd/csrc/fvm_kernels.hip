@@ -37,7 +37,8 @@
 namespace fvm {
 
 // One wave strip of the CPL layout (1: 64 cells per wave, any pitch; 2: 128
-// cells per wave, 16-byte aligned accesses).
+// cells per wave, 16-byte aligned accesses; down: march the rows from the
+// top of the tile, CPL 2 only).
 // (gh: the Dirichlet ghost states, BC == kDirichlet only; HALO: rows -1 and
 // ny may come from the halo buffers)
 template <class M, int BC, int CPL, bool HALO>
@@ -46,7 +47,7 @@ __device__ __forceinline__ void strip(const M& m, const double* __restrict__ win
                                       const GridGeom& g, int xs, int j0, int j1, double mux,
                                       double muy, double dt, unsigned long long& bx,
                                       unsigned long long& by, const double* gh,
-                                      const Halo& halo) {
+                                      const Halo& halo, bool down) {
   if (xs >= g.nx) return;
   if (CPL == 1) {
     if (xs + kWave <= g.nx)
@@ -56,11 +57,19 @@ __device__ __forceinline__ void strip(const M& m, const double* __restrict__ win
       march_strip1<M, BC, true, HALO>(m, win, wout, ug, g, xs, j0, j1, mux, muy, dt, bx, by, gh,
                                       halo);
   } else if (xs + 2 * kWave <= g.nx) {
-    march_strip2<M, BC, false, M::kPrefetch2, HALO>(m, win, wout, ug, g, xs, j0, j1, mux, muy,
-                                                    dt, bx, by, gh, halo);
+    if (down)
+      march_strip2<M, BC, false, M::kPrefetch2, HALO, true>(m, win, wout, ug, g, xs, j0, j1,
+                                                            mux, muy, dt, bx, by, gh, halo);
+    else
+      march_strip2<M, BC, false, M::kPrefetch2, HALO>(m, win, wout, ug, g, xs, j0, j1, mux,
+                                                      muy, dt, bx, by, gh, halo);
   } else {
-    march_strip2<M, BC, true, M::kPrefetch2, HALO>(m, win, wout, ug, g, xs, j0, j1, mux, muy,
-                                                   dt, bx, by, gh, halo);
+    if (down)
+      march_strip2<M, BC, true, M::kPrefetch2, HALO, true>(m, win, wout, ug, g, xs, j0, j1,
+                                                           mux, muy, dt, bx, by, gh, halo);
+    else
+      march_strip2<M, BC, true, M::kPrefetch2, HALO>(m, win, wout, ug, g, xs, j0, j1, mux, muy,
+                                                     dt, bx, by, gh, halo);
   }
 }
 
@@ -78,8 +87,10 @@ __global__ FVM_STEP_BOUNDS(WPB) void step_kernel(StepArgs a) {
   const int j0 = ty * a.t.rows;
   const int j1 = min(j0 + a.t.rows, a.g.ny);
   unsigned long long bx = 0, by = 0;
+  // two-cells-per-lane strips of odd tile rows march down: vertically
+  // adjacent tiles then read the rows they share at about the same time
   strip<M, BC, CPL, HALO>(m, a.win, a.wout, a.ug, a.g, xs, j0, j1, mux, muy, dt_eff, bx, by,
-                          a.ghost, a.halo);
+                          a.ghost, a.halo, (ty & 1) != 0);
   if constexpr (M::kCommit) {
     if (block_commit<WPB>(bx, by, a.scr, gridDim.x) && threadIdx.x == 0) {
       if (cfl_fail) atomicOr(&a.scr->status, kStatusCfl);

@@ -288,7 +288,8 @@ __device__ __forceinline__ void load_pair(double* a, double* b, const double* __
   }
 }
 
-template <class M, int BC, bool EDGE, int PF = M::kPrefetch2, bool HALO = false>
+template <class M, int BC, bool EDGE, int PF = M::kPrefetch2, bool HALO = false,
+          bool DOWN = false>
 __device__ __forceinline__ void march_strip2(const M& m, const double* __restrict__ win,
                                              double* __restrict__ wout,
                                              const double* __restrict__ ug, const GridGeom& g,
@@ -317,35 +318,53 @@ __device__ __forceinline__ void march_strip2(const M& m, const double* __restric
     if constexpr (BC == kDirichlet) ghost_if<NV>(w, gh, h_side, h_out);
   };
 
+  // Rows march up from j0, or with DOWN from j1 - 1 down (alternate tiles
+  // of a column go opposite ways, so vertical neighbours read the rows they
+  // share at about the same time and the second read hits L2); the y-face
+  // between the current row and the next one in the march is computed with
+  // the lower row first either way, so results do not depend on it.
   constexpr int R = PF + 2;  // PF rows of loads in flight
+  constexpr int S = DOWN ? -1 : 1;
+  const int jf = DOWN ? j1 - 1 : j0;  // the first row of the march
+  const int jh = DOWN ? j0 - 1 : j1;  // the halo row past its last
+  auto ahead = [&](int r) { return DOWN ? max(r, jh) : min(r, jh); };
+  auto ahead_h = [&](int r) { return DOWN ? max(r, j0) : min(r, j1 - 1); };
+  // GA[k], GB[k]: the y-face between the rows in slots k and k - 1 of the
+  // march (the previous row's)
   double A[R][NV], B[R][NV], H[R][NV], GA[R][NV], GB[R][NV];
   Prim PA[R], PB[R];
-  prow(A[R - 1], B[R - 1], j0 - 1);
-  prow(A[0], B[0], j0);
-  hrow(H[0], j0);
+  prow(A[R - 1], B[R - 1], jf - S);
+  prow(A[0], B[0], jf);
+  hrow(H[0], jf);
 #pragma unroll
   for (int p = 1; p <= PF; ++p) {
-    prow(A[p], B[p], min(j0 + p, j1));
-    hrow(H[p], min(j0 + p, j1 - 1));
+    prow(A[p], B[p], ahead(jf + S * p));
+    hrow(H[p], ahead_h(jf + S * p));
   }
   m.prim(A[R - 1], PA[R - 1]);
   m.prim(B[R - 1], PB[R - 1]);
   m.prim(A[0], PA[0]);
   m.prim(B[0], PB[0]);
-  m.template flux<1>(A[R - 1], PA[R - 1], A[0], PA[0], GA[0]);
-  m.template flux<1>(B[R - 1], PB[R - 1], B[0], PB[0], GB[0]);
+  {
+    const int lo = DOWN ? 0 : R - 1, up = DOWN ? R - 1 : 0;
+    m.template flux<1>(A[lo], PA[lo], A[up], PA[up], GA[0]);
+    m.template flux<1>(B[lo], PB[lo], B[up], PB[up], GB[0]);
+  }
 
-  for (int jb = j0; jb < j1; jb += R) {
+  for (int jb = jf; DOWN ? jb > jh : jb < jh; jb += S * R) {
 #pragma unroll
     for (int u = 0; u < R; ++u) {
-      const int j = jb + u;
+      const int j = jb + S * u;
       const int c = u, n = (u + 1) % R, l = (u + R - 1) % R;
-      prow(A[l], B[l], min(j + 1 + PF, j1));
-      hrow(H[(u + PF + 1) % R], min(j + 1 + PF, j1 - 1));
+      prow(A[l], B[l], ahead(j + S * (1 + PF)));
+      hrow(H[(u + PF + 1) % R], ahead_h(j + S * (1 + PF)));
       m.prim(A[n], PA[n]);
       m.prim(B[n], PB[n]);
-      m.template flux<1>(A[c], PA[c], A[n], PA[n], GA[n]);
-      m.template flux<1>(B[c], PB[c], B[n], PB[n], GB[n]);
+      const int glo = DOWN ? n : c, gup = DOWN ? c : n;
+      m.template flux<1>(A[glo], PA[glo], A[gup], PA[gup], GA[n]);
+      m.template flux<1>(B[glo], PB[glo], B[gup], PB[gup], GB[n]);
+      // row j's north and south faces
+      const int kn = DOWN ? c : n, ks = DOWN ? n : c;
       double Fab[NV], Fr[NV], Fh[NV], Wr[NV], Oa[NV], Ob[NV];
       Prim Pr, Ph;
       m.template flux<0>(A[c], PA[c], B[c], PB[c], Fab);
@@ -366,8 +385,8 @@ __device__ __forceinline__ void march_strip2(const M& m, const double* __restric
 #pragma unroll
       for (int v = 0; v < NV; ++v) {
         const double fw = first ? Fh[v] : Fp[v];
-        Oa[v] = A[c][v] - fma(mux, Fab[v] - fw, muy * (GA[n][v] - GA[c][v]));
-        Ob[v] = B[c][v] - fma(mux, Fr[v] - Fab[v], muy * (GB[n][v] - GB[c][v]));
+        Oa[v] = A[c][v] - fma(mux, Fab[v] - fw, muy * (GA[kn][v] - GA[ks][v]));
+        Ob[v] = B[c][v] - fma(mux, Fr[v] - Fab[v], muy * (GB[kn][v] - GB[ks][v]));
       }
       const size_t row = static_cast<size_t>(j) * g.ld;
       if constexpr (M::kSource) {
@@ -380,7 +399,7 @@ __device__ __forceinline__ void march_strip2(const M& m, const double* __restric
         m.source(Oa, ua[0], ua[1], dt);
         m.source(Ob, ub[0], ub[1], dt);
       }
-      if (j < j1) {
+      if (j >= j0 && j < j1) {
         if (EDGE) {
 #pragma unroll
           for (int v = 0; v < NV; ++v) {

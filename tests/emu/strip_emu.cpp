@@ -54,7 +54,7 @@ using namespace fvm;
 template <class M, int BC>
 static void run_strip(const M& m, const double* win, double* wout, const double* ug,
                       const GridGeom& g, int cpl, int xs, int j0, int j1, double mux, double muy,
-                      double dt, const double* gh) {
+                      double dt, const double* gh, bool down) {
   std::barrier<> bar(64);
   g_bar = &bar;
   std::vector<std::thread> lanes;
@@ -70,8 +70,15 @@ static void run_strip(const M& m, const double* win, double* wout, const double*
         else
           march_strip1<M, BC, true>(m, win, wout, ug, g, xs, j0, j1, mux, muy, dt, bx, by, gh);
       } else {
-        if (xs + 2 * kWave <= g.nx)
+        constexpr int PF = M::kPrefetch2;
+        if (xs + 2 * kWave <= g.nx && down)
+          march_strip2<M, BC, false, PF, false, true>(m, win, wout, ug, g, xs, j0, j1, mux, muy,
+                                                      dt, bx, by, gh);
+        else if (xs + 2 * kWave <= g.nx)
           march_strip2<M, BC, false>(m, win, wout, ug, g, xs, j0, j1, mux, muy, dt, bx, by, gh);
+        else if (down)
+          march_strip2<M, BC, true, PF, false, true>(m, win, wout, ug, g, xs, j0, j1, mux, muy,
+                                                     dt, bx, by, gh);
         else
           march_strip2<M, BC, true>(m, win, wout, ug, g, xs, j0, j1, mux, muy, dt, bx, by, gh);
       }
@@ -177,17 +184,21 @@ int main(int argc, char** argv) {
     for (int tx = 0; tx < tiles_x; ++tx)
       for (int w = 0; w < wpb; ++w) {
         const int xs = (tx * wpb + w) * sw, j0 = ty * rows, j1 = std::min(j0 + rows, ny);
+        // two-cells-per-lane strips of odd tile rows march down, as in the kernel
+        const bool down = (ty & 1) != 0;
         auto go = [&](auto bct) {
           constexpr int B = decltype(bct)::value;
           if (model == 0)
-            run_strip<Adv, B>(Adv(mc), win, wout, ug, g, cpl, xs, j0, j1, mux, muy, dt, gh);
+            run_strip<Adv, B>(Adv(mc), win, wout, ug, g, cpl, xs, j0, j1, mux, muy, dt, gh, down);
           else if (model == 1)
-            run_strip<Euler, B>(Euler(mc), win, wout, ug, g, cpl, xs, j0, j1, mux, muy, dt, gh);
+            run_strip<Euler, B>(Euler(mc), win, wout, ug, g, cpl, xs, j0, j1, mux, muy, dt, gh,
+                                down);
           else if (model == 2)
-            run_strip<Spray, B>(Spray(mc), win, wout, ug, g, cpl, xs, j0, j1, mux, muy, dt, gh);
+            run_strip<Spray, B>(Spray(mc), win, wout, ug, g, cpl, xs, j0, j1, mux, muy, dt, gh,
+                                down);
           else
             run_strip<SprayTransport, B>(SprayTransport(mc), win, wout, ug, g, cpl, xs, j0, j1,
-                                         mux, muy, dt, gh);
+                                         mux, muy, dt, gh, down);
         };
         if (bc == 0) go(std::integral_constant<int, 0>());
         else if (bc == 1) go(std::integral_constant<int, 1>());
